@@ -1,0 +1,32 @@
+"""Pin of the storage-size helper against the figures the paper prints.
+
+Sec. III-I gives S_enc = 48 N + H (eq:size) and CR = S_src / S_enc (eq:cr);
+Sec. V-A/V-B print the resulting ratios and sizes (fixture tests/golden/
+compression_ratios.json, with its citation).  H is not printed: the three
+2,000-primitive ratios put it near 7 kB.
+"""
+import json
+import os
+
+from oracle import field as F
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "compression_ratios.json")
+
+
+def test_printed_ratios_reproduce_with_one_header():
+    g = json.load(open(GOLD))
+    H = 7000
+    assert F.encoded_bytes(2000, H) == g["encoded_bytes_2000"]
+    assert F.encoded_bytes(1_400_000, 0) == g["encoded_bytes_1400000"]
+    for case in g["cases"]:
+        src = g["source_bytes"][case["dataset"]]
+        cr = F.compression_ratio(src, 1, case["n"], H)
+        # printed ratios are rounded (to the unit at 1.4M; H itself is ~7.0 kB +- 40 B)
+        tol = 0.5 if case["cr"] < 100 else 0.0005 * case["cr"]
+        assert abs(cr - case["cr"]) <= tol, (case, cr)
+
+
+def test_no_compression_thresholds():
+    g = json.load(open(GOLD))
+    for name, n in g["no_compression_threshold"].items():
+        assert abs(g["source_bytes"][name] / 48 - n) / n < 0.002
