@@ -1,0 +1,174 @@
+/*
+ * gve.h -- C ABI of the fixed-budget Gaussian volume encoder (libgve.so).
+ *
+ * A scalar field on a regular voxel grid is represented by a fixed set of N
+ * weighted anisotropic 3-D Gaussians (paper Sec. III-A: the budget N is set
+ * before training and never changes).  Primitive i has centre mu_i, a raw
+ * quaternion q_i = (w, x, y, z) (scalar first, Hamilton convention, normalised
+ * inside every call), log-scales l_i and a scalar weight c_i, and covariance
+ * Sigma_i = R(q_i) S_i S_i^T R(q_i)^T with S_i = diag(exp(l_i)).  The encoded
+ * field is the truncated weighted sum (Sec. III-C, eq:field, read for an
+ * unnormalised sum with one weight per primitive):
+ *
+ *     Vhat(p) = sum_i c_i exp(-m_i(p)^2 / 2) [m_i(p)^2 < k^2],
+ *     m_i(p)^2 = (p - mu_i)^T Sigma_i^{-1} (p - mu_i),
+ *
+ * with the hard k-sigma cut of Sec. III-C ("squared Mahalanobis distance below"
+ * k^2).  Coordinates are voxel-index coordinates (Sec. III-B): voxel (i, j, k)
+ * of a grid is the point (x0 + i, y0 + j, z0 + k); field buffers are float32,
+ * x fastest: index = i + nx * (j + ny * k).
+ *
+ * Conventions for every call:
+ *  - Return GVE_OK or an error status; no C++ exception crosses the ABI.
+ *  - Arguments are validated on the host before any device work is queued; on
+ *    a validation error nothing is written.  gve_last_error(ctx) describes the
+ *    most recent failure.
+ *  - "d_" pointers are device pointers (HIP device memory on the context's
+ *    device); "h_" pointers are host pointers.  The caller owns every buffer it
+ *    passes and must keep it alive until the stream has executed the work.
+ *  - Work is queued on the context's stream.  Calls that write host memory
+ *    (h_ outputs) synchronise that stream before returning; the others are
+ *    asynchronous except for one small device-to-host read of the pair count
+ *    per evaluation (the binning below sizes its buffers from it).
+ *  - A context is not thread-safe; use one per host thread.  Contexts own
+ *    device scratch that grows as needed and is released by gve_destroy.
+ */
+#ifndef GVE_H
+#define GVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GVE_NPARAM 11 /* mu_x mu_y mu_z q_w q_x q_y q_z l_x l_y l_z c */
+
+typedef enum gve_status {
+  GVE_OK = 0,
+  GVE_ERR_INVALID_ARGUMENT = 1,
+  GVE_ERR_BUDGET_INFEASIBLE = 2, /* Sec. V-B: request cannot be met by distinct seeds */
+  GVE_ERR_OUT_OF_MEMORY = 3,
+  GVE_ERR_DEVICE = 4,            /* a HIP call or kernel launch failed */
+  GVE_ERR_NUMERIC = 5,           /* non-finite loss or parameters */
+  GVE_ERR_UNSUPPORTED = 6
+} gve_status;
+
+/* Regular voxel grid: nx*ny*nz voxels, voxel (i,j,k) at (x0+i, y0+j, z0+k). */
+typedef struct gve_grid {
+  int64_t nx, ny, nz;
+  int64_t x0, y0, z0;
+} gve_grid;
+
+/*
+ * Options.  k: truncation radius in standard deviations (> 0; Sec. III-C uses
+ * 5).  brick: edge of the cubic voxel bricks primitives are binned to (8 or
+ * 16; 0 picks 8).  lr, beta1, beta2, eps: Adam (Sec. III-F cites Kingma and
+ * Ba; Table tab:training-config gives lr 8e-3).  ell_min/ell_max: clamp of the
+ * log-scales after each Adam step (a guard against collapsing or exploding
+ * primitives; pass -inf/+inf to disable).
+ */
+typedef struct gve_options {
+  float k;
+  int32_t brick;
+  float lr, beta1, beta2, eps;
+  float ell_min, ell_max;
+} gve_options;
+
+/* Counters of the most recent evaluation / refinement iteration. */
+typedef struct gve_stats {
+  int64_t n_primitives;   /* N */
+  int64_t n_bricks;       /* bricks of the last grid */
+  int64_t n_overlaps;     /* T: (primitive, brick) pairs after binning */
+  int64_t n_clamped;      /* log-scale entries clamped so far (cumulative) */
+  int64_t iterations;     /* Adam steps taken on the last refined params */
+  double last_loss;       /* L = sum (Vhat - V)^2 of the last loss evaluation */
+} gve_stats;
+
+typedef struct gve_ctx gve_ctx;
+typedef struct gve_params gve_params;
+
+/* Fill *opt with k = 3, brick = 8, lr = 8e-3, beta = (0.9, 0.999),
+ * eps = 1e-8, no clamp.  Returns INVALID_ARGUMENT if opt is NULL. */
+gve_status gve_default_options(gve_options* opt);
+
+/* Create a context on the current HIP device.  hip_stream is a hipStream_t
+ * borrowed from the caller (NULL = the default stream); it must outlive the
+ * context.  opt NULL = defaults.  On success *out owns device scratch. */
+gve_status gve_create(gve_ctx** out, const gve_options* opt, void* hip_stream);
+gve_status gve_destroy(gve_ctx* ctx);
+gve_status gve_set_options(gve_ctx* ctx, const gve_options* opt);
+gve_status gve_get_options(const gve_ctx* ctx, gve_options* opt);
+
+/*
+ * Primitive sets.  A gve_params holds the N x 11 parameters as a device
+ * structure-of-arrays [11][n] (row a = parameter a, in GVE_NPARAM order),
+ * the Adam moments of the same shape and the Adam step counter.  n is fixed
+ * at creation (the fixed budget of Sec. III-A); n >= 1.
+ * upload/download copy the [11][n] float32 host array (and reset / keep the
+ * Adam state respectively).  gve_params_device returns the device pointer of
+ * the [11][n] parameter array (owned by the params; valid until destroy).
+ */
+gve_status gve_params_create(gve_ctx* ctx, int64_t n, gve_params** out);
+gve_status gve_params_destroy(gve_params* p);
+gve_status gve_params_size(const gve_params* p, int64_t* n);
+gve_status gve_params_upload(gve_ctx* ctx, gve_params* p, const float* h_soa);
+gve_status gve_params_download(gve_ctx* ctx, const gve_params* p, float* h_soa);
+gve_status gve_params_copy_from_device(gve_ctx* ctx, gve_params* p, const float* d_soa);
+gve_status gve_params_device(gve_params* p, float** d_soa);
+/* Zero the Adam moments and step counter. */
+gve_status gve_params_reset_adam(gve_ctx* ctx, gve_params* p);
+/* Adam state access: d_m, d_v are [11][n] device arrays owned by p; t the step. */
+gve_status gve_params_adam_state(gve_params* p, float** d_m, float** d_v, int64_t* t);
+gve_status gve_params_set_step(gve_params* p, int64_t t);
+
+/*
+ * Truncated field evaluation (Sec. III-C eq:field; Sec. III-G truncation-aware
+ * evaluation).  Writes Vhat on every voxel of g into d_out [nz][ny][nx]
+ * (caller-owned, nx*ny*nz floats).  Primitives are binned to bricks by their
+ * k-sigma bounding boxes; every (primitive, voxel) pair with m^2 < k^2 is
+ * summed in float32, in increasing primitive index per voxel, so the result is
+ * bitwise reproducible.  Errors: INVALID_ARGUMENT for null pointers or
+ * non-positive sizes; DEVICE for HIP failures.
+ */
+gve_status gve_evaluate(gve_ctx* ctx, const gve_params* p, gve_grid g, float* d_out);
+
+/*
+ * Loss and gradient (Sec. III-F value term, as a plain squared norm over
+ * every voxel of g).  L = sum_p (Vhat(p) - V(p))^2 with V = d_field [nz][ny][nx]
+ * float32.  Writes dL/dtheta as [11][n] float32 into d_grad (caller-owned;
+ * may be NULL to skip) with the truncation indicator held fixed, and L into
+ * *h_loss if h_loss is not NULL (synchronises).  Gradient sums use float32
+ * atomics, so the last bits depend on execution order.
+ */
+gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field, gve_grid g,
+                         float* d_grad, double* h_loss);
+
+/* One bias-corrected Adam step on p from the caller's gradient d_grad [11][n]
+ * (float32 device), followed by the optional log-scale clamp. */
+gve_status gve_adam_step(gve_ctx* ctx, gve_params* p, const float* d_grad);
+
+/*
+ * Fixed-budget refinement (Sec. III-F; Table tab:stages row S2): iters rounds
+ * of {bin, fused forward + squared-error + backward, chain rule + Adam}
+ * against the target d_field on grid g.  If h_loss_hist is not NULL it
+ * receives iters doubles, the loss L before each update (synchronises at the
+ * end).  iters >= 0.  The primitive count never changes.
+ */
+gve_status gve_refine(gve_ctx* ctx, gve_params* p, const float* d_field, gve_grid g,
+                      int32_t iters, double* h_loss_hist);
+
+/* Counters of the last call (see gve_stats). */
+gve_status gve_get_stats(const gve_ctx* ctx, gve_stats* out);
+
+/* Static description of a status code; never NULL. */
+const char* gve_status_string(gve_status s);
+/* Message of the last error on ctx ("" if none); valid until the next call. */
+const char* gve_last_error(const gve_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GVE_H */

@@ -1,0 +1,300 @@
+"""Python binding of libgve.so, the MI355X (gfx950) fixed-budget Gaussian volume encoder.
+
+Argument marshalling only: every step of evaluation, binning, loss, gradient
+and Adam runs in the HIP kernels of libgve.so (declared in include/gve.h).
+torch tensors supply device memory and the HIP stream; they are passed to the
+library as raw pointers.  Importing this module fails loudly if the library
+has not been built (``python -m paper_2608_14112_amd.build``).
+
+Names follow the C ABI without the ``gve_`` prefix:
+
+    ctx = Context(k=3.0, brick=8, lr=8e-3)
+    p = Params(ctx, n)              # fixed budget n (paper Sec. III-A)
+    p.upload(theta)                 # [11, n] float32 host array
+    evaluate(ctx, p, grid, out)     # out: float32 cuda tensor [nz, ny, nx]
+    L = loss_grad(ctx, p, field, grid, grad)
+    losses = refine(ctx, p, field, grid, iters)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgve.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2608_14112_amd.build` "
+        "(there is no fallback implementation)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+NPARAM = 11
+PARAM_NAMES = ("mu_x", "mu_y", "mu_z", "q_w", "q_x", "q_y", "q_z", "l_x", "l_y", "l_z", "c")
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "budget infeasible", 3: "out of device memory",
+          4: "device error", 5: "non-finite value", 6: "unsupported"}
+OK, INVALID_ARGUMENT, BUDGET_INFEASIBLE, OUT_OF_MEMORY, DEVICE, NUMERIC, UNSUPPORTED = range(7)
+
+
+class GveError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class GridC(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("x0", ctypes.c_int64), ("y0", ctypes.c_int64), ("z0", ctypes.c_int64)]
+
+
+class OptionsC(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_float), ("brick", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("ell_min", ctypes.c_float), ("ell_max", ctypes.c_float)]
+
+
+class StatsC(ctypes.Structure):
+    _fields_ = [("n_primitives", ctypes.c_int64), ("n_bricks", ctypes.c_int64),
+                ("n_overlaps", ctypes.c_int64), ("n_clamped", ctypes.c_int64),
+                ("iterations", ctypes.c_int64), ("last_loss", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_SIGS = {
+    "gve_default_options": [ctypes.POINTER(OptionsC)],
+    "gve_create": [ctypes.POINTER(_vp), ctypes.POINTER(OptionsC), _vp],
+    "gve_destroy": [_vp],
+    "gve_set_options": [_vp, ctypes.POINTER(OptionsC)],
+    "gve_get_options": [_vp, ctypes.POINTER(OptionsC)],
+    "gve_params_create": [_vp, _i64, ctypes.POINTER(_vp)],
+    "gve_params_destroy": [_vp],
+    "gve_params_size": [_vp, ctypes.POINTER(_i64)],
+    "gve_params_upload": [_vp, _vp, _vp],
+    "gve_params_download": [_vp, _vp, _vp],
+    "gve_params_copy_from_device": [_vp, _vp, _vp],
+    "gve_params_device": [_vp, ctypes.POINTER(_vp)],
+    "gve_params_reset_adam": [_vp, _vp],
+    "gve_params_adam_state": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i64)],
+    "gve_params_set_step": [_vp, _i64],
+    "gve_evaluate": [_vp, _vp, GridC, _vp],
+    "gve_loss_grad": [_vp, _vp, _vp, GridC, _vp, ctypes.POINTER(ctypes.c_double)],
+    "gve_adam_step": [_vp, _vp, _vp],
+    "gve_refine": [_vp, _vp, _vp, GridC, ctypes.c_int32, _vp],
+    "gve_get_stats": [_vp, ctypes.POINTER(StatsC)],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.gve_status_string.argtypes = [ctypes.c_int]
+_lib.gve_status_string.restype = ctypes.c_char_p
+_lib.gve_last_error.argtypes = [_vp]
+_lib.gve_last_error.restype = ctypes.c_char_p
+
+EXPORTED = tuple(_SIGS) + ("gve_status_string", "gve_last_error")
+
+
+def _check(status, ctx_handle=None):
+    if status != OK:
+        msg = _lib.gve_last_error(ctx_handle).decode() if ctx_handle else ""
+        raise GveError(status, msg or _lib.gve_status_string(status).decode())
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Voxel grid: voxel (i, j, k) sits at (x0 + i, y0 + j, z0 + k); arrays [nz, ny, nx]."""
+
+    nx: int
+    ny: int
+    nz: int
+    x0: int = 0
+    y0: int = 0
+    z0: int = 0
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def c(self):
+        return GridC(self.nx, self.ny, self.nz, self.x0, self.y0, self.z0)
+
+
+def _ptr(t, dtype=None, numel=None):
+    """Device pointer of a contiguous cuda tensor (checked)."""
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_options():
+    o = OptionsC()
+    _check(_lib.gve_default_options(ctypes.byref(o)))
+    return o
+
+
+class Context:
+    """Owns a gve_ctx bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, k=3.0, brick=8, lr=8e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 ell_min=-math.inf, ell_max=math.inf, stream=None):
+        import torch
+
+        self._torch_stream = stream if stream is not None else torch.cuda.current_stream()
+        o = OptionsC(k, brick, lr, beta1, beta2, eps, ell_min, ell_max)
+        h = _vp()
+        st = _lib.gve_create(ctypes.byref(h), ctypes.byref(o),
+                             _vp(self._torch_stream.cuda_stream))
+        if st != OK:
+            raise GveError(st, "gve_create failed")
+        self.handle = h
+
+    @property
+    def options(self):
+        o = OptionsC()
+        _check(_lib.gve_get_options(self.handle, ctypes.byref(o)), self.handle)
+        return o
+
+    def set_options(self, **kw):
+        o = self.options
+        for key, val in kw.items():
+            setattr(o, key, val)
+        _check(_lib.gve_set_options(self.handle, ctypes.byref(o)), self.handle)
+
+    def stats(self):
+        s = StatsC()
+        _check(_lib.gve_get_stats(self.handle, ctypes.byref(s)), self.handle)
+        return {f: getattr(s, f) for f, _ in StatsC._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Params:
+    """A fixed-budget primitive set: device [11][n] parameters plus Adam state."""
+
+    def __init__(self, ctx: Context, n: int):
+        self.ctx = ctx
+        self.n = int(n)
+        h = _vp()
+        _check(_lib.gve_params_create(ctx.handle, _i64(self.n), ctypes.byref(h)), ctx.handle)
+        self.handle = h
+
+    def upload(self, theta):
+        a = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).reshape(NPARAM, self.n))
+        _check(_lib.gve_params_upload(self.ctx.handle, self.handle, a.ctypes.data_as(_vp)),
+               self.ctx.handle)
+        return self
+
+    def upload_device(self, theta):
+        import torch
+
+        _check(_lib.gve_params_copy_from_device(
+            self.ctx.handle, self.handle, _ptr(theta, torch.float32, NPARAM * self.n)),
+            self.ctx.handle)
+        return self
+
+    def download(self):
+        a = np.empty((NPARAM, self.n), dtype=np.float32)
+        _check(_lib.gve_params_download(self.ctx.handle, self.handle, a.ctypes.data_as(_vp)),
+               self.ctx.handle)
+        return a
+
+    def device_ptr(self):
+        d = _vp()
+        _check(_lib.gve_params_device(self.handle, ctypes.byref(d)))
+        return d.value
+
+    def reset_adam(self):
+        _check(_lib.gve_params_reset_adam(self.ctx.handle, self.handle), self.ctx.handle)
+
+    @property
+    def step(self):
+        t = _i64()
+        _check(_lib.gve_params_adam_state(self.handle, None, None, ctypes.byref(t)))
+        return t.value
+
+    @step.setter
+    def step(self, t):
+        _check(_lib.gve_params_set_step(self.handle, _i64(int(t))))
+
+    def adam_state_ptrs(self):
+        m, v, t = _vp(), _vp(), _i64()
+        _check(_lib.gve_params_adam_state(self.handle, ctypes.byref(m), ctypes.byref(v),
+                                          ctypes.byref(t)))
+        return m.value, v.value, t.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gve_params_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def evaluate(ctx: Context, params: Params, grid: Grid, out):
+    """gve_evaluate: truncated field on ``grid`` into ``out`` (float32 cuda [nz, ny, nx])."""
+    import torch
+
+    _check(_lib.gve_evaluate(ctx.handle, params.handle, grid.c(),
+                             _ptr(out, torch.float32, grid.nx * grid.ny * grid.nz)), ctx.handle)
+    return out
+
+
+def loss_grad(ctx: Context, params: Params, field, grid: Grid, grad=None, want_loss=True):
+    """gve_loss_grad: returns L (float) if want_loss; fills grad ([11, n] float32 cuda) if given."""
+    import torch
+
+    n = grid.nx * grid.ny * grid.nz
+    gp = _ptr(grad, torch.float32, NPARAM * params.n) if grad is not None else None
+    L = ctypes.c_double(0.0)
+    _check(_lib.gve_loss_grad(ctx.handle, params.handle, _ptr(field, torch.float32, n), grid.c(),
+                              gp, ctypes.byref(L) if want_loss else None), ctx.handle)
+    return L.value if want_loss else None
+
+
+def adam_step(ctx: Context, params: Params, grad):
+    """gve_adam_step: one Adam step from a caller gradient ([11, n] float32 cuda)."""
+    import torch
+
+    _check(_lib.gve_adam_step(ctx.handle, params.handle, _ptr(grad, torch.float32,
+                                                               NPARAM * params.n)), ctx.handle)
+
+
+def refine(ctx: Context, params: Params, field, grid: Grid, iters: int, want_losses=True):
+    """gve_refine: ``iters`` fused iterations; returns the loss before each update."""
+    import torch
+
+    n = grid.nx * grid.ny * grid.nz
+    hist = np.zeros(max(int(iters), 1), dtype=np.float64) if want_losses else None
+    _check(_lib.gve_refine(ctx.handle, params.handle, _ptr(field, torch.float32, n), grid.c(),
+                           ctypes.c_int32(int(iters)),
+                           hist.ctypes.data_as(_vp) if want_losses else None), ctx.handle)
+    return hist[:iters] if want_losses else None

@@ -1,0 +1,195 @@
+// Truncation-aware binning of primitives to voxel bricks (paper Sec. III-G:
+// only pairs inside the k-sigma support contribute, so each primitive is
+// visited only from the bricks its support can reach).
+//
+//   prep   : per primitive, normalised quaternion -> R, scales, the column
+//            form of A = -(log2 e / 2) R S^-2 R^T (see Record), the k-sigma
+//            bounding box
+//            (|d_j| < k sqrt(Sigma_jj) bounds the ellipsoid m^2 < k^2) clipped
+//            to the grid, and the number of bricks that box touches;
+//   emit   : the (brick, primitive) pairs at the scanned offsets;
+//   ranges : first pair of every brick in the brick-sorted list (binary search).
+#include "common.h"
+
+namespace gve {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ inline uint32_t prep_one(const float* __restrict__ theta, int64_t n, int64_t i,
+                                    gve_grid g, float k, BrickGeom bg, Record* __restrict__ rec) {
+  const float mx = theta[0 * n + i], my = theta[1 * n + i], mz = theta[2 * n + i];
+  float qw = theta[3 * n + i], qx = theta[4 * n + i], qy = theta[5 * n + i],
+        qz = theta[6 * n + i];
+  const float lx = theta[7 * n + i], ly = theta[8 * n + i], lz = theta[9 * n + i];
+  const float c = theta[10 * n + i];
+  const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  if (qn >= 1e-12f) {
+    const float inv = 1.0f / qn;
+    qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+  } else {
+    qw = 1.f; qx = qy = qz = 0.f;
+  }
+  const float r00 = 1.f - 2.f * (qy * qy + qz * qz), r01 = 2.f * (qx * qy - qw * qz),
+              r02 = 2.f * (qx * qz + qw * qy);
+  const float r10 = 2.f * (qx * qy + qw * qz), r11 = 1.f - 2.f * (qx * qx + qz * qz),
+              r12 = 2.f * (qy * qz - qw * qx);
+  const float r20 = 2.f * (qx * qz - qw * qy), r21 = 2.f * (qy * qz + qw * qx),
+              r22 = 1.f - 2.f * (qx * qx + qy * qy);
+  const float i0 = expf(-2.f * lx), i1 = expf(-2.f * ly), i2 = expf(-2.f * lz);
+  const float s0 = expf(2.f * lx), s1 = expf(2.f * ly), s2 = expf(2.f * lz);
+  // z row of the precision P = R diag(i) R^T
+  const float pxz = r00 * r20 * i0 + r01 * r21 * i1 + r02 * r22 * i2;
+  const float pyz = r10 * r20 * i0 + r11 * r21 * i1 + r12 * r22 * i2;
+  const float pzz = r20 * r20 * i0 + r21 * r21 * i1 + r22 * r22 * i2;
+  // diagonal of Sigma = R diag(s^2) R^T
+  const float sxx = r00 * r00 * s0 + r01 * r01 * s1 + r02 * r02 * s2;
+  const float syy = r10 * r10 * s0 + r11 * r11 * s1 + r12 * r12 * s2;
+  const float szz = r20 * r20 * s0 + r21 * r21 * s1 + r22 * r22 * s2;
+
+  // xy block of Sigma and its inverse.  det(Sigma_xy) = det(Sigma) P_zz
+  // (Cauchy-Binet; the 2x2 minors of R's first two rows are its third row),
+  // a sum of positive terms, so 1 / det needs no cancelling subtraction.
+  const float sxy = r00 * r10 * s0 + r01 * r11 * s1 + r02 * r12 * s2;
+  const float idet = (i0 * i1 * i2) / pzz;
+
+  Record r;
+  r.mu[0] = mx; r.mu[1] = my; r.mu[2] = mz;
+  r.c = c;
+  r.azz = -kHalfLog2e * pzz;
+  r.s[0] = -kHalfLog2e * syy * idet;
+  r.s[1] = kHalfLog2e * sxy * idet;
+  r.s[2] = -kHalfLog2e * sxx * idet;
+  r.gx = -pxz / pzz;
+  r.gy = -pyz / pzz;
+
+  // conservative box: relative and absolute slack cover float32 rounding here
+  const float mu3[3] = {mx, my, mz};
+  const float sd[3] = {sxx, syy, szz};
+  const int64_t org[3] = {g.x0, g.y0, g.z0};
+  const int64_t dim[3] = {g.nx, g.ny, g.nz};
+  bool empty = false;
+  int lo[3], hi[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float h = k * sqrtf(sd[j]) * (1.0f + 1e-5f) + 1e-3f;
+    const float a = mu3[j] - (float)org[j] - h;
+    const float b = mu3[j] - (float)org[j] + h;
+    if (!(a == a) || !(b == b) || !(h == h)) {  // NaN
+      empty = true;
+      lo[j] = 0; hi[j] = -1;
+      continue;
+    }
+    const float fd = (float)dim[j];
+    const float ac = fminf(fmaxf(ceilf(a), -1.0f), fd);
+    const float bc = fminf(fmaxf(floorf(b), -1.0f), fd);
+    lo[j] = clampi((int)ac, 0, (int)dim[j] - 1);
+    hi[j] = clampi((int)bc, 0, (int)dim[j] - 1);
+    if (ac > bc || bc < 0.f || ac > fd - 1.f) empty = true;
+  }
+  uint32_t cnt = 0;
+  if (!empty) {
+    cnt = (uint32_t)(hi[0] / bg.B - lo[0] / bg.B + 1) * (uint32_t)(hi[1] / bg.B - lo[1] / bg.B + 1) *
+          (uint32_t)(hi[2] / bg.B - lo[2] / bg.B + 1);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { lo[j] = 1; hi[j] = 0; }
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) { r.lo[j] = lo[j]; r.hi[j] = hi[j]; }
+  rec[i] = r;
+  return cnt;
+}
+
+__global__ __launch_bounds__(kThreads) void k_prep(const float* __restrict__ theta, int64_t n,
+                                                   gve_grid g, float k, BrickGeom bg,
+                                                   Record* __restrict__ rec,
+                                                   uint32_t* __restrict__ count,
+                                                   unsigned long long* __restrict__ total) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  uint32_t cnt = 0;
+  if (i < n) cnt = prep_one(theta, n, i, g, k, bg, rec);
+  if (i < n) count[i] = cnt;
+  // 64-bit pair total (the scan itself is 32-bit): one atomic per wave
+  unsigned long long w = cnt;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) w += __shfl_xor(w, d, 64);
+  if ((threadIdx.x & 63) == 0 && w) atomicAdd(total, w);
+}
+
+__global__ __launch_bounds__(kThreads) void k_emit(const Record* __restrict__ rec,
+                                                   const uint32_t* __restrict__ offset, int64_t n,
+                                                   BrickGeom bg, uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  uint32_t o = offset[i];
+  const uint32_t e = offset[i + 1];
+  if (o == e) return;
+  const Record& r = rec[i];
+  const int bx0 = r.lo[0] / bg.B, bx1 = r.hi[0] / bg.B;
+  const int by0 = r.lo[1] / bg.B, by1 = r.hi[1] / bg.B;
+  const int bz0 = r.lo[2] / bg.B, bz1 = r.hi[2] / bg.B;
+  for (int bz = bz0; bz <= bz1; ++bz)
+    for (int by = by0; by <= by1; ++by) {
+      const uint32_t row = (uint32_t)bg.nbx * ((uint32_t)by + (uint32_t)bg.nby * (uint32_t)bz);
+      for (int bx = bx0; bx <= bx1; ++bx) {
+        keys[o] = row + (uint32_t)bx;
+        vals[o] = (uint32_t)i;
+        ++o;
+      }
+    }
+}
+
+// brick_start[b] = first index whose key >= b, for b in [0, nbricks].
+__global__ __launch_bounds__(kThreads) void k_ranges(const uint32_t* __restrict__ keys,
+                                                     int64_t npairs, int64_t nbricks,
+                                                     uint32_t* __restrict__ start) {
+  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (b > nbricks) return;
+  int64_t lo = 0, hi = npairs;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)keys[mid] < b) lo = mid + 1; else hi = mid;
+  }
+  start[b] = (uint32_t)lo;
+}
+
+}  // namespace
+
+BrickGeom brick_geometry(const gve_grid& g, int B) {
+  BrickGeom bg;
+  bg.B = B;
+  bg.nbx = (int)((g.nx + B - 1) / B);
+  bg.nby = (int)((g.ny + B - 1) / B);
+  bg.nbz = (int)((g.nz + B - 1) / B);
+  bg.nbricks = (int64_t)bg.nbx * bg.nby * bg.nbz;
+  return bg;
+}
+
+hipError_t launch_prep(const float* theta, int64_t n, gve_grid g, float k, BrickGeom bg,
+                       Record* rec, uint32_t* count, unsigned long long* total, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(kThreads), 0, s, theta, n, g, k, bg, rec, count,
+                     total);
+  return hipGetLastError();
+}
+
+hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, BrickGeom bg,
+                       uint32_t* keys, uint32_t* vals, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, rec, offset, n, bg, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t npairs, int64_t nbricks,
+                         uint32_t* brick_start, hipStream_t s) {
+  const unsigned blocks = (unsigned)((nbricks + 1 + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(kThreads), 0, s, sorted_keys, npairs, nbricks,
+                     brick_start);
+  return hipGetLastError();
+}
+
+}  // namespace gve

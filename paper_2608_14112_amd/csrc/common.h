@@ -1,0 +1,134 @@
+// Internal declarations shared by the HIP translation units of libgve.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "gve.h"
+
+namespace gve {
+
+// Per-primitive record written by the prep kernel and read by the field
+// kernels: 16 x 32-bit = 64 bytes, one scalar-load line.  With
+// A = -(log2 e / 2) Sigma^{-1}, exp(-m^2/2) = exp2(d^T A d).  Along a voxel
+// column (fixed dx, dy) d^T A d is a parabola in dz with its vertex at
+// dz = gx dx + gy dy and height qxy(dx, dy) = d_xy^T S d_xy, S the Schur
+// complement -(log2 e / 2) (Sigma_xy)^{-1}:
+//     d^T A d = qxy + azz (dz - gx dx - gy dy)^2.
+//   mu[3], c, azz, s[3] = (S_xx, S_xy, S_yy), gx, gy,
+//   lo[3], hi[3] : inclusive voxel-index bounding box of the k-sigma support.
+struct alignas(64) Record {
+  float mu[3];
+  float c;
+  float azz;
+  float s[3];
+  float gx, gy;
+  int lo[3];
+  int hi[3];
+};
+static_assert(sizeof(Record) == 64, "record must be 64 bytes");
+
+constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
+
+struct Scratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// Buffers owned by a context, grown on demand.
+struct Workspace {
+  Scratch keys[2], vals[2];      // (brick key, primitive id) pairs, ping-pong
+  Scratch brick_start;           // uint32 [n_bricks + 1]
+  Scratch brick_loss;            // float  [n_bricks]
+  Scratch scan_tmp;              // scan partials
+  Scratch sort_hist;             // radix sort histograms
+  Scratch dloss;                 // double [4]
+  Scratch clamp_count;           // unsigned long long
+  Scratch grad_tmp;              // float [11][n] for loss_grad without caller buffer
+  void* h_pinned = nullptr;      // pinned host staging (64 bytes)
+};
+
+}  // namespace gve
+
+struct gve_ctx {
+  gve_options opt;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  gve::Workspace ws;
+  gve_stats stats{};
+  std::string last_error;
+};
+
+struct gve_params {
+  int64_t n = 0;
+  int device = 0;
+  float* theta = nullptr;   // [11][n]
+  float* m = nullptr;       // [11][n]
+  float* v = nullptr;       // [11][n]
+  float* acc = nullptr;     // [10][n] gradient partial sums (see field kernels)
+  gve::Record* rec = nullptr;  // [n]
+  uint32_t* count = nullptr;   // [n]   bricks overlapped per primitive
+  uint32_t* offset = nullptr;  // [n+1] exclusive scan of count
+  int64_t t = 0;               // Adam step
+};
+
+namespace gve {
+
+// ---- launch wrappers (each returns hipSuccess or the launch error) ----------
+
+// Device-wide exclusive scan of n uint32 values into out[0..n]; out[n] = total.
+// tmp must hold scan_tmp_bytes(n) bytes.
+size_t scan_tmp_bytes(int64_t n);
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void* tmp,
+                              hipStream_t s);
+
+// Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits of
+// the key.  Ping-pongs between buffers 0 and 1; returns in *which the index of
+// the buffer that holds the result.
+size_t sort_hist_bytes(int64_t n);
+hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits,
+                            void* hist, int* which, hipStream_t s);
+
+struct BrickGeom {
+  int B;                 // brick edge in voxels
+  int nbx, nby, nbz;     // bricks per axis
+  int64_t nbricks;
+};
+
+BrickGeom brick_geometry(const gve_grid& g, int B);
+
+// Writes rec and count for every primitive and adds the pair total to *total
+// (which the caller zeroes first).
+hipError_t launch_prep(const float* theta, int64_t n, gve_grid g, float k, BrickGeom bg,
+                       Record* rec, uint32_t* count, unsigned long long* total, hipStream_t s);
+hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, BrickGeom bg,
+                       uint32_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t npairs, int64_t nbricks,
+                         uint32_t* brick_start, hipStream_t s);
+
+hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid,
+                          const uint32_t* brick_start, gve_grid g, BrickGeom bg, float k,
+                          float* out, hipStream_t s);
+hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid,
+                        const uint32_t* brick_start, gve_grid g, BrickGeom bg, float k,
+                        const float* field, float* acc, int64_t n, float* brick_loss,
+                        hipStream_t s);
+// Sum of brick_loss in double into *out; part holds loss_reduce_tmp_doubles().
+size_t loss_reduce_tmp_doubles();
+hipError_t launch_loss_reduce(const float* brick_loss, int64_t nbricks, double* part, double* out,
+                              hipStream_t s);
+
+// Small utility kernels.
+hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t s);
+hipError_t fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
+
+// mode 0: chain rule -> grad_out ([11][n]); mode 1: chain rule + Adam;
+// mode 2: Adam from grad_in.  Zeroes acc in modes 0 and 1.
+hipError_t launch_update(int mode, float* theta, float* m, float* v, float* acc,
+                         const float* grad_in, float* grad_out, int64_t n, int64_t t,
+                         const gve_options& opt, unsigned long long* clamp_count,
+                         hipStream_t s);
+
+}  // namespace gve

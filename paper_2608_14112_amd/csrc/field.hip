@@ -1,0 +1,300 @@
+// Per-brick field kernels.
+//
+// A workgroup owns one B x B x B brick; lane (lx, ly) owns the voxel column
+// (x, y, z0 .. z0 + B - 1) and keeps its B values in registers.  The brick's
+// primitives (a contiguous run of the brick-sorted pair list, increasing
+// primitive index) are read one at a time with wave-uniform scalar loads.
+//
+// Along a column (fixed dx, dy) the exponent is a parabola in dz (see Record):
+//     Q = qxy + azz t^2,  t = dz - (gx dx + gy dy),
+// with exp(-m^2/2) = exp2(Q), and the cut m^2 < k^2 (Sec. III-C) is
+// Q > -(log2 e / 2) k^2.  t advances by exactly 1 per voxel and Q is formed
+// afresh from it (two operations), so rounding does not accumulate along the
+// column.  The loop runs over the primitive's bounding-box z-range inside the
+// brick only.
+//
+//   k_forward : Vhat on the brick (Sec. III-C eq:field, truncated).
+//   k_fused   : Vhat, residual r = 2 (Vhat - V), the brick's share of
+//               L = sum (Vhat - V)^2, then for every primitive of the brick the
+//               ten sums of the analytic gradient (e = r G, g = c e,
+//               d = p - mu): sum e, sum g d (3), sum g d d^T (6 unique),
+//               reduced over the workgroup with cross-lane shuffles and LDS and
+//               added to the primitive's accumulators with one float atomic
+//               each.  Per column only sum e, sum e t, sum e t^2 are needed
+//               because dx, dy and dz - t are constant along it.
+#include "common.h"
+
+namespace gve {
+namespace {
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+struct ColumnSetup {
+  float qxy, t, ofs;
+  int za, zb;
+};
+
+template <int B>
+__device__ inline ColumnSetup column_setup(const Record& r, float px, float py, float pz0, int iz0) {
+  ColumnSetup s;
+  s.za = max(r.lo[2] - iz0, 0);
+  s.zb = min(r.hi[2] - iz0, B - 1);
+  const float dx = px - r.mu[0];
+  const float dy = py - r.mu[1];
+  s.qxy = (r.s[0] * dx + 2.0f * r.s[1] * dy) * dx + r.s[2] * dy * dy;
+  s.ofs = r.gx * dx + r.gy * dy;
+  s.t = (pz0 + (float)s.za - r.mu[2]) - s.ofs;
+  return s;
+}
+
+__device__ inline Record load_record(const Record* __restrict__ rec, uint32_t gid) {
+  return rec[gid];
+}
+
+template <int B>
+__device__ inline void accumulate_brick(const Record* __restrict__ rec,
+                                        const uint32_t* __restrict__ pair_gid, uint32_t j0,
+                                        uint32_t j1, float px, float py, float pz0, int iz0,
+                                        float thr, float (&acc)[B]) {
+  for (uint32_t j = j0; j < j1; ++j) {
+    const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
+    const Record r = load_record(rec, gid);
+    ColumnSetup s = column_setup<B>(r, px, py, pz0, iz0);
+#pragma unroll
+    for (int zz = 0; zz < B; ++zz) {
+      if (zz >= s.za && zz <= s.zb) {
+        const float q = fmaf(r.azz * s.t, s.t, s.qxy);
+        if (q > thr) acc[zz] += r.c * __builtin_amdgcn_exp2f(q);
+        s.t += 1.0f;
+      }
+    }
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(B* B) void k_forward(const Record* __restrict__ rec,
+                                                  const uint32_t* __restrict__ pair_gid,
+                                                  const uint32_t* __restrict__ brick_start,
+                                                  gve_grid g, BrickGeom bg, float thr,
+                                                  float* __restrict__ out) {
+  const int64_t b = blockIdx.x;
+  const int bx = (int)(b % bg.nbx);
+  const int by = (int)((b / bg.nbx) % bg.nby);
+  const int bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
+  const int ix = bx * B + (int)(threadIdx.x % B);
+  const int iy = by * B + (int)(threadIdx.x / B);
+  const int iz0 = bz * B;
+  const float px = (float)(g.x0 + ix), py = (float)(g.y0 + iy), pz0 = (float)(g.z0 + iz0);
+  float acc[B];
+#pragma unroll
+  for (int zz = 0; zz < B; ++zz) acc[zz] = 0.0f;
+  accumulate_brick<B>(rec, pair_gid, brick_start[b], brick_start[b + 1], px, py, pz0, iz0, thr,
+                      acc);
+  if (ix < g.nx && iy < g.ny) {
+    const size_t plane = (size_t)g.nx * (size_t)g.ny;
+    const size_t base = (size_t)ix + (size_t)g.nx * (size_t)iy;
+#pragma unroll
+    for (int zz = 0; zz < B; ++zz)
+      if (iz0 + zz < g.nz) out[base + plane * (size_t)(iz0 + zz)] = acc[zz];
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(B* B) void k_fused(const Record* __restrict__ rec,
+                                                const uint32_t* __restrict__ pair_gid,
+                                                const uint32_t* __restrict__ brick_start,
+                                                gve_grid g, BrickGeom bg, float thr,
+                                                const float* __restrict__ field,
+                                                float* __restrict__ gacc, int64_t n,
+                                                float* __restrict__ brick_loss) {
+  constexpr int kWaves = (B * B + 63) / 64;
+  __shared__ float red[kWaves][10];
+  const int64_t b = blockIdx.x;
+  const int bx = (int)(b % bg.nbx);
+  const int by = (int)((b / bg.nbx) % bg.nby);
+  const int bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
+  const int ix = bx * B + (int)(threadIdx.x % B);
+  const int iy = by * B + (int)(threadIdx.x / B);
+  const int iz0 = bz * B;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const float px = (float)(g.x0 + ix), py = (float)(g.y0 + iy), pz0 = (float)(g.z0 + iz0);
+  const uint32_t j0 = brick_start[b], j1 = brick_start[b + 1];
+
+  float res[B];
+#pragma unroll
+  for (int zz = 0; zz < B; ++zz) res[zz] = 0.0f;
+  accumulate_brick<B>(rec, pair_gid, j0, j1, px, py, pz0, iz0, thr, res);
+
+  // residual and this brick's share of the loss
+  float lsum = 0.0f;
+  const bool col_in = (ix < g.nx) && (iy < g.ny);
+  const size_t plane = (size_t)g.nx * (size_t)g.ny;
+  const size_t base = (size_t)ix + (size_t)g.nx * (size_t)iy;
+#pragma unroll
+  for (int zz = 0; zz < B; ++zz) {
+    float r = 0.0f;
+    if (col_in && iz0 + zz < g.nz) {
+      const float d = res[zz] - field[base + plane * (size_t)(iz0 + zz)];
+      lsum += d * d;
+      r = 2.0f * d;
+    }
+    res[zz] = r;
+  }
+  lsum = wave_sum(lsum);
+  if (lane == 0) red[wave][0] = lsum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int w = 0; w < kWaves; ++w) t += red[w][0];
+    brick_loss[b] = t;
+  }
+  __syncthreads();
+
+  for (uint32_t j = j0; j < j1; ++j) {
+    const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
+    const Record r = load_record(rec, gid);
+    ColumnSetup s = column_setup<B>(r, px, py, pz0, iz0);
+    float se = 0.0f, st = 0.0f, stt = 0.0f;
+#pragma unroll
+    for (int zz = 0; zz < B; ++zz) {
+      if (zz >= s.za && zz <= s.zb) {
+        const float q = fmaf(r.azz * s.t, s.t, s.qxy);
+        const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
+        const float e = res[zz] * G;
+        se += e;
+        const float et = e * s.t;
+        st += et;
+        stt = fmaf(et, s.t, stt);
+        s.t += 1.0f;
+      }
+    }
+    const float dx = px - r.mu[0];
+    const float dy = py - r.mu[1];
+    // sum e dz = st + ofs se;  sum e dz^2 = stt + 2 ofs st + ofs^2 se
+    const float s1 = fmaf(s.ofs, se, st);
+    const float s2 = fmaf(s.ofs, fmaf(s.ofs, se, 2.0f * st), stt);
+    const float cse = r.c * se, cs1 = r.c * s1;
+    float v[10];
+    v[0] = se;
+    v[1] = dx * cse;
+    v[2] = dy * cse;
+    v[3] = cs1;
+    v[4] = dx * dx * cse;
+    v[5] = dx * dy * cse;
+    v[6] = dx * cs1;
+    v[7] = dy * dy * cse;
+    v[8] = dy * cs1;
+    v[9] = r.c * s2;
+#pragma unroll
+    for (int a = 0; a < 10; ++a) v[a] = wave_sum(v[a]);
+    if (kWaves == 1) {
+      if (lane < 10) {
+        float mine = v[0];
+#pragma unroll
+        for (int a = 1; a < 10; ++a) mine = (lane == a) ? v[a] : mine;
+        unsafeAtomicAdd(&gacc[(int64_t)lane * n + gid], mine);
+      }
+    } else {
+      if (lane < 10) {
+        float mine = v[0];
+#pragma unroll
+        for (int a = 1; a < 10; ++a) mine = (lane == a) ? v[a] : mine;
+        red[wave][lane] = mine;
+      }
+      __syncthreads();
+      if (threadIdx.x < 10) {
+        float t = 0.0f;
+        for (int w = 0; w < kWaves; ++w) t += red[w][threadIdx.x];
+        unsafeAtomicAdd(&gacc[(int64_t)threadIdx.x * n + gid], t);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Deterministic two-level sum of the per-brick losses in double precision.
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 512;
+
+__global__ __launch_bounds__(kRedThreads) void k_loss_partial(const float* __restrict__ x,
+                                                              int64_t n, double* __restrict__ part) {
+  __shared__ double sh[kRedThreads];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t a = (int64_t)blockIdx.x * per;
+  const int64_t e = min(n, a + per);
+  double s = 0.0;
+  for (int64_t i = a + threadIdx.x; i < e; i += kRedThreads) s += (double)x[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_loss_final(const double* __restrict__ part, int np,
+                                                            double* __restrict__ out) {
+  __shared__ double sh[kRedThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += kRedThreads) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+}  // namespace
+
+hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
+                          gve_grid g, BrickGeom bg, float k, float* out, hipStream_t s) {
+  const float thr = -kHalfLog2e * k * k;
+  const dim3 grid((unsigned)bg.nbricks);
+  if (bg.B == 8)
+    hipLaunchKernelGGL(k_forward<8>, grid, dim3(64), 0, s, rec, pair_gid, brick_start, g, bg, thr,
+                       out);
+  else if (bg.B == 16)
+    hipLaunchKernelGGL(k_forward<16>, grid, dim3(256), 0, s, rec, pair_gid, brick_start, g, bg,
+                       thr, out);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
+                        gve_grid g, BrickGeom bg, float k, const float* field, float* acc,
+                        int64_t n, float* brick_loss, hipStream_t s) {
+  const float thr = -kHalfLog2e * k * k;
+  const dim3 grid((unsigned)bg.nbricks);
+  if (bg.B == 8)
+    hipLaunchKernelGGL(k_fused<8>, grid, dim3(64), 0, s, rec, pair_gid, brick_start, g, bg, thr,
+                       field, acc, n, brick_loss);
+  else if (bg.B == 16)
+    hipLaunchKernelGGL(k_fused<16>, grid, dim3(256), 0, s, rec, pair_gid, brick_start, g, bg, thr,
+                       field, acc, n, brick_loss);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+size_t loss_reduce_tmp_doubles() { return kRedBlocks; }
+
+hipError_t launch_loss_reduce(const float* brick_loss, int64_t nbricks, double* part, double* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_loss_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, s, brick_loss,
+                     nbricks, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kRedThreads), 0, s, part, kRedBlocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace gve

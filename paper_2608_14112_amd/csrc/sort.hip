@@ -1,0 +1,128 @@
+// Stable LSD radix sort of (key, value) uint32 pairs.
+//
+// Sorts the (brick, primitive) overlap pairs by brick so that each brick's
+// primitives form one contiguous run, in increasing primitive index (the
+// pairs are emitted in primitive order and every pass is stable).  Each pass
+// handles `w` <= 8 key bits:
+//   1. per-tile digit histogram, stored digit-major: hist[d * ntiles + tile];
+//   2. exclusive scan of the flattened histogram -> global write offsets;
+//   3. stable scatter: a tile is consumed in rounds of 256 items in index
+//      order; an item's rank among equal digits in its wave comes from eight
+//      ballots, across waves from per-wave counts in LDS.
+#include "common.h"
+
+namespace gve {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kRounds = 8;
+constexpr int kTile = kThreads * kRounds;
+constexpr int kRadix = 256;
+
+__global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                   int shift, uint32_t mask, int64_t ntiles,
+                                                   uint32_t* __restrict__ hist) {
+  __shared__ uint32_t cnt[kRadix];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int64_t n, int shift,
+    uint32_t mask, int wbits, int64_t ntiles, const uint32_t* __restrict__ offs,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+  __shared__ uint32_t run[kRadix];            // items of each digit already placed
+  __shared__ uint32_t wcnt[kWaves][kRadix];   // this round's count per wave and digit
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  run[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  for (int r = 0; r < kRounds; ++r) {
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    const bool valid = i < n;
+    uint32_t key = 0, val = 0, d = 0;
+    if (valid) {
+      key = kin[i];
+      val = vin[i];
+      d = (key >> shift) & mask;
+    }
+    // lanes holding the same digit (invalid lanes excluded)
+    uint64_t same = __ballot(valid);
+    for (int b = 0; b < wbits; ++b) {
+      uint64_t bal = __ballot((d >> b) & 1u);
+      same &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    const uint32_t rank_in_wave = __popcll(same & lt_mask);
+    if (valid && rank_in_wave == 0) wcnt[wave][d] = (uint32_t)__popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank_in_wave;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) add += wcnt[w][threadIdx.x];
+    run[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+int64_t ntiles_of(int64_t n) { return (n + kTile - 1) / kTile; }
+
+}  // namespace
+
+size_t sort_hist_bytes(int64_t n) {
+  int64_t t = ntiles_of(n > 0 ? n : 1);
+  int64_t h = (int64_t)kRadix * t;
+  return 2 * (size_t)(h + 1) * sizeof(uint32_t) + scan_tmp_bytes(h) + 256;
+}
+
+hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits,
+                            void* hist_mem, int* which, hipStream_t s) {
+  *which = 0;
+  if (n <= 1 || bits <= 0) return hipSuccess;
+  const int64_t t = ntiles_of(n);
+  const int64_t h = (int64_t)kRadix * t;
+  uint32_t* hist = static_cast<uint32_t*>(hist_mem);
+  uint32_t* offs = hist + (h + 1);
+  void* stmp = offs + (h + 1);
+  const int passes = (bits + 7) / 8;
+  const int w = (bits + passes - 1) / passes;
+  int cur = 0;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * w;
+    const int wb = (shift + w <= bits) ? w : (bits - shift);
+    const uint32_t mask = (1u << wb) - 1u;
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)t), dim3(kThreads), 0, s, keys[cur], n, shift, mask,
+                       t, hist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_exclusive_u32(hist, offs, h, stmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)t), dim3(kThreads), 0, s, keys[cur], vals[cur], n,
+                       shift, mask, wb, t, offs, keys[cur ^ 1], vals[cur ^ 1]);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    cur ^= 1;
+  }
+  *which = cur;
+  return hipSuccess;
+}
+
+}  // namespace gve

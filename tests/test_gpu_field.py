@@ -1,0 +1,196 @@
+"""GPU parity of evaluation, loss/gradient, Adam and refinement vs the oracle.
+
+Every case calls the HIP path through the C ABI (the Python binding) and the
+float64 oracle on the same seeded inputs; tolerances are those of
+tests/parity.py.
+"""
+import numpy as np
+import pytest
+
+from oracle import field as F
+from synth import fields as S
+from tests.parity import BAND, check_field, check_grad
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import torch
+
+    import paper_2608_14112_amd as g
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return g, torch
+
+
+def _eval_gpu(g, torch, params, grid, k, brick):
+    ctx = g.Context(k=k, brick=brick)
+    p = g.Params(ctx, params.shape[1]).upload(params.astype(np.float32))
+    out = torch.empty(grid.shape, device="cuda", dtype=torch.float32)
+    g.evaluate(ctx, p, g.Grid(grid.nx, grid.ny, grid.nz, grid.x0, grid.y0, grid.z0), out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ctx.stats()
+
+
+def _case(n, grid, seed, scale_range=(0.6, 4.0)):
+    p = S.random_params(n, (grid.nx, grid.ny, grid.nz), seed=seed, scale_range=scale_range,
+                        unit_quat=False)
+    # let some primitives hang over the grid faces
+    p[0] += grid.x0 + np.random.default_rng(seed).uniform(-3, 3, n)
+    p[1] += grid.y0
+    p[2] += grid.z0
+    return p.astype(np.float32).astype(np.float64)
+
+
+CASES = [
+    # (grid, n, seed): several bricks per axis with ragged tails, non-zero origins
+    (F.Grid(37, 29, 21, 3, -2, 5), 60, 0),
+    (F.Grid(17, 40, 33, -7, 0, 2), 45, 1),
+]
+
+
+@pytest.mark.parametrize("k", [3.0, 5.0])
+@pytest.mark.parametrize("brick", [8, 16])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_evaluate_matches_oracle(k, brick, case):
+    g, torch = _lib()
+    grid, n, seed = CASES[case]
+    print(f"evaluate grid={grid} n={n} seed={seed} k={k} B={brick}", flush=True)
+    params = _case(n, grid, seed)
+    got, st = _eval_gpu(g, torch, params, grid, k, brick)
+    V, A, br = F.evaluate_windowed(params, grid, k, band=BAND)
+    check_field(got, V, A, br)
+    assert st["n_primitives"] == n and st["n_overlaps"] > 0
+
+
+def test_evaluate_tiny_workload_size():
+    """64^3 grid, 2,048 primitives with scales 1.5-4 (the small workload's budget)."""
+    g, torch = _lib()
+    grid = F.Grid(64, 64, 64)
+    params = S.random_params(2048, 64, seed=7, scale_range=(1.5, 4.0)).astype(np.float32)
+    params = params.astype(np.float64)
+    print("evaluate 64^3 x 2048", flush=True)
+    got, _ = _eval_gpu(g, torch, params, grid, 3.0, 8)
+    V, A, br = F.evaluate_windowed(params, grid, 3.0, band=BAND)
+    check_field(got, V, A, br)
+
+
+def test_forward_is_bitwise_reproducible_and_brick_invariant():
+    g, torch = _lib()
+    grid = F.Grid(40, 33, 27)
+    params = _case(80, grid, 3)
+    a, _ = _eval_gpu(g, torch, params, grid, 3.0, 8)
+    b, _ = _eval_gpu(g, torch, params, grid, 3.0, 8)
+    assert np.array_equal(a, b)
+    c, _ = _eval_gpu(g, torch, params, grid, 3.0, 16)
+    _, A = F.evaluate_windowed(params, grid, 3.0)
+    assert np.max(np.abs(a.astype(np.float64) - c) / (A + 1e-30)) < 2e-6
+
+
+def test_large_k_equals_untruncated_field():
+    g, torch = _lib()
+    grid = F.Grid(30, 30, 30)
+    params = _case(20, grid, 4, scale_range=(0.8, 2.0))
+    got, _ = _eval_gpu(g, torch, params, grid, 8.0, 8)
+    ref = F.evaluate_bruteforce(params, grid, None)
+    _, A = F.evaluate_windowed(params, grid, 8.0)
+    check_field(got, ref, A)
+
+
+def test_edge_cases():
+    g, torch = _lib()
+    # every primitive outside the grid: no pairs, zero field
+    grid = F.Grid(12, 12, 12)
+    p = _case(10, grid, 5, scale_range=(0.5, 1.0))
+    p[0] += 100.0
+    got, st = _eval_gpu(g, torch, p, grid, 3.0, 8)
+    assert st["n_overlaps"] == 0 and not np.any(got)
+    # a single voxel
+    grid1 = F.Grid(1, 1, 1, 5, 5, 5)
+    p1 = _case(4, F.Grid(3, 3, 3, 4, 4, 4), 6, scale_range=(0.7, 2.0))
+    got1, _ = _eval_gpu(g, torch, p1, grid1, 3.0, 8)
+    V1, A1 = F.evaluate_windowed(p1, grid1, 3.0)
+    check_field(got1, V1, A1)
+    # zero quaternion is the identity rotation
+    grid2 = F.Grid(9, 8, 17)
+    p2 = _case(6, grid2, 8)
+    p2[3:7, 0] = 0.0
+    got2, _ = _eval_gpu(g, torch, p2, grid2, 3.0, 16)
+    V2, A2, br = F.evaluate_windowed(p2, grid2, 3.0, band=BAND)
+    check_field(got2, V2, A2, br)
+
+
+# ----------------------------------------------------------------------------- gradient
+
+def _loss_grad_gpu(g, torch, params, field, grid, k, brick):
+    ctx = g.Context(k=k, brick=brick)
+    p = g.Params(ctx, params.shape[1]).upload(params.astype(np.float32))
+    f = torch.from_numpy(np.ascontiguousarray(field, dtype=np.float32)).cuda()
+    grad = torch.empty((11, params.shape[1]), device="cuda", dtype=torch.float32)
+    L = g.loss_grad(ctx, p, f, g.Grid(grid.nx, grid.ny, grid.nz, grid.x0, grid.y0, grid.z0), grad)
+    return L, grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("brick", [8, 16])
+@pytest.mark.parametrize("k", [3.0, 5.0])
+def test_loss_grad_matches_oracle(brick, k):
+    g, torch = _lib()
+    grid = F.Grid(30, 26, 22, 1, -3, 2)
+    params = _case(40, grid, 10, scale_range=(0.8, 3.5))
+    field = np.random.default_rng(11).uniform(-0.3, 1.0, size=grid.shape).astype(np.float32)
+    print(f"loss_grad k={k} B={brick}", flush=True)
+    L, grad = _loss_grad_gpu(g, torch, params, field, grid, k, brick)
+    Lr, gr = F.loss_grad(params, field.astype(np.float64), grid, k)
+    assert abs(L - Lr) <= 1e-5 * Lr
+    check_grad(grad, gr)
+
+
+def test_loss_grad_tiny_workload():
+    """64^3 signed-mixture target, 2,048 primitives, k = 3."""
+    g, torch = _lib()
+    field, _ = S.tiny_mixture(seed=0)
+    grid = F.Grid(64, 64, 64)
+    params = S.random_params(2048, 64, seed=12, scale_range=(1.5, 4.0), weight_range=(-0.2, 0.2))
+    params = params.astype(np.float32).astype(np.float64)
+    L, grad = _loss_grad_gpu(g, torch, params, field, grid, 3.0, 8)
+    Lr, gr = F.loss_grad(params, field.astype(np.float64), grid, 3.0)
+    assert abs(L - Lr) <= 1e-5 * Lr
+    check_grad(grad, gr)
+
+
+def test_adam_step_matches_oracle():
+    g, torch = _lib()
+    rng = np.random.default_rng(0)
+    n = 1000
+    theta = rng.normal(size=(11, n)).astype(np.float32)
+    ctx = g.Context(lr=3e-3, ell_min=-1.0, ell_max=1.5)
+    p = g.Params(ctx, n).upload(theta)
+    st = F.AdamState.zeros(n)
+    ref = theta.astype(np.float64)
+    for it in range(3):
+        gr = rng.normal(size=(11, n)).astype(np.float32)
+        g.adam_step(ctx, p, torch.from_numpy(gr).cuda())
+        ref, _ = F.adam_update(ref, gr.astype(np.float64), st, lr=3e-3, ell_clamp=(-1.0, 1.5))
+    got = p.download().astype(np.float64)
+    assert p.step == 3
+    assert np.max(np.abs(got - ref)) < 1e-6 * (1 + np.max(np.abs(ref)))
+
+
+def test_refine_trajectory_matches_oracle():
+    g, torch = _lib()
+    grid = F.Grid(24, 24, 24)
+    gen = S.random_params(12, 24, seed=21, scale_range=(1.5, 3.0))
+    field = S.mixture_field(gen, grid.shape).astype(np.float32)
+    start = gen.copy()
+    start[0:3] += np.random.default_rng(1).normal(0, 0.5, size=(3, 12))
+    start[10] *= 0.7
+    start = start.astype(np.float32).astype(np.float64)
+    ctx = g.Context(k=3.0, brick=8, lr=1e-2)
+    p = g.Params(ctx, 12).upload(start.astype(np.float32))
+    f = torch.from_numpy(field).cuda()
+    losses = g.refine(ctx, p, f, g.Grid(24, 24, 24), 20)
+    ref_p, _, ref_l = F.refine(start, field.astype(np.float64), grid, 3.0, 20, lr=1e-2)
+    rel = np.abs(losses - ref_l) / ref_l
+    assert np.max(rel) < 1e-3, rel
+    got = p.download().astype(np.float64)
+    assert np.max(np.abs(got - ref_p)) < 1e-3
+    assert p.step == 20 and losses[-1] < losses[0]
