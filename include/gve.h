@@ -159,6 +159,41 @@ gve_status gve_adam_step(gve_ctx* ctx, gve_params* p, const float* d_grad);
 gve_status gve_refine(gve_ctx* ctx, gve_params* p, const float* d_field, gve_grid g,
                       int32_t iters, double* h_loss_hist);
 
+/*
+ * Structure-aware fixed-budget allocation (Sec. III-E; stage table rows
+ * S1a-S1e).  d_field: device float32 [nz][ny][nx], expected in [0, 1] (the
+ * preprocessing of Sec. III-B; see gve_normalize).  Draws N_det =
+ * floor(0.55 budget + 1/2) detail seeds with probability proportional to
+ * |grad V| over the occupied domain V > 0.02 and N_cov = budget - N_det
+ * coverage seeds uniformly over it, each draw without replacement (distinct
+ * voxels), jitters them off the grid, sets per-group scales from the median
+ * nearest-neighbour spacing, orients each primitive along the smallest-
+ * eigenvalue axis of its 7^3 structure tensor (elongated with |grad V|,
+ * capped at max(dims)/16), and sets weights kappa V(c_i) with kappa the
+ * least-squares fit of the allocated field to V.  All steps run on the
+ * device; the draws are reproducible from `seed`.  On success *out is a new
+ * gve_params of exactly `budget` primitives (detail seeds first, each group in
+ * increasing voxel order).  If the field cannot host the budget (Sec. V-B:
+ * N_det > #eligible voxels or N_cov > #occupied voxels) returns
+ * GVE_ERR_BUDGET_INFEASIBLE, leaves *out untouched and reports the shortfall
+ * in info.  info may be NULL.  Synchronises.
+ */
+typedef struct gve_alloc_info {
+  int64_t n_detail, n_coverage;   /* requested split of the budget */
+  int64_t n_eligible, n_occupied; /* voxels with V > 0.02 and |grad V| > 0; with V > 0.02 */
+  int64_t shortfall;              /* > 0 only for GVE_ERR_BUDGET_INFEASIBLE */
+  double s_base_detail, s_base_coverage; /* group scales (voxels) */
+  double g99;                     /* 99th percentile of |grad V| over V > 0.02 */
+  double kappa;                   /* least-squares weight factor */
+} gve_alloc_info;
+
+gve_status gve_allocate(gve_ctx* ctx, const float* d_field, gve_grid g, int64_t budget,
+                        uint64_t seed, gve_params** out, gve_alloc_info* info);
+
+/* Min-max normalisation of a device float32 field of n values to [0, 1] in
+ * place (Sec. III-B).  A constant field becomes 0.  Asynchronous. */
+gve_status gve_normalize(gve_ctx* ctx, float* d_field, int64_t n);
+
 /* Counters of the last call (see gve_stats). */
 gve_status gve_get_stats(const gve_ctx* ctx, gve_stats* out);
 

@@ -84,9 +84,9 @@ def hash_bits(seed, stream, idx):
 
 
 def uniform01(seed, stream, idx):
-    """Uniform in (0, 1): (top 53 bits + 1/2) * 2^-53."""
-    b = hash_bits(seed, stream, idx) >> np.uint64(11)
-    return (b.astype(np.float64) + 0.5) * (2.0 ** -53)
+    """Uniform in (0, 1]: (top 53 bits + 1) * 2^-53, exact in float64."""
+    b = (hash_bits(seed, stream, idx) >> np.uint64(11)) + np.uint64(1)
+    return b.astype(np.float64) * (2.0 ** -53)
 
 
 # ----------------------------------------------------------------------------- S1a

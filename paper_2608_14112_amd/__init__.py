@@ -66,6 +66,14 @@ class StatsC(ctypes.Structure):
                 ("iterations", ctypes.c_int64), ("last_loss", ctypes.c_double)]
 
 
+class AllocInfoC(ctypes.Structure):
+    _fields_ = [("n_detail", ctypes.c_int64), ("n_coverage", ctypes.c_int64),
+                ("n_eligible", ctypes.c_int64), ("n_occupied", ctypes.c_int64),
+                ("shortfall", ctypes.c_int64), ("s_base_detail", ctypes.c_double),
+                ("s_base_coverage", ctypes.c_double), ("g99", ctypes.c_double),
+                ("kappa", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _SIGS = {
@@ -89,6 +97,9 @@ _SIGS = {
     "gve_adam_step": [_vp, _vp, _vp],
     "gve_refine": [_vp, _vp, _vp, GridC, ctypes.c_int32, _vp],
     "gve_get_stats": [_vp, ctypes.POINTER(StatsC)],
+    "gve_allocate": [_vp, _vp, GridC, _i64, ctypes.c_uint64, ctypes.POINTER(_vp),
+                     ctypes.POINTER(AllocInfoC)],
+    "gve_normalize": [_vp, _vp, _i64],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -196,9 +207,12 @@ class Context:
 class Params:
     """A fixed-budget primitive set: device [11][n] parameters plus Adam state."""
 
-    def __init__(self, ctx: Context, n: int):
+    def __init__(self, ctx: Context, n: int, _handle=None):
         self.ctx = ctx
         self.n = int(n)
+        if _handle is not None:
+            self.handle = _handle
+            return
         h = _vp()
         _check(_lib.gve_params_create(ctx.handle, _i64(self.n), ctypes.byref(h)), ctx.handle)
         self.handle = h
@@ -298,3 +312,36 @@ def refine(ctx: Context, params: Params, field, grid: Grid, iters: int, want_los
                            ctypes.c_int32(int(iters)),
                            hist.ctypes.data_as(_vp) if want_losses else None), ctx.handle)
     return hist[:iters] if want_losses else None
+
+
+class BudgetInfeasible(GveError):
+    def __init__(self, info, message):
+        super().__init__(BUDGET_INFEASIBLE, message)
+        self.info = info
+        self.shortfall = info["shortfall"]
+
+
+def allocate(ctx: Context, field, grid: Grid, budget: int, seed: int):
+    """gve_allocate: returns (Params, info dict); raises BudgetInfeasible (Sec. V-B)."""
+    import torch
+
+    n = grid.nx * grid.ny * grid.nz
+    h = _vp()
+    inf = AllocInfoC()
+    st = _lib.gve_allocate(ctx.handle, _ptr(field, torch.float32, n), grid.c(), _i64(int(budget)),
+                           ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), ctypes.byref(h),
+                           ctypes.byref(inf))
+    info = {f: getattr(inf, f) for f, _ in AllocInfoC._fields_}
+    if st == BUDGET_INFEASIBLE:
+        raise BudgetInfeasible(info, _lib.gve_last_error(ctx.handle).decode())
+    _check(st, ctx.handle)
+    return Params(ctx, int(budget), _handle=h), info
+
+
+def normalize(ctx: Context, field):
+    """gve_normalize: min-max normalise a float32 cuda tensor to [0, 1] in place."""
+    import torch
+
+    _check(_lib.gve_normalize(ctx.handle, _ptr(field, torch.float32), _i64(field.numel())),
+           ctx.handle)
+    return field

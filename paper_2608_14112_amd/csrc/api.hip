@@ -275,7 +275,7 @@ gve_status gve_destroy(gve_ctx* ctx) {
   auto& ws = ctx->ws;
   Scratch* all[] = {&ws.keys[0], &ws.keys[1], &ws.vals[0], &ws.vals[1], &ws.brick_start,
                     &ws.brick_loss, &ws.scan_tmp, &ws.sort_hist, &ws.dloss, &ws.clamp_count,
-                    &ws.grad_tmp};
+                    &ws.grad_tmp, &ws.alloc, &ws.voxf};
   for (Scratch* s : all)
     if (s->ptr) hipFree(s->ptr);
   if (ws.h_pinned) hipHostFree(ws.h_pinned);
@@ -488,6 +488,140 @@ gve_status gve_refine(gve_ctx* ctx, gve_params* p, const float* d_field, gve_gri
         if (!std::isfinite(h_loss_hist[it])) return fail(ctx, GVE_ERR_NUMERIC, "loss is not finite");
     }
   }
+  return GVE_OK;
+}
+
+gve_status gve_normalize(gve_ctx* ctx, float* d_field, int64_t n) {
+  if (!ctx) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  if (!d_field || n <= 0) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "need a field of n > 0 values");
+  TRY(set_device(ctx));
+  TRY(ensure(ctx, ctx->ws.alloc, sizeof(float) * gve::normalize_tmp_floats()));
+  TRY_HIP(ctx, gve::normalize_field(d_field, n, static_cast<float*>(ctx->ws.alloc.ptr),
+                                    ctx->stream));
+  return GVE_OK;
+}
+
+gve_status gve_allocate(gve_ctx* ctx, const float* d_field, gve_grid g, int64_t budget,
+                        uint64_t seed, gve_params** out, gve_alloc_info* info) {
+  if (!ctx) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  if (!d_field || !out) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "d_field and out are required");
+  if (budget < 1 || budget >= ((int64_t)1 << 31))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "budget must be in [1, 2^31)");
+  TRY(validate_grid(ctx, g));
+  TRY(set_device(ctx));
+  hipStream_t s = ctx->stream;
+  const int64_t M = g.nx * g.ny * g.nz;
+  const int64_t nb = (int64_t)gve::alloc_block_count(M);
+  const int64_t n_det = (int64_t)std::floor(0.55 * (double)budget + 0.5);
+  const int64_t n_cov = budget - n_det;
+  // carve the allocation scratch
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t o_counts = take(16), o_st = take(48), o_hist = take(256 * 8), o_sb = take(16),
+               o_best = take(4096 * 8), o_dot = take(sizeof(double) * gve::alloc_dot_tmp_doubles()),
+               o_less = take(4 * (nb + 1)), o_tie = take(4 * (nb + 1)), o_toff = take(4 * (nb + 1)),
+               o_take = take(4 * (nb + 1)), o_ooff = take(4 * (nb + 1)), o_det = take(8 * n_det),
+               o_cov = take(8 * n_cov);
+  TRY(ensure(ctx, ctx->ws.alloc, off));
+  TRY(ensure(ctx, ctx->ws.voxf, sizeof(float) * (size_t)M));
+  TRY(ensure(ctx, ctx->ws.scan_tmp, gve::scan_tmp_bytes(nb + 1)));
+  char* base = static_cast<char*>(ctx->ws.alloc.ptr);
+  auto U64 = [&](size_t o) { return reinterpret_cast<unsigned long long*>(base + o); };
+  auto U32 = [&](size_t o) { return reinterpret_cast<uint32_t*>(base + o); };
+  auto I64 = [&](size_t o) { return reinterpret_cast<int64_t*>(base + o); };
+  auto F64 = [&](size_t o) { return reinterpret_cast<double*>(base + o); };
+  float* g32 = static_cast<float*>(ctx->ws.voxf.ptr);
+
+  // S1a: gradient magnitude and domain counts; feasibility (Sec. V-B)
+  TRY_HIP(ctx, gve::fill_u64(U64(o_counts), 2, s));
+  TRY_HIP(ctx, gve::fill_u64(U64(o_hist), 256, s));
+  TRY_HIP(ctx, gve::alloc_grad(d_field, g, g32, U64(o_counts), s));
+  TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, U64(o_counts), 16, hipMemcpyDeviceToHost, s));
+  TRY_HIP(ctx, hipStreamSynchronize(s));
+  const int64_t n_occ = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[0];
+  const int64_t n_el = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[1];
+  gve_alloc_info inf{};
+  inf.n_detail = n_det;
+  inf.n_coverage = n_cov;
+  inf.n_eligible = n_el;
+  inf.n_occupied = n_occ;
+  int64_t shortfall = n_det - n_el;
+  if (n_cov - n_occ > shortfall) shortfall = n_cov - n_occ;
+  if (shortfall > 0) {
+    inf.shortfall = shortfall;
+    if (info) *info = inf;
+    return fail(ctx, GVE_ERR_BUDGET_INFEASIBLE,
+                "budget needs " + std::to_string(shortfall) + " more distinct seed voxels");
+  }
+  // S1b: the two draws and the 99th percentile of |grad V| over V > 0.02
+  unsigned long long* st_det = U64(o_st);
+  unsigned long long* st_cov = st_det + 2;
+  unsigned long long* st_g99 = st_det + 4;
+  const int64_t r99 = (int64_t)std::floor(0.99 * (double)(n_occ - 1));
+  TRY_HIP(ctx, gve::alloc_set_state(st_det, 0ull, (unsigned long long)n_det, s));
+  TRY_HIP(ctx, gve::alloc_set_state(st_cov, 0ull, (unsigned long long)n_cov, s));
+  TRY_HIP(ctx, gve::alloc_set_state(st_g99, 0ull, (unsigned long long)(r99 + 1), s));
+  int64_t* det = I64(o_det);
+  int64_t* cov = I64(o_cov);
+  TRY_HIP(ctx, gve::alloc_select(0, d_field, g32, g, seed, st_det, U64(o_hist), U32(o_less),
+                                 U32(o_tie), U32(o_toff), U32(o_take), U32(o_ooff),
+                                 ctx->ws.scan_tmp.ptr, det, s));
+  TRY_HIP(ctx, gve::alloc_select(1, d_field, g32, g, seed, st_cov, U64(o_hist), U32(o_less),
+                                 U32(o_tie), U32(o_toff), U32(o_take), U32(o_ooff),
+                                 ctx->ws.scan_tmp.ptr, cov, s));
+  TRY_HIP(ctx, gve::alloc_select(2, d_field, g32, g, seed, st_g99, U64(o_hist), nullptr, nullptr,
+                                 nullptr, nullptr, nullptr, nullptr, nullptr, s));
+  gve_params* p = nullptr;
+  TRY(gve_params_create(ctx, budget, &p));
+  auto cleanup = [&](gve_status st) {
+    gve_params_destroy(p);
+    return st;
+  };
+  gve_status st = GVE_OK;
+#define TRY_A(call)                                                        \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess) return cleanup(from_hip(ctx, e_, #call));        \
+  } while (0)
+  TRY_A(gve::alloc_jitter(g, det, cov, n_det, budget, seed, p->theta, s));
+  // S1c: group spacing
+  double* sb = F64(o_sb);
+  TRY_A(gve::alloc_spacing(p->theta, budget, 0, n_det, F64(o_best), sb, s));
+  TRY_A(gve::alloc_spacing(p->theta, budget, n_det, n_cov, F64(o_best), sb + 1, s));
+  // S1d/S1e: frames, scales, values
+  TRY_A(gve::alloc_assemble(d_field, g32, g, det, cov, n_det, budget, sb, st_g99, seed, p->theta,
+                            s));
+  // weights: U = sum a_i G_i on the grid (g32's buffer is free now), kappa
+  Binned bn;
+  st = bin(ctx, p, g, &bn);
+  if (st != GVE_OK) return cleanup(st);
+  TRY_A(gve::launch_forward(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, g32, s));
+  TRY_A(gve::alloc_weights(g32, d_field, M, p->theta + 10 * budget, budget, F64(o_dot), s));
+#undef TRY_A
+  // report
+  double* hp = static_cast<double*>(ctx->ws.h_pinned);
+  hipError_t e = hipMemcpyAsync(hp, sb, 16, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp + 2, F64(o_dot), 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp + 3, st_g99, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cleanup(from_hip(ctx, e, "gve_allocate readback"));
+  inf.s_base_detail = hp[0];
+  inf.s_base_coverage = hp[1];
+  inf.kappa = hp[2];
+  unsigned long long gb;
+  std::memcpy(&gb, hp + 3, 8);
+  float g99f;
+  const uint32_t gb32 = (uint32_t)gb;
+  std::memcpy(&g99f, &gb32, 4);
+  inf.g99 = g99f;
+  if (info) *info = inf;
+  *out = p;
   return GVE_OK;
 }
 

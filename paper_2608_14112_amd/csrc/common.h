@@ -46,7 +46,9 @@ struct Workspace {
   Scratch sort_hist;             // radix sort histograms
   Scratch dloss;                 // double [4]
   Scratch clamp_count;           // unsigned long long
-  Scratch grad_tmp;              // float [11][n] for loss_grad without caller buffer
+  Scratch grad_tmp;              // per-iteration loss history of gve_refine
+  Scratch alloc;                 // allocation scratch (block counts, indices, states)
+  Scratch voxf;                  // float [M] gradient magnitude, then U
   void* h_pinned = nullptr;      // pinned host staging (64 bytes)
 };
 
@@ -123,6 +125,31 @@ hipError_t launch_loss_reduce(const float* brick_loss, int64_t nbricks, double* 
 // Small utility kernels.
 hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
+
+// ---- allocation (alloc.hip) --------------------------------------------------
+size_t alloc_block_count(int64_t M);
+hipError_t alloc_grad(const float* f, const gve_grid& g, float* g32, unsigned long long* counts,
+                      hipStream_t s);
+hipError_t alloc_set_state(unsigned long long* st, unsigned long long prefix,
+                           unsigned long long rank, hipStream_t s);
+hipError_t alloc_select(int mode, const float* f, const float* g32, const gve_grid& g,
+                        uint64_t seed, unsigned long long* st, unsigned long long* hist,
+                        uint32_t* less_cnt, uint32_t* tie_cnt, uint32_t* tie_off,
+                        uint32_t* take_cnt, uint32_t* out_off, void* scan_tmp, int64_t* out,
+                        hipStream_t s);
+hipError_t alloc_jitter(const gve_grid& g, const int64_t* det, const int64_t* cov, int64_t n_det,
+                        int64_t n, uint64_t seed, float* theta, hipStream_t s);
+hipError_t alloc_spacing(const float* theta, int64_t n, int64_t first, int64_t ng, double* best,
+                         double* s_base, hipStream_t s);
+hipError_t alloc_assemble(const float* f, const float* g32, const gve_grid& g, const int64_t* det,
+                          const int64_t* cov, int64_t n_det, int64_t n, const double* s_base,
+                          const unsigned long long* g99_state, uint64_t seed, float* theta,
+                          hipStream_t s);
+size_t alloc_dot_tmp_doubles();
+hipError_t alloc_weights(const float* U, const float* f, int64_t M, float* c_row, int64_t n,
+                         double* tmp, hipStream_t s);
+size_t normalize_tmp_floats();
+hipError_t normalize_field(float* f, int64_t M, float* tmp, hipStream_t s);
 
 // mode 0: chain rule -> grad_out ([11][n]); mode 1: chain rule + Adam;
 // mode 2: Adam from grad_in.  Zeroes acc in modes 0 and 1.
