@@ -84,6 +84,12 @@ typedef struct gve_stats {
   int64_t n_clamped;      /* log-scale entries clamped so far (cumulative) */
   int64_t iterations;     /* Adam steps taken on the last refined params */
   double last_loss;       /* L = sum (Vhat - V)^2 of the last loss evaluation */
+  /* Stage timers of the last gve_refine call (HIP events on the context's
+   * stream; filled only while timing is enabled, see gve_set_timing). */
+  int64_t timed_iterations;
+  double ms_bin;          /* prep + scan + emit + sort + ranges */
+  double ms_fused;        /* fused forward + squared error + backward kernel */
+  double ms_update;       /* loss reduction + chain rule + Adam */
 } gve_stats;
 
 typedef struct gve_ctx gve_ctx;
@@ -193,6 +199,21 @@ gve_status gve_allocate(gve_ctx* ctx, const float* d_field, gve_grid g, int64_t 
 /* Min-max normalisation of a device float32 field of n values to [0, 1] in
  * place (Sec. III-B).  A constant field becomes 0.  Asynchronous. */
 gve_status gve_normalize(gve_ctx* ctx, float* d_field, int64_t n);
+
+/* Enable (1) or disable (0) the per-stage HIP-event timers of gve_refine.
+ * Timing records events between the stages of every iteration; it does not
+ * add synchronisation (the elapsed times are read at the end of the call). */
+gve_status gve_set_timing(gve_ctx* ctx, int32_t enable);
+
+/*
+ * Work counters of one truncated evaluation on grid g (Sec. III-G measures the
+ * same quantity: the fraction of candidate pairs that contribute).
+ * *h_in_support = number of (primitive, voxel) pairs with m^2 < k^2 inside the
+ * grid; *h_candidates = lane-voxel evaluations the brick kernels perform.
+ * Synchronises.
+ */
+gve_status gve_count_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, int64_t* h_in_support,
+                           int64_t* h_candidates);
 
 /* Counters of the last call (see gve_stats). */
 gve_status gve_get_stats(const gve_ctx* ctx, gve_stats* out);

@@ -4,7 +4,7 @@ Argument marshalling only: every step of evaluation, binning, loss, gradient
 and Adam runs in the HIP kernels of libgve.so (declared in include/gve.h).
 torch tensors supply device memory and the HIP stream; they are passed to the
 library as raw pointers.  Importing this module fails loudly if the library
-has not been built (``python -m paper_2608_14112_amd.build``).
+has not been built (``python paper_2608_14112_amd/build.py``).
 
 Names follow the C ABI without the ``gve_`` prefix:
 
@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(_HERE, "libgve.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it with `python -m paper_2608_14112_amd.build` "
+        f"{LIB_PATH} is missing: build it with `python paper_2608_14112_amd/build.py` "
         "(there is no fallback implementation)")
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -63,7 +63,9 @@ class OptionsC(ctypes.Structure):
 class StatsC(ctypes.Structure):
     _fields_ = [("n_primitives", ctypes.c_int64), ("n_bricks", ctypes.c_int64),
                 ("n_overlaps", ctypes.c_int64), ("n_clamped", ctypes.c_int64),
-                ("iterations", ctypes.c_int64), ("last_loss", ctypes.c_double)]
+                ("iterations", ctypes.c_int64), ("last_loss", ctypes.c_double),
+                ("timed_iterations", ctypes.c_int64), ("ms_bin", ctypes.c_double),
+                ("ms_fused", ctypes.c_double), ("ms_update", ctypes.c_double)]
 
 
 class AllocInfoC(ctypes.Structure):
@@ -100,6 +102,8 @@ _SIGS = {
     "gve_allocate": [_vp, _vp, GridC, _i64, ctypes.c_uint64, ctypes.POINTER(_vp),
                      ctypes.POINTER(AllocInfoC)],
     "gve_normalize": [_vp, _vp, _i64],
+    "gve_set_timing": [_vp, ctypes.c_int32],
+    "gve_count_pairs": [_vp, _vp, GridC, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -191,6 +195,9 @@ class Context:
         s = StatsC()
         _check(_lib.gve_get_stats(self.handle, ctypes.byref(s)), self.handle)
         return {f: getattr(s, f) for f, _ in StatsC._fields_}
+
+    def set_timing(self, enable=True):
+        _check(_lib.gve_set_timing(self.handle, 1 if enable else 0), self.handle)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -345,3 +352,11 @@ def normalize(ctx: Context, field):
     _check(_lib.gve_normalize(ctx.handle, _ptr(field, torch.float32), _i64(field.numel())),
            ctx.handle)
     return field
+
+
+def count_pairs(ctx: Context, params: Params, grid: Grid):
+    """gve_count_pairs: (in-support pairs, candidate lane-voxel evaluations)."""
+    a, b = _i64(), _i64()
+    _check(_lib.gve_count_pairs(ctx.handle, params.handle, grid.c(), ctypes.byref(a),
+                                ctypes.byref(b)), ctx.handle)
+    return a.value, b.value

@@ -1,10 +1,11 @@
 """Build libgve.so (the HIP/gfx950 library behind include/gve.h) in-tree.
 
-    python -m paper_2608_14112_amd.build
+    python paper_2608_14112_amd/build.py
 
 Each csrc/*.hip file is compiled for gfx950 with hipcc into _build/, then
-linked into paper_2608_14112_amd/libgve.so.  Packed FP32 instructions are
-disabled for device code ("Build").
+linked into paper_2608_14112_amd/libgve.so.  Device code is built without
+packed FP32 instructions (the compiler would otherwise form v_pk_* float ops
+from ordinary scalar code) and with hardware float atomics.
 """
 from __future__ import annotations
 

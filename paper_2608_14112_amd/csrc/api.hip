@@ -279,6 +279,7 @@ gve_status gve_destroy(gve_ctx* ctx) {
   for (Scratch* s : all)
     if (s->ptr) hipFree(s->ptr);
   if (ws.h_pinned) hipHostFree(ws.h_pinned);
+  for (hipEvent_t e : ctx->events) hipEventDestroy(e);
   delete ctx;
   return GVE_OK;
 }
@@ -453,6 +454,31 @@ gve_status gve_adam_step(gve_ctx* ctx, gve_params* p, const float* d_grad) {
   return GVE_OK;
 }
 
+gve_status gve_set_timing(gve_ctx* ctx, int32_t enable) {
+  if (!ctx) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->timing = enable != 0;
+  return GVE_OK;
+}
+
+gve_status gve_count_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, int64_t* h_in_support,
+                           int64_t* h_candidates) {
+  TRY(check_ctx_params(ctx, p));
+  if (!h_in_support || !h_candidates)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "output pointers are required");
+  TRY(validate_grid(ctx, g));
+  TRY(set_device(ctx));
+  Binned bn;
+  TRY(bin(ctx, p, g, &bn));
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ctx->ws.dloss.ptr) + 4;
+  TRY_HIP(ctx, gve::fill_u64(cnt, 2, ctx->stream));
+  TRY_HIP(ctx, gve::launch_count(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, cnt, ctx->stream));
+  TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, cnt, 16, hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *h_in_support = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[0];
+  *h_candidates = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[1];
+  return GVE_OK;
+}
+
 gve_status gve_refine(gve_ctx* ctx, gve_params* p, const float* d_field, gve_grid g,
                       int32_t iters, double* h_loss_hist) {
   TRY(check_ctx_params(ctx, p));
@@ -464,13 +490,50 @@ gve_status gve_refine(gve_ctx* ctx, gve_params* p, const float* d_field, gve_gri
   TRY(ensure(ctx, ctx->ws.grad_tmp, sizeof(double) * (size_t)(iters > 0 ? iters : 1)));
   double* hist = static_cast<double*>(ctx->ws.grad_tmp.ptr);
   TRY_HIP(ctx, gve::fill_f32(p->acc, 10 * p->n, 0.0f, ctx->stream));
+  const bool timing = ctx->timing && iters > 0;
+  if (timing) {
+    while ((int64_t)ctx->events.size() < 4 * (int64_t)iters) {
+      hipEvent_t e;
+      TRY_HIP(ctx, hipEventCreate(&e));
+      ctx->events.push_back(e);
+    }
+  }
+  hipStream_t s = ctx->stream;
   for (int32_t it = 0; it < iters; ++it) {
-    TRY(loss_and_sums(ctx, p, d_field, g, hist + it));
+    hipEvent_t* ev = timing ? &ctx->events[4 * (size_t)it] : nullptr;
+    if (timing) TRY_HIP(ctx, hipEventRecord(ev[0], s));
+    Binned bn;
+    TRY(bin(ctx, p, g, &bn));
+    TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)bn.bg.nbricks));
+    float* bl = static_cast<float*>(ctx->ws.brick_loss.ptr);
+    if (timing) TRY_HIP(ctx, hipEventRecord(ev[1], s));
+    TRY_HIP(ctx, gve::launch_fused(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, d_field,
+                                   p->acc, p->n, bl, s));
+    if (timing) TRY_HIP(ctx, hipEventRecord(ev[2], s));
+    double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
+    TRY_HIP(ctx, gve::launch_loss_reduce(bl, bn.bg.nbricks, dl + 16, hist + it, s));
     p->t += 1;
     TRY_HIP(ctx, gve::launch_update(1, p->theta, p->m, p->v, p->acc, nullptr, nullptr, p->n, p->t,
-                                    ctx->opt, clamp_counter(ctx), ctx->stream));
+                                    ctx->opt, clamp_counter(ctx), s));
+    if (timing) TRY_HIP(ctx, hipEventRecord(ev[3], s));
   }
   ctx->stats.iterations = p->t;
+  if (timing) {
+    TRY_HIP(ctx, hipStreamSynchronize(s));
+    double tb = 0, tf = 0, tu = 0;
+    for (int32_t it = 0; it < iters; ++it) {
+      hipEvent_t* ev = &ctx->events[4 * (size_t)it];
+      float a = 0, b = 0, c = 0;
+      TRY_HIP(ctx, hipEventElapsedTime(&a, ev[0], ev[1]));
+      TRY_HIP(ctx, hipEventElapsedTime(&b, ev[1], ev[2]));
+      TRY_HIP(ctx, hipEventElapsedTime(&c, ev[2], ev[3]));
+      tb += a; tf += b; tu += c;
+    }
+    ctx->stats.timed_iterations = iters;
+    ctx->stats.ms_bin = tb;
+    ctx->stats.ms_fused = tf;
+    ctx->stats.ms_update = tu;
+  }
   if (iters > 0) {
     TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, clamp_counter(ctx), sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, ctx->stream));

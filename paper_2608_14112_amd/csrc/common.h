@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "gve.h"
 
@@ -61,6 +62,8 @@ struct gve_ctx {
   gve::Workspace ws;
   gve_stats stats{};
   std::string last_error;
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // stage-timer pool, 4 per refinement iteration
 };
 
 struct gve_params {
@@ -116,6 +119,9 @@ hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid,
 hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid,
                         const uint32_t* brick_start, gve_grid g, BrickGeom bg, float k,
                         const float* field, float* acc, int64_t n, float* brick_loss,
+                        hipStream_t s);
+hipError_t launch_count(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
+                        gve_grid g, BrickGeom bg, float k, unsigned long long* counts,
                         hipStream_t s);
 // Sum of brick_loss in double into *out; part holds loss_reduce_tmp_doubles().
 size_t loss_reduce_tmp_doubles();

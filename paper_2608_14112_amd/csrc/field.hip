@@ -33,8 +33,64 @@ __device__ inline float wave_sum(float v) {
   return v;
 }
 
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// ---- cross-lane reduction of ten values (gfx950 lane permutes + DPP) ---------
+//
+// v_permlane32_swap exchanges the upper half-wave of one register with the
+// lower half-wave of another, v_permlane16_swap the odd rows (16 lanes) of one
+// with the even rows of another, so pairs of registers are folded without LDS:
+//   5 half-wave folds (10 -> 5 registers), 3 row folds (5 -> 3 registers),
+//   then a 16-lane DPP butterfly (quad_perm 1032, quad_perm 2301, row half
+//   mirror, row mirror) leaves every lane of a row holding that row's sum.
+// Result: out[0] rows (0, 1, 2, 3) = sums of (v0, v1, v5, v6); out[1] =
+// (v2, v3, v7, v8); out[2] = (v4, v4, v9, v9).
+__device__ inline float row_sum16(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+  return v;
+}
+
+__device__ inline float fold32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ inline float fold16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ inline void wave_reduce10(const float (&v)[10], float (&out)[3]) {
+  const float w0 = fold32(v[0], v[5]), w1 = fold32(v[1], v[6]), w2 = fold32(v[2], v[7]),
+              w3 = fold32(v[3], v[8]), w4 = fold32(v[4], v[9]);
+  out[0] = row_sum16(fold16(w0, w1));
+  out[1] = row_sum16(fold16(w2, w3));
+  out[2] = row_sum16(fold16(w4, w4));
+}
+
+// Which of the ten sums row r of out[k] holds (-1: duplicate).
+__device__ inline int reduce10_slot(int k, int row) {
+  const int m0[4] = {0, 1, 5, 6}, m1[4] = {2, 3, 7, 8}, m2[4] = {4, -1, 9, -1};
+  return k == 0 ? m0[row] : (k == 1 ? m1[row] : m2[row]);
+}
+
+// ---- per (primitive, column) setup -------------------------------------------
+//
+// With t0 = (z0 - mu_z) - (gx dx + gy dy) the column coordinate at the brick's
+// first z, Q at brick offset zz is qxy + (a_zz t) t with t = t0 + zz.  Both
+// terms are <= 0, so the sum never cancels (an expansion in powers of zz about
+// the brick's first voxel would, when the vertex is far from it).
 struct ColumnSetup {
-  float qxy, t, ofs;
+  float qxy, t0;
   int za, zb;
 };
 
@@ -46,30 +102,43 @@ __device__ inline ColumnSetup column_setup(const Record& r, float px, float py, 
   const float dx = px - r.mu[0];
   const float dy = py - r.mu[1];
   s.qxy = (r.s[0] * dx + 2.0f * r.s[1] * dy) * dx + r.s[2] * dy * dy;
-  s.ofs = r.gx * dx + r.gy * dy;
-  s.t = (pz0 + (float)s.za - r.mu[2]) - s.ofs;
+  const float ofs = r.gx * dx + r.gy * dy;
+  s.t0 = (pz0 - r.mu[2]) - ofs;
   return s;
+}
+
+__device__ inline float quad_at(const ColumnSetup& s, float azz, float t) {
+  return fmaf(azz * t, t, s.qxy);
 }
 
 __device__ inline Record load_record(const Record* __restrict__ rec, uint32_t gid) {
   return rec[gid];
 }
 
+// True if any lane's column meets the support (the vertex of the parabola is
+// the column's largest Q); otherwise the whole (primitive, brick) is skipped.
+__device__ inline bool column_hit(const ColumnSetup& s, bool col_in, float thr) {
+  return __builtin_amdgcn_ballot_w64(col_in && s.qxy > thr) != 0ull;
+}
+
 template <int B>
 __device__ inline void accumulate_brick(const Record* __restrict__ rec,
                                         const uint32_t* __restrict__ pair_gid, uint32_t j0,
                                         uint32_t j1, float px, float py, float pz0, int iz0,
-                                        float thr, float (&acc)[B]) {
+                                        bool col_in, float thr, float (&acc)[B]) {
   for (uint32_t j = j0; j < j1; ++j) {
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
-    ColumnSetup s = column_setup<B>(r, px, py, pz0, iz0);
+    const ColumnSetup s = column_setup<B>(r, px, py, pz0, iz0);
+    if (!column_hit(s, col_in, thr)) continue;
 #pragma unroll
     for (int zz = 0; zz < B; ++zz) {
       if (zz >= s.za && zz <= s.zb) {
-        const float q = fmaf(r.azz * s.t, s.t, s.qxy);
-        if (q > thr) acc[zz] += r.c * __builtin_amdgcn_exp2f(q);
-        s.t += 1.0f;
+        const float q = quad_at(s, r.azz, s.t0 + (float)zz);
+        if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
+          const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
+          acc[zz] = fmaf(r.c, G, acc[zz]);
+        }
       }
     }
   }
@@ -89,12 +158,13 @@ __global__ __launch_bounds__(B* B) void k_forward(const Record* __restrict__ rec
   const int iy = by * B + (int)(threadIdx.x / B);
   const int iz0 = bz * B;
   const float px = (float)(g.x0 + ix), py = (float)(g.y0 + iy), pz0 = (float)(g.z0 + iz0);
+  const bool col_in = ix < g.nx && iy < g.ny;
   float acc[B];
 #pragma unroll
   for (int zz = 0; zz < B; ++zz) acc[zz] = 0.0f;
-  accumulate_brick<B>(rec, pair_gid, brick_start[b], brick_start[b + 1], px, py, pz0, iz0, thr,
-                      acc);
-  if (ix < g.nx && iy < g.ny) {
+  accumulate_brick<B>(rec, pair_gid, brick_start[b], brick_start[b + 1], px, py, pz0, iz0, col_in,
+                      thr, acc);
+  if (col_in) {
     const size_t plane = (size_t)g.nx * (size_t)g.ny;
     const size_t base = (size_t)ix + (size_t)g.nx * (size_t)iy;
 #pragma unroll
@@ -122,17 +192,18 @@ __global__ __launch_bounds__(B* B) void k_fused(const Record* __restrict__ rec,
   const int iz0 = bz * B;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  const int row = lane >> 4;
   const float px = (float)(g.x0 + ix), py = (float)(g.y0 + iy), pz0 = (float)(g.z0 + iz0);
+  const bool col_in = (ix < g.nx) && (iy < g.ny);
   const uint32_t j0 = brick_start[b], j1 = brick_start[b + 1];
 
   float res[B];
 #pragma unroll
   for (int zz = 0; zz < B; ++zz) res[zz] = 0.0f;
-  accumulate_brick<B>(rec, pair_gid, j0, j1, px, py, pz0, iz0, thr, res);
+  accumulate_brick<B>(rec, pair_gid, j0, j1, px, py, pz0, iz0, col_in, thr, res);
 
   // residual and this brick's share of the loss
   float lsum = 0.0f;
-  const bool col_in = (ix < g.nx) && (iy < g.ny);
   const size_t plane = (size_t)g.nx * (size_t)g.ny;
   const size_t base = (size_t)ix + (size_t)g.nx * (size_t)iy;
 #pragma unroll
@@ -140,7 +211,7 @@ __global__ __launch_bounds__(B* B) void k_fused(const Record* __restrict__ rec,
     float r = 0.0f;
     if (col_in && iz0 + zz < g.nz) {
       const float d = res[zz] - field[base + plane * (size_t)(iz0 + zz)];
-      lsum += d * d;
+      lsum = fmaf(d, d, lsum);
       r = 2.0f * d;
     }
     res[zz] = r;
@@ -158,62 +229,112 @@ __global__ __launch_bounds__(B* B) void k_fused(const Record* __restrict__ rec,
   for (uint32_t j = j0; j < j1; ++j) {
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
-    ColumnSetup s = column_setup<B>(r, px, py, pz0, iz0);
-    float se = 0.0f, st = 0.0f, stt = 0.0f;
-#pragma unroll
-    for (int zz = 0; zz < B; ++zz) {
-      if (zz >= s.za && zz <= s.zb) {
-        const float q = fmaf(r.azz * s.t, s.t, s.qxy);
-        const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
-        const float e = res[zz] * G;
-        se += e;
-        const float et = e * s.t;
-        st += et;
-        stt = fmaf(et, s.t, stt);
-        s.t += 1.0f;
-      }
-    }
-    const float dx = px - r.mu[0];
-    const float dy = py - r.mu[1];
-    // sum e dz = st + ofs se;  sum e dz^2 = stt + 2 ofs st + ofs^2 se
-    const float s1 = fmaf(s.ofs, se, st);
-    const float s2 = fmaf(s.ofs, fmaf(s.ofs, se, 2.0f * st), stt);
-    const float cse = r.c * se, cs1 = r.c * s1;
+    const ColumnSetup s = column_setup<B>(r, px, py, pz0, iz0);
+    const bool hit = column_hit(s, col_in, thr);
+    if (kWaves == 1 && !hit) continue;
     float v[10];
-    v[0] = se;
-    v[1] = dx * cse;
-    v[2] = dy * cse;
-    v[3] = cs1;
-    v[4] = dx * dx * cse;
-    v[5] = dx * dy * cse;
-    v[6] = dx * cs1;
-    v[7] = dy * dy * cse;
-    v[8] = dy * cs1;
-    v[9] = r.c * s2;
+    {
+      float se = 0.0f, st = 0.0f, stt = 0.0f;
+      if (hit) {
 #pragma unroll
-    for (int a = 0; a < 10; ++a) v[a] = wave_sum(v[a]);
+        for (int zz = 0; zz < B; ++zz) {
+          if (zz >= s.za && zz <= s.zb) {
+            const float t = s.t0 + (float)zz;
+            const float q = quad_at(s, r.azz, t);
+            if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
+              const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
+              const float e = res[zz] * G;
+              se += e;
+              const float et = e * t;
+              st += et;
+              stt = fmaf(et, t, stt);
+            }
+          }
+        }
+      }
+      // back to d = p - mu: sum e dz = st + ofs se, sum e dz^2 = stt + 2 ofs st + ofs^2 se
+      const float dx = px - r.mu[0];
+      const float dy = py - r.mu[1];
+      const float ofs = (pz0 - r.mu[2]) - s.t0;
+      const float s1 = fmaf(ofs, se, st);
+      const float s2 = fmaf(ofs, fmaf(ofs, se, 2.0f * st), stt);
+      const float cse = r.c * se, cs1 = r.c * s1;
+      v[0] = se;
+      v[1] = dx * cse;
+      v[2] = dy * cse;
+      v[3] = cs1;
+      v[4] = dx * dx * cse;
+      v[5] = dx * dy * cse;
+      v[6] = dx * cs1;
+      v[7] = dy * dy * cse;
+      v[8] = dy * cs1;
+      v[9] = r.c * s2;
+    }
+    float o[3];
+    wave_reduce10(v, o);
     if (kWaves == 1) {
-      if (lane < 10) {
-        float mine = v[0];
+      if ((lane & 15) == 0) {
 #pragma unroll
-        for (int a = 1; a < 10; ++a) mine = (lane == a) ? v[a] : mine;
-        unsafeAtomicAdd(&gacc[(int64_t)lane * n + gid], mine);
+        for (int k = 0; k < 3; ++k) {
+          const int slot = reduce10_slot(k, row);
+          if (slot >= 0) unsafeAtomicAdd(&gacc[(int64_t)slot * n + gid], o[k]);
+        }
       }
     } else {
-      if (lane < 10) {
-        float mine = v[0];
+      if ((lane & 15) == 0) {
 #pragma unroll
-        for (int a = 1; a < 10; ++a) mine = (lane == a) ? v[a] : mine;
-        red[wave][lane] = mine;
+        for (int k = 0; k < 3; ++k) {
+          const int slot = reduce10_slot(k, row);
+          if (slot >= 0) red[wave][slot] = o[k];
+        }
       }
       __syncthreads();
       if (threadIdx.x < 10) {
         float t = 0.0f;
         for (int w = 0; w < kWaves; ++w) t += red[w][threadIdx.x];
-        unsafeAtomicAdd(&gacc[(int64_t)threadIdx.x * n + gid], t);
+        if (t != 0.0f) unsafeAtomicAdd(&gacc[(int64_t)threadIdx.x * n + gid], t);
       }
       __syncthreads();
     }
+  }
+}
+
+// Work counters of one evaluation: [0] in-support (primitive, voxel) pairs
+// inside the grid (m^2 < k^2), [1] lane-voxel evaluations the brick kernels
+// perform after their wave-level skips (the candidate pairs, masked lanes
+// included).
+template <int B>
+__global__ __launch_bounds__(B* B) void k_count(const Record* __restrict__ rec,
+                                                const uint32_t* __restrict__ pair_gid,
+                                                const uint32_t* __restrict__ brick_start,
+                                                gve_grid g, BrickGeom bg, float thr,
+                                                unsigned long long* __restrict__ counts) {
+  const int64_t b = blockIdx.x;
+  const int bx = (int)(b % bg.nbx);
+  const int by = (int)((b / bg.nbx) % bg.nby);
+  const int bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
+  const int ix = bx * B + (int)(threadIdx.x % B);
+  const int iy = by * B + (int)(threadIdx.x / B);
+  const int iz0 = bz * B;
+  const float px = (float)(g.x0 + ix), py = (float)(g.y0 + iy), pz0 = (float)(g.z0 + iz0);
+  const bool col_in = ix < g.nx && iy < g.ny;
+  unsigned long long nin = 0, ncand = 0;
+  for (uint32_t j = brick_start[b]; j < brick_start[b + 1]; ++j) {
+    const Record r = load_record(rec, __builtin_amdgcn_readfirstlane(pair_gid[j]));
+    const ColumnSetup s = column_setup<B>(r, px, py, pz0, iz0);
+    if (!column_hit(s, col_in, thr)) continue;
+    for (int zz = s.za; zz <= s.zb; ++zz) {
+      const float q = quad_at(s, r.azz, s.t0 + (float)zz);
+      if (__builtin_amdgcn_ballot_w64(q > thr) == 0ull) continue;
+      ncand += 1;
+      nin += (col_in && iz0 + zz < g.nz && q > thr) ? 1 : 0;
+    }
+  }
+  nin = wave_sum_u64(nin);
+  ncand = wave_sum_u64(ncand);
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&counts[0], nin);
+    atomicAdd(&counts[1], ncand);
   }
 }
 
@@ -280,6 +401,22 @@ hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid, const uint3
   else if (bg.B == 16)
     hipLaunchKernelGGL(k_fused<16>, grid, dim3(256), 0, s, rec, pair_gid, brick_start, g, bg, thr,
                        field, acc, n, brick_loss);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_count(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
+                        gve_grid g, BrickGeom bg, float k, unsigned long long* counts,
+                        hipStream_t s) {
+  const float thr = -kHalfLog2e * k * k;
+  const dim3 grid((unsigned)bg.nbricks);
+  if (bg.B == 8)
+    hipLaunchKernelGGL(k_count<8>, grid, dim3(64), 0, s, rec, pair_gid, brick_start, g, bg, thr,
+                       counts);
+  else if (bg.B == 16)
+    hipLaunchKernelGGL(k_count<16>, grid, dim3(256), 0, s, rec, pair_gid, brick_start, g, bg, thr,
+                       counts);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
