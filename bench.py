@@ -70,6 +70,7 @@ def main():
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--budget", type=int, default=1_400_000)
     ap.add_argument("--brick", type=int, default=8)
+    ap.add_argument("--brick-z", type=int, default=32)
     ap.add_argument("--k", type=float, default=3.0)
     ap.add_argument("--lr", type=float, default=8e-3)
     ap.add_argument("--seed", type=int, default=2026)
@@ -94,8 +95,8 @@ def main():
     t_field = time.perf_counter() - t0
     grid = g.Grid(n, n, n)
     M = n ** 3
-    ctx = g.Context(k=args.k, brick=args.brick, lr=args.lr, ell_min=math.log(0.25),
-                    ell_max=math.log(max(n / 16.0, 0.25)))
+    ctx = g.Context(k=args.k, brick=args.brick, brick_z=args.brick_z, lr=args.lr,
+                    ell_min=math.log(0.25), ell_max=math.log(max(n / 16.0, 0.25)))
     t0 = time.perf_counter()
     P, info = g.allocate(ctx, field, grid, args.budget, args.seed)
     torch.cuda.synchronize()
@@ -147,11 +148,12 @@ def main():
         "config": {
             "workload": f"fronts-{n}^3 tanh fronts + k^-5/3 background, "
                         f"{args.budget} Gaussians from structure-aware allocation, "
-                        f"k={args.k:g}, brick {args.brick}, Adam lr {args.lr:g}",
+                        f"k={args.k:g}, bricks {args.brick}x{args.brick}x{args.brick_z}, "
+                        f"Adam lr {args.lr:g}",
             "grid": [n, n, n],
             "budget": args.budget,
             "k": args.k,
-            "brick": args.brick,
+            "brick": [args.brick, args.brick, args.brick_z],
             "seed": args.seed,
         },
         "roofline": {

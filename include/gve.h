@@ -63,9 +63,12 @@ typedef struct gve_grid {
 
 /*
  * Options.  k: truncation radius in standard deviations (> 0; Sec. III-C uses
- * 5).  brick: edge of the cubic voxel bricks primitives are binned to (8 or
- * 16; 0 picks 8).  lr, beta1, beta2, eps: Adam (Sec. III-F cites Kingma and
- * Ba; Table tab:training-config gives lr 8e-3).  ell_min/ell_max: clamp of the
+ * 5).  brick, brick_z: primitives are binned to bricks of brick x brick x
+ * brick_z voxels; supported shapes are 8x8x8, 8x8x16, 8x8x32 and 16x16x16
+ * (brick 0 picks 8; brick_z 0 picks the same as brick).  The shape changes
+ * only the summation order, not the result beyond float32 rounding.  lr,
+ * beta1, beta2, eps: Adam (Sec. III-F cites Kingma and Ba; Table
+ * tab:training-config gives lr 8e-3).  ell_min/ell_max: clamp of the
  * log-scales after each Adam step (a guard against collapsing or exploding
  * primitives; pass -inf/+inf to disable).
  */
@@ -74,6 +77,7 @@ typedef struct gve_options {
   int32_t brick;
   float lr, beta1, beta2, eps;
   float ell_min, ell_max;
+  int32_t brick_z;
 } gve_options;
 
 /* Counters of the most recent evaluation / refinement iteration. */
@@ -95,7 +99,7 @@ typedef struct gve_stats {
 typedef struct gve_ctx gve_ctx;
 typedef struct gve_params gve_params;
 
-/* Fill *opt with k = 3, brick = 8, lr = 8e-3, beta = (0.9, 0.999),
+/* Fill *opt with k = 3, brick 8 x 8 x 32, lr = 8e-3, beta = (0.9, 0.999),
  * eps = 1e-8, no clamp.  Returns INVALID_ARGUMENT if opt is NULL. */
 gve_status gve_default_options(gve_options* opt);
 

@@ -8,7 +8,7 @@ has not been built (``python paper_2608_14112_amd/build.py``).
 
 Names follow the C ABI without the ``gve_`` prefix:
 
-    ctx = Context(k=3.0, brick=8, lr=8e-3)
+    ctx = Context(k=3.0, brick=8, brick_z=32, lr=8e-3)
     p = Params(ctx, n)              # fixed budget n (paper Sec. III-A)
     p.upload(theta)                 # [11, n] float32 host array
     evaluate(ctx, p, grid, out)     # out: float32 cuda tensor [nz, ny, nx]
@@ -57,7 +57,8 @@ class GridC(ctypes.Structure):
 class OptionsC(ctypes.Structure):
     _fields_ = [("k", ctypes.c_float), ("brick", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
-                ("ell_min", ctypes.c_float), ("ell_max", ctypes.c_float)]
+                ("ell_min", ctypes.c_float), ("ell_max", ctypes.c_float),
+                ("brick_z", ctypes.c_int32)]
 
 
 class StatsC(ctypes.Structure):
@@ -167,11 +168,13 @@ class Context:
     """Owns a gve_ctx bound to a HIP stream (default: torch's current stream)."""
 
     def __init__(self, k=3.0, brick=8, lr=8e-3, beta1=0.9, beta2=0.999, eps=1e-8,
-                 ell_min=-math.inf, ell_max=math.inf, stream=None):
+                 ell_min=-math.inf, ell_max=math.inf, brick_z=None, stream=None):
         import torch
 
+        if brick_z is None:                       # library default shape 8 x 8 x 32
+            brick_z = 32 if brick in (0, 8) else 0
         self._torch_stream = stream if stream is not None else torch.cuda.current_stream()
-        o = OptionsC(k, brick, lr, beta1, beta2, eps, ell_min, ell_max)
+        o = OptionsC(k, brick, lr, beta1, beta2, eps, ell_min, ell_max, brick_z)
         h = _vp()
         st = _lib.gve_create(ctypes.byref(h), ctypes.byref(o),
                              _vp(self._torch_stream.cuda_stream))

@@ -76,8 +76,13 @@ gve_status ensure_dloss(gve_ctx* ctx) {
 gve_status validate_options(const gve_ctx* ctx, const gve_options& o) {
   if (!(o.k > 0.0f) || !std::isfinite(o.k) || o.k > 64.0f)
     return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "k must be finite, > 0 and <= 64");
-  if (!(o.brick == 0 || o.brick == 8 || o.brick == 16))
-    return fail(ctx, GVE_ERR_UNSUPPORTED, "brick must be 0 (auto), 8 or 16");
+  {
+    const int bxy = o.brick == 0 ? 8 : o.brick;
+    const int bz = o.brick_z == 0 ? bxy : o.brick_z;
+    if (!gve::brick_shape_supported(bxy, bz))
+      return fail(ctx, GVE_ERR_UNSUPPORTED,
+                  "brick shape must be 8x8x8, 8x8x16, 8x8x32 or 16x16x16");
+  }
   if (!(o.lr >= 0.0f) || !std::isfinite(o.lr))
     return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "lr must be finite and >= 0");
   if (!(o.beta1 >= 0.0f && o.beta1 < 1.0f) || !(o.beta2 >= 0.0f && o.beta2 < 1.0f))
@@ -102,7 +107,8 @@ gve_status validate_grid(const gve_ctx* ctx, const gve_grid& g) {
   return GVE_OK;
 }
 
-int brick_edge(const gve_ctx* ctx) { return ctx->opt.brick == 0 ? 8 : ctx->opt.brick; }
+int brick_xy(const gve_ctx* ctx) { return ctx->opt.brick == 0 ? 8 : ctx->opt.brick; }
+int brick_z(const gve_ctx* ctx) { return ctx->opt.brick_z == 0 ? brick_xy(ctx) : ctx->opt.brick_z; }
 
 int bits_for(int64_t nbricks) {
   int b = 0;
@@ -123,7 +129,7 @@ gve_status bin(gve_ctx* ctx, const gve_params* p, const gve_grid& g, Binned* out
   hipStream_t s = ctx->stream;
   auto& ws = ctx->ws;
   const int64_t n = p->n;
-  gve::BrickGeom bg = gve::brick_geometry(g, brick_edge(ctx));
+  gve::BrickGeom bg = gve::brick_geometry(g, brick_xy(ctx), brick_z(ctx));
   if (bg.nbricks >= ((int64_t)1 << 31))
     return fail(ctx, GVE_ERR_UNSUPPORTED, "too many bricks for 32-bit brick keys");
   TRY(ensure(ctx, ws.scan_tmp, gve::scan_tmp_bytes(n + 1)));
@@ -243,6 +249,7 @@ gve_status gve_default_options(gve_options* opt) {
   opt->eps = 1e-8f;
   opt->ell_min = -INFINITY;
   opt->ell_max = INFINITY;
+  opt->brick_z = 32;
   return GVE_OK;
 }
 

@@ -91,8 +91,9 @@ __device__ inline uint32_t prep_one(const float* __restrict__ theta, int64_t n, 
   }
   uint32_t cnt = 0;
   if (!empty) {
-    cnt = (uint32_t)(hi[0] / bg.B - lo[0] / bg.B + 1) * (uint32_t)(hi[1] / bg.B - lo[1] / bg.B + 1) *
-          (uint32_t)(hi[2] / bg.B - lo[2] / bg.B + 1);
+    cnt = (uint32_t)(hi[0] / bg.Bxy - lo[0] / bg.Bxy + 1) *
+          (uint32_t)(hi[1] / bg.Bxy - lo[1] / bg.Bxy + 1) *
+          (uint32_t)(hi[2] / bg.Bz - lo[2] / bg.Bz + 1);
   } else {
 #pragma unroll
     for (int j = 0; j < 3; ++j) { lo[j] = 1; hi[j] = 0; }
@@ -129,9 +130,9 @@ __global__ __launch_bounds__(kThreads) void k_emit(const Record* __restrict__ re
   const uint32_t e = offset[i + 1];
   if (o == e) return;
   const Record& r = rec[i];
-  const int bx0 = r.lo[0] / bg.B, bx1 = r.hi[0] / bg.B;
-  const int by0 = r.lo[1] / bg.B, by1 = r.hi[1] / bg.B;
-  const int bz0 = r.lo[2] / bg.B, bz1 = r.hi[2] / bg.B;
+  const int bx0 = r.lo[0] / bg.Bxy, bx1 = r.hi[0] / bg.Bxy;
+  const int by0 = r.lo[1] / bg.Bxy, by1 = r.hi[1] / bg.Bxy;
+  const int bz0 = r.lo[2] / bg.Bz, bz1 = r.hi[2] / bg.Bz;
   for (int bz = bz0; bz <= bz1; ++bz)
     for (int by = by0; by <= by1; ++by) {
       const uint32_t row = (uint32_t)bg.nbx * ((uint32_t)by + (uint32_t)bg.nby * (uint32_t)bz);
@@ -159,12 +160,13 @@ __global__ __launch_bounds__(kThreads) void k_ranges(const uint32_t* __restrict_
 
 }  // namespace
 
-BrickGeom brick_geometry(const gve_grid& g, int B) {
+BrickGeom brick_geometry(const gve_grid& g, int Bxy, int Bz) {
   BrickGeom bg;
-  bg.B = B;
-  bg.nbx = (int)((g.nx + B - 1) / B);
-  bg.nby = (int)((g.ny + B - 1) / B);
-  bg.nbz = (int)((g.nz + B - 1) / B);
+  bg.Bxy = Bxy;
+  bg.Bz = Bz;
+  bg.nbx = (int)((g.nx + Bxy - 1) / Bxy);
+  bg.nby = (int)((g.ny + Bxy - 1) / Bxy);
+  bg.nbz = (int)((g.nz + Bz - 1) / Bz);
   bg.nbricks = (int64_t)bg.nbx * bg.nby * bg.nbz;
   return bg;
 }

@@ -96,13 +96,15 @@ size_t sort_hist_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits,
                             void* hist, int* which, hipStream_t s);
 
+// Bricks are Bxy x Bxy x Bz voxels: a workgroup's lanes own the Bxy^2 voxel
+// columns, each lane Bz voxels of its column.
 struct BrickGeom {
-  int B;                 // brick edge in voxels
+  int Bxy, Bz;           // brick edges in voxels
   int nbx, nby, nbz;     // bricks per axis
   int64_t nbricks;
 };
 
-BrickGeom brick_geometry(const gve_grid& g, int B);
+BrickGeom brick_geometry(const gve_grid& g, int Bxy, int Bz);
 
 // Writes rec and count for every primitive and adds the pair total to *total
 // (which the caller zeroes first).
@@ -113,6 +115,8 @@ hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, Bri
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t npairs, int64_t nbricks,
                          uint32_t* brick_start, hipStream_t s);
 
+// Brick shapes (Bxy, Bz) the field kernels are compiled for.
+bool brick_shape_supported(int bxy, int bz);
 hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid,
                           const uint32_t* brick_start, gve_grid g, BrickGeom bg, float k,
                           float* out, hipStream_t s);

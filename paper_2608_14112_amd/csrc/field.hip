@@ -1,7 +1,7 @@
 // Per-brick field kernels.
 //
-// A workgroup owns one B x B x B brick; lane (lx, ly) owns the voxel column
-// (x, y, z0 .. z0 + B - 1) and keeps its B values in registers.  The brick's
+// A workgroup owns one BXY x BXY x BZ brick; lane (lx, ly) owns the voxel
+// column (x, y, z0 .. z0 + BZ - 1) and keeps its BZ values in registers.  The brick's
 // primitives (a contiguous run of the brick-sorted pair list, increasing
 // primitive index) are read one at a time with wave-uniform scalar loads.
 //
@@ -94,11 +94,11 @@ struct ColumnSetup {
   int za, zb;
 };
 
-template <int B>
+template <int BZ>
 __device__ inline ColumnSetup column_setup(const Record& r, float px, float py, float pz0, int iz0) {
   ColumnSetup s;
   s.za = max(r.lo[2] - iz0, 0);
-  s.zb = min(r.hi[2] - iz0, B - 1);
+  s.zb = min(r.hi[2] - iz0, BZ - 1);
   const float dx = px - r.mu[0];
   const float dy = py - r.mu[1];
   s.qxy = (r.s[0] * dx + 2.0f * r.s[1] * dy) * dx + r.s[2] * dy * dy;
@@ -121,18 +121,18 @@ __device__ inline bool column_hit(const ColumnSetup& s, bool col_in, float thr) 
   return __builtin_amdgcn_ballot_w64(col_in && s.qxy > thr) != 0ull;
 }
 
-template <int B>
+template <int BZ>
 __device__ inline void accumulate_brick(const Record* __restrict__ rec,
                                         const uint32_t* __restrict__ pair_gid, uint32_t j0,
                                         uint32_t j1, float px, float py, float pz0, int iz0,
-                                        bool col_in, float thr, float (&acc)[B]) {
+                                        bool col_in, float thr, float (&acc)[BZ]) {
   for (uint32_t j = j0; j < j1; ++j) {
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
-    const ColumnSetup s = column_setup<B>(r, px, py, pz0, iz0);
+    const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
     if (!column_hit(s, col_in, thr)) continue;
 #pragma unroll
-    for (int zz = 0; zz < B; ++zz) {
+    for (int zz = 0; zz < BZ; ++zz) {
       if (zz >= s.za && zz <= s.zb) {
         const float q = quad_at(s, r.azz, s.t0 + (float)zz);
         if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
@@ -144,8 +144,8 @@ __device__ inline void accumulate_brick(const Record* __restrict__ rec,
   }
 }
 
-template <int B>
-__global__ __launch_bounds__(B* B) void k_forward(const Record* __restrict__ rec,
+template <int BXY, int BZ>
+__global__ __launch_bounds__(BXY* BXY) void k_forward(const Record* __restrict__ rec,
                                                   const uint32_t* __restrict__ pair_gid,
                                                   const uint32_t* __restrict__ brick_start,
                                                   gve_grid g, BrickGeom bg, float thr,
@@ -154,42 +154,42 @@ __global__ __launch_bounds__(B* B) void k_forward(const Record* __restrict__ rec
   const int bx = (int)(b % bg.nbx);
   const int by = (int)((b / bg.nbx) % bg.nby);
   const int bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-  const int ix = bx * B + (int)(threadIdx.x % B);
-  const int iy = by * B + (int)(threadIdx.x / B);
-  const int iz0 = bz * B;
+  const int ix = bx * BXY + (int)(threadIdx.x % BXY);
+  const int iy = by * BXY + (int)(threadIdx.x / BXY);
+  const int iz0 = bz * BZ;
   const float px = (float)(g.x0 + ix), py = (float)(g.y0 + iy), pz0 = (float)(g.z0 + iz0);
   const bool col_in = ix < g.nx && iy < g.ny;
-  float acc[B];
+  float acc[BZ];
 #pragma unroll
-  for (int zz = 0; zz < B; ++zz) acc[zz] = 0.0f;
-  accumulate_brick<B>(rec, pair_gid, brick_start[b], brick_start[b + 1], px, py, pz0, iz0, col_in,
+  for (int zz = 0; zz < BZ; ++zz) acc[zz] = 0.0f;
+  accumulate_brick<BZ>(rec, pair_gid, brick_start[b], brick_start[b + 1], px, py, pz0, iz0, col_in,
                       thr, acc);
   if (col_in) {
     const size_t plane = (size_t)g.nx * (size_t)g.ny;
     const size_t base = (size_t)ix + (size_t)g.nx * (size_t)iy;
 #pragma unroll
-    for (int zz = 0; zz < B; ++zz)
+    for (int zz = 0; zz < BZ; ++zz)
       if (iz0 + zz < g.nz) out[base + plane * (size_t)(iz0 + zz)] = acc[zz];
   }
 }
 
-template <int B>
-__global__ __launch_bounds__(B* B) void k_fused(const Record* __restrict__ rec,
+template <int BXY, int BZ>
+__global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ rec,
                                                 const uint32_t* __restrict__ pair_gid,
                                                 const uint32_t* __restrict__ brick_start,
                                                 gve_grid g, BrickGeom bg, float thr,
                                                 const float* __restrict__ field,
                                                 float* __restrict__ gacc, int64_t n,
                                                 float* __restrict__ brick_loss) {
-  constexpr int kWaves = (B * B + 63) / 64;
+  constexpr int kWaves = (BXY * BXY + 63) / 64;
   __shared__ float red[kWaves][10];
   const int64_t b = blockIdx.x;
   const int bx = (int)(b % bg.nbx);
   const int by = (int)((b / bg.nbx) % bg.nby);
   const int bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-  const int ix = bx * B + (int)(threadIdx.x % B);
-  const int iy = by * B + (int)(threadIdx.x / B);
-  const int iz0 = bz * B;
+  const int ix = bx * BXY + (int)(threadIdx.x % BXY);
+  const int iy = by * BXY + (int)(threadIdx.x / BXY);
+  const int iz0 = bz * BZ;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int row = lane >> 4;
@@ -197,17 +197,17 @@ __global__ __launch_bounds__(B* B) void k_fused(const Record* __restrict__ rec,
   const bool col_in = (ix < g.nx) && (iy < g.ny);
   const uint32_t j0 = brick_start[b], j1 = brick_start[b + 1];
 
-  float res[B];
+  float res[BZ];
 #pragma unroll
-  for (int zz = 0; zz < B; ++zz) res[zz] = 0.0f;
-  accumulate_brick<B>(rec, pair_gid, j0, j1, px, py, pz0, iz0, col_in, thr, res);
+  for (int zz = 0; zz < BZ; ++zz) res[zz] = 0.0f;
+  accumulate_brick<BZ>(rec, pair_gid, j0, j1, px, py, pz0, iz0, col_in, thr, res);
 
   // residual and this brick's share of the loss
   float lsum = 0.0f;
   const size_t plane = (size_t)g.nx * (size_t)g.ny;
   const size_t base = (size_t)ix + (size_t)g.nx * (size_t)iy;
 #pragma unroll
-  for (int zz = 0; zz < B; ++zz) {
+  for (int zz = 0; zz < BZ; ++zz) {
     float r = 0.0f;
     if (col_in && iz0 + zz < g.nz) {
       const float d = res[zz] - field[base + plane * (size_t)(iz0 + zz)];
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(B* B) void k_fused(const Record* __restrict__ rec,
   for (uint32_t j = j0; j < j1; ++j) {
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
-    const ColumnSetup s = column_setup<B>(r, px, py, pz0, iz0);
+    const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
     const bool hit = column_hit(s, col_in, thr);
     if (kWaves == 1 && !hit) continue;
     float v[10];
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(B* B) void k_fused(const Record* __restrict__ rec,
       float se = 0.0f, st = 0.0f, stt = 0.0f;
       if (hit) {
 #pragma unroll
-        for (int zz = 0; zz < B; ++zz) {
+        for (int zz = 0; zz < BZ; ++zz) {
           if (zz >= s.za && zz <= s.zb) {
             const float t = s.t0 + (float)zz;
             const float q = quad_at(s, r.azz, t);
@@ -303,8 +303,8 @@ __global__ __launch_bounds__(B* B) void k_fused(const Record* __restrict__ rec,
 // inside the grid (m^2 < k^2), [1] lane-voxel evaluations the brick kernels
 // perform after their wave-level skips (the candidate pairs, masked lanes
 // included).
-template <int B>
-__global__ __launch_bounds__(B* B) void k_count(const Record* __restrict__ rec,
+template <int BXY, int BZ>
+__global__ __launch_bounds__(BXY* BXY) void k_count(const Record* __restrict__ rec,
                                                 const uint32_t* __restrict__ pair_gid,
                                                 const uint32_t* __restrict__ brick_start,
                                                 gve_grid g, BrickGeom bg, float thr,
@@ -313,15 +313,15 @@ __global__ __launch_bounds__(B* B) void k_count(const Record* __restrict__ rec,
   const int bx = (int)(b % bg.nbx);
   const int by = (int)((b / bg.nbx) % bg.nby);
   const int bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-  const int ix = bx * B + (int)(threadIdx.x % B);
-  const int iy = by * B + (int)(threadIdx.x / B);
-  const int iz0 = bz * B;
+  const int ix = bx * BXY + (int)(threadIdx.x % BXY);
+  const int iy = by * BXY + (int)(threadIdx.x / BXY);
+  const int iz0 = bz * BZ;
   const float px = (float)(g.x0 + ix), py = (float)(g.y0 + iy), pz0 = (float)(g.z0 + iz0);
   const bool col_in = ix < g.nx && iy < g.ny;
   unsigned long long nin = 0, ncand = 0;
   for (uint32_t j = brick_start[b]; j < brick_start[b + 1]; ++j) {
     const Record r = load_record(rec, __builtin_amdgcn_readfirstlane(pair_gid[j]));
-    const ColumnSetup s = column_setup<B>(r, px, py, pz0, iz0);
+    const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
     if (!column_hit(s, col_in, thr)) continue;
     for (int zz = s.za; zz <= s.zb; ++zz) {
       const float q = quad_at(s, r.azz, s.t0 + (float)zz);
@@ -375,19 +375,28 @@ __global__ __launch_bounds__(kRedThreads) void k_loss_final(const double* __rest
 
 }  // namespace
 
+#define GVE_BRICK_SHAPES(X) X(8, 8) X(8, 16) X(8, 32) X(16, 16)
+
+bool brick_shape_supported(int bxy, int bz) {
+#define GVE_CASE(XY, Z) if (bxy == XY && bz == Z) return true;
+  GVE_BRICK_SHAPES(GVE_CASE)
+#undef GVE_CASE
+  return false;
+}
+
 hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
                           gve_grid g, BrickGeom bg, float k, float* out, hipStream_t s) {
   const float thr = -kHalfLog2e * k * k;
   const dim3 grid((unsigned)bg.nbricks);
-  if (bg.B == 8)
-    hipLaunchKernelGGL(k_forward<8>, grid, dim3(64), 0, s, rec, pair_gid, brick_start, g, bg, thr,
-                       out);
-  else if (bg.B == 16)
-    hipLaunchKernelGGL(k_forward<16>, grid, dim3(256), 0, s, rec, pair_gid, brick_start, g, bg,
-                       thr, out);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+#define GVE_CASE(XY, Z)                                                                       \
+  if (bg.Bxy == XY && bg.Bz == Z) {                                                           \
+    hipLaunchKernelGGL((k_forward<XY, Z>), grid, dim3(XY * XY), 0, s, rec, pair_gid,            \
+                       brick_start, g, bg, thr, out);                                           \
+    return hipGetLastError();                                                                 \
+  }
+  GVE_BRICK_SHAPES(GVE_CASE)
+#undef GVE_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
@@ -395,15 +404,15 @@ hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid, const uint3
                         int64_t n, float* brick_loss, hipStream_t s) {
   const float thr = -kHalfLog2e * k * k;
   const dim3 grid((unsigned)bg.nbricks);
-  if (bg.B == 8)
-    hipLaunchKernelGGL(k_fused<8>, grid, dim3(64), 0, s, rec, pair_gid, brick_start, g, bg, thr,
-                       field, acc, n, brick_loss);
-  else if (bg.B == 16)
-    hipLaunchKernelGGL(k_fused<16>, grid, dim3(256), 0, s, rec, pair_gid, brick_start, g, bg, thr,
-                       field, acc, n, brick_loss);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+#define GVE_CASE(XY, Z)                                                                       \
+  if (bg.Bxy == XY && bg.Bz == Z) {                                                           \
+    hipLaunchKernelGGL((k_fused<XY, Z>), grid, dim3(XY * XY), 0, s, rec, pair_gid, brick_start, \
+                       g, bg, thr, field, acc, n, brick_loss);                                  \
+    return hipGetLastError();                                                                 \
+  }
+  GVE_BRICK_SHAPES(GVE_CASE)
+#undef GVE_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_count(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
@@ -411,15 +420,15 @@ hipError_t launch_count(const Record* rec, const uint32_t* pair_gid, const uint3
                         hipStream_t s) {
   const float thr = -kHalfLog2e * k * k;
   const dim3 grid((unsigned)bg.nbricks);
-  if (bg.B == 8)
-    hipLaunchKernelGGL(k_count<8>, grid, dim3(64), 0, s, rec, pair_gid, brick_start, g, bg, thr,
-                       counts);
-  else if (bg.B == 16)
-    hipLaunchKernelGGL(k_count<16>, grid, dim3(256), 0, s, rec, pair_gid, brick_start, g, bg, thr,
-                       counts);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+#define GVE_CASE(XY, Z)                                                                       \
+  if (bg.Bxy == XY && bg.Bz == Z) {                                                           \
+    hipLaunchKernelGGL((k_count<XY, Z>), grid, dim3(XY * XY), 0, s, rec, pair_gid, brick_start, \
+                       g, bg, thr, counts);                                                     \
+    return hipGetLastError();                                                                 \
+  }
+  GVE_BRICK_SHAPES(GVE_CASE)
+#undef GVE_CASE
+  return hipErrorInvalidValue;
 }
 
 size_t loss_reduce_tmp_doubles() { return kRedBlocks; }

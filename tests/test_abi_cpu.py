@@ -36,7 +36,7 @@ def test_default_options_and_status_strings():
     import paper_2608_14112_amd as g
 
     o = g.default_options()
-    assert o.k == 3.0 and o.brick == 8
+    assert o.k == 3.0 and o.brick == 8 and o.brick_z == 32
     assert abs(o.lr - 8e-3) < 1e-9 and abs(o.beta1 - 0.9) < 1e-7 and abs(o.beta2 - 0.999) < 1e-7
     assert math.isinf(o.ell_min) and math.isinf(o.ell_max)
     for s in range(7):
@@ -62,6 +62,7 @@ def test_null_arguments_are_rejected():
 
 @pytest.mark.parametrize("field,value,status", [
     ("k", -1.0, 1), ("k", float("nan"), 1), ("k", 0.0, 1), ("brick", 4, 6), ("brick", 7, 6),
+    ("brick_z", 4, 6), ("brick_z", 24, 6),
     ("lr", -1.0, 1), ("beta1", 1.0, 1), ("beta2", -0.1, 1), ("eps", 0.0, 1),
     ("ell_min", 3.0, 1),
 ])

@@ -22,8 +22,12 @@ def _lib():
     return g, torch
 
 
+SHAPES = [(8, 8), (8, 16), (8, 32), (16, 16)]
+
+
 def _eval_gpu(g, torch, params, grid, k, brick):
-    ctx = g.Context(k=k, brick=brick)
+    bxy, bz = brick if isinstance(brick, tuple) else (brick, brick)
+    ctx = g.Context(k=k, brick=bxy, brick_z=bz)
     p = g.Params(ctx, params.shape[1]).upload(params.astype(np.float32))
     out = torch.empty(grid.shape, device="cuda", dtype=torch.float32)
     g.evaluate(ctx, p, g.Grid(grid.nx, grid.ny, grid.nz, grid.x0, grid.y0, grid.z0), out)
@@ -49,7 +53,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("k", [3.0, 5.0])
-@pytest.mark.parametrize("brick", [8, 16])
+@pytest.mark.parametrize("brick", SHAPES)
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_evaluate_matches_oracle(k, brick, case):
     g, torch = _lib()
@@ -81,9 +85,12 @@ def test_forward_is_bitwise_reproducible_and_brick_invariant():
     a, _ = _eval_gpu(g, torch, params, grid, 3.0, 8)
     b, _ = _eval_gpu(g, torch, params, grid, 3.0, 8)
     assert np.array_equal(a, b)
-    c, _ = _eval_gpu(g, torch, params, grid, 3.0, 16)
     _, A = F.evaluate_windowed(params, grid, 3.0)
-    assert np.max(np.abs(a.astype(np.float64) - c) / (A + 1e-30)) < 2e-6
+    # another brick shape changes only the float32 rounding of each column's
+    # coordinates (both results are within 1e-5 A of the oracle)
+    for shape in SHAPES[1:]:
+        c, _ = _eval_gpu(g, torch, params, grid, 3.0, shape)
+        assert np.max(np.abs(a.astype(np.float64) - c) / (A + 1e-30)) < 1e-5
 
 
 def test_large_k_equals_untruncated_field():
@@ -122,7 +129,8 @@ def test_edge_cases():
 # ----------------------------------------------------------------------------- gradient
 
 def _loss_grad_gpu(g, torch, params, field, grid, k, brick):
-    ctx = g.Context(k=k, brick=brick)
+    bxy, bz = brick if isinstance(brick, tuple) else (brick, brick)
+    ctx = g.Context(k=k, brick=bxy, brick_z=bz)
     p = g.Params(ctx, params.shape[1]).upload(params.astype(np.float32))
     f = torch.from_numpy(np.ascontiguousarray(field, dtype=np.float32)).cuda()
     grad = torch.empty((11, params.shape[1]), device="cuda", dtype=torch.float32)
@@ -130,7 +138,7 @@ def _loss_grad_gpu(g, torch, params, field, grid, k, brick):
     return L, grad.cpu().numpy()
 
 
-@pytest.mark.parametrize("brick", [8, 16])
+@pytest.mark.parametrize("brick", SHAPES)
 @pytest.mark.parametrize("k", [3.0, 5.0])
 def test_loss_grad_matches_oracle(brick, k):
     g, torch = _lib()
@@ -151,10 +159,11 @@ def test_loss_grad_tiny_workload():
     grid = F.Grid(64, 64, 64)
     params = S.random_params(2048, 64, seed=12, scale_range=(1.5, 4.0), weight_range=(-0.2, 0.2))
     params = params.astype(np.float32).astype(np.float64)
-    L, grad = _loss_grad_gpu(g, torch, params, field, grid, 3.0, 8)
-    Lr, gr = F.loss_grad(params, field.astype(np.float64), grid, 3.0)
-    assert abs(L - Lr) <= 1e-5 * Lr
-    check_grad(grad, gr)
+    for shape in ((8, 8), (8, 32)):
+        L, grad = _loss_grad_gpu(g, torch, params, field, grid, 3.0, shape)
+        Lr, gr = F.loss_grad(params, field.astype(np.float64), grid, 3.0)
+        assert abs(L - Lr) <= 1e-5 * Lr
+        check_grad(grad, gr)
 
 
 def test_adam_step_matches_oracle():
