@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--lr", type=float, default=8e-3)
     ap.add_argument("--seed", type=int, default=2026)
     ap.add_argument("--cpu-block", type=int, default=256)
+    ap.add_argument("--atomics", action="store_true",
+                    help="accumulate gradient sums with float atomics instead of per-pair slots")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -96,7 +98,8 @@ def main():
     grid = g.Grid(n, n, n)
     M = n ** 3
     ctx = g.Context(k=args.k, brick=args.brick, brick_z=args.brick_z, lr=args.lr,
-                    ell_min=math.log(0.25), ell_max=math.log(max(n / 16.0, 0.25)))
+                    ell_min=math.log(0.25), ell_max=math.log(max(n / 16.0, 0.25)),
+                    deterministic=not args.atomics)
     t0 = time.perf_counter()
     P, info = g.allocate(ctx, field, grid, args.budget, args.seed)
     torch.cuda.synchronize()
@@ -154,6 +157,7 @@ def main():
             "budget": args.budget,
             "k": args.k,
             "brick": [args.brick, args.brick, args.brick_z],
+            "gradient_sums": "float atomics" if args.atomics else "per-pair slots, fixed order",
             "seed": args.seed,
         },
         "roofline": {

@@ -70,7 +70,10 @@ typedef struct gve_grid {
  * beta1, beta2, eps: Adam (Sec. III-F cites Kingma and Ba; Table
  * tab:training-config gives lr 8e-3).  ell_min/ell_max: clamp of the
  * log-scales after each Adam step (a guard against collapsing or exploding
- * primitives; pass -inf/+inf to disable).
+ * primitives; pass -inf/+inf to disable).  deterministic: 1 = each
+ * (primitive, brick) pair writes its gradient sums to its own slot and the
+ * update sums them per primitive in a fixed order, so gradients are bitwise
+ * reproducible and no atomics are issued (default); 0 = float atomics.
  */
 typedef struct gve_options {
   float k;
@@ -78,6 +81,7 @@ typedef struct gve_options {
   float lr, beta1, beta2, eps;
   float ell_min, ell_max;
   int32_t brick_z;
+  int32_t deterministic;
 } gve_options;
 
 /* Counters of the most recent evaluation / refinement iteration. */
@@ -100,7 +104,8 @@ typedef struct gve_ctx gve_ctx;
 typedef struct gve_params gve_params;
 
 /* Fill *opt with k = 3, brick 8 x 8 x 32, lr = 8e-3, beta = (0.9, 0.999),
- * eps = 1e-8, no clamp.  Returns INVALID_ARGUMENT if opt is NULL. */
+ * eps = 1e-8, no clamp, deterministic gradients.  Returns INVALID_ARGUMENT if
+ * opt is NULL. */
 gve_status gve_default_options(gve_options* opt);
 
 /* Create a context on the current HIP device.  hip_stream is a hipStream_t
@@ -149,8 +154,9 @@ gve_status gve_evaluate(gve_ctx* ctx, const gve_params* p, gve_grid g, float* d_
  * every voxel of g).  L = sum_p (Vhat(p) - V(p))^2 with V = d_field [nz][ny][nx]
  * float32.  Writes dL/dtheta as [11][n] float32 into d_grad (caller-owned;
  * may be NULL to skip) with the truncation indicator held fixed, and L into
- * *h_loss if h_loss is not NULL (synchronises).  Gradient sums use float32
- * atomics, so the last bits depend on execution order.
+ * *h_loss if h_loss is not NULL (synchronises).  With options.deterministic
+ * the gradient is bitwise reproducible; with float atomics its last bits
+ * depend on execution order.
  */
 gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field, gve_grid g,
                          float* d_grad, double* h_loss);

@@ -58,7 +58,7 @@ class OptionsC(ctypes.Structure):
     _fields_ = [("k", ctypes.c_float), ("brick", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("ell_min", ctypes.c_float), ("ell_max", ctypes.c_float),
-                ("brick_z", ctypes.c_int32)]
+                ("brick_z", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 class StatsC(ctypes.Structure):
@@ -168,13 +168,15 @@ class Context:
     """Owns a gve_ctx bound to a HIP stream (default: torch's current stream)."""
 
     def __init__(self, k=3.0, brick=8, lr=8e-3, beta1=0.9, beta2=0.999, eps=1e-8,
-                 ell_min=-math.inf, ell_max=math.inf, brick_z=None, stream=None):
+                 ell_min=-math.inf, ell_max=math.inf, brick_z=None, deterministic=True,
+                 stream=None):
         import torch
 
         if brick_z is None:                       # library default shape 8 x 8 x 32
             brick_z = 32 if brick in (0, 8) else 0
         self._torch_stream = stream if stream is not None else torch.cuda.current_stream()
-        o = OptionsC(k, brick, lr, beta1, beta2, eps, ell_min, ell_max, brick_z)
+        o = OptionsC(k, brick, lr, beta1, beta2, eps, ell_min, ell_max, brick_z,
+                     1 if deterministic else 0)
         h = _vp()
         st = _lib.gve_create(ctypes.byref(h), ctypes.byref(o),
                              _vp(self._torch_stream.cuda_stream))

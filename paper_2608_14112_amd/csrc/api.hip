@@ -89,6 +89,8 @@ gve_status validate_options(const gve_ctx* ctx, const gve_options& o) {
     return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "beta1, beta2 must lie in [0, 1)");
   if (!(o.eps > 0.0f) || !std::isfinite(o.eps))
     return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "eps must be finite and > 0");
+  if (o.deterministic != 0 && o.deterministic != 1)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "deterministic must be 0 or 1");
   if (std::isnan(o.ell_min) || std::isnan(o.ell_max) || o.ell_min > o.ell_max)
     return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "ell_min must be <= ell_max");
   return GVE_OK;
@@ -182,15 +184,27 @@ gve_status set_device(const gve_ctx* ctx) {
   return GVE_OK;
 }
 
+// Partials buffer for deterministic gradients (nullptr selects atomics).
+gve_status partials_for(gve_ctx* ctx, int64_t npairs, float** part) {
+  *part = nullptr;
+  if (!ctx->opt.deterministic) return GVE_OK;
+  TRY(ensure(ctx, ctx->ws.partials, sizeof(float) * 10 * (size_t)(npairs > 0 ? npairs : 1)));
+  *part = static_cast<float*>(ctx->ws.partials.ptr);
+  return GVE_OK;
+}
+
 // Fused forward + squared error + backward into p->acc, loss into dloss[0].
 gve_status loss_and_sums(gve_ctx* ctx, const gve_params* p, const float* d_field, const gve_grid& g,
-                         double* d_loss_out) {
+                         double* d_loss_out, float** part_out) {
   Binned bn;
   TRY(bin(ctx, p, g, &bn));
   TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)bn.bg.nbricks));
   float* bl = static_cast<float*>(ctx->ws.brick_loss.ptr);
+  float* part = nullptr;
+  TRY(partials_for(ctx, bn.npairs, &part));
+  *part_out = part;
   TRY_HIP(ctx, gve::launch_fused(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, d_field, p->acc,
-                                 p->n, bl, ctx->stream));
+                                 p->n, part, p->offset, bl, ctx->stream));
   double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
   TRY_HIP(ctx, gve::launch_loss_reduce(bl, bn.bg.nbricks, dl + 16, d_loss_out, ctx->stream));
   return GVE_OK;
@@ -250,6 +264,7 @@ gve_status gve_default_options(gve_options* opt) {
   opt->ell_min = -INFINITY;
   opt->ell_max = INFINITY;
   opt->brick_z = 32;
+  opt->deterministic = 1;
   return GVE_OK;
 }
 
@@ -282,7 +297,7 @@ gve_status gve_destroy(gve_ctx* ctx) {
   auto& ws = ctx->ws;
   Scratch* all[] = {&ws.keys[0], &ws.keys[1], &ws.vals[0], &ws.vals[1], &ws.brick_start,
                     &ws.brick_loss, &ws.scan_tmp, &ws.sort_hist, &ws.dloss, &ws.clamp_count,
-                    &ws.grad_tmp, &ws.alloc, &ws.voxf};
+                    &ws.grad_tmp, &ws.alloc, &ws.voxf, &ws.partials};
   for (Scratch* s : all)
     if (s->ptr) hipFree(s->ptr);
   if (ws.h_pinned) hipHostFree(ws.h_pinned);
@@ -431,10 +446,11 @@ gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field
   TRY(ensure_dloss(ctx));
   TRY_HIP(ctx, gve::fill_f32(pm->acc, 10 * p->n, 0.0f, ctx->stream));
   double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
-  TRY(loss_and_sums(ctx, p, d_field, g, dl));
+  float* part = nullptr;
+  TRY(loss_and_sums(ctx, p, d_field, g, dl, &part));
   if (d_grad) {
-    TRY_HIP(ctx, gve::launch_update(0, pm->theta, pm->m, pm->v, pm->acc, nullptr, d_grad, p->n,
-                                    p->t, ctx->opt, nullptr, ctx->stream));
+    TRY_HIP(ctx, gve::launch_update(0, pm->theta, pm->m, pm->v, pm->acc, part, p->offset, nullptr,
+                                    d_grad, p->n, p->t, ctx->opt, nullptr, ctx->stream));
   } else {
     TRY_HIP(ctx, gve::fill_f32(pm->acc, 10 * p->n, 0.0f, ctx->stream));
   }
@@ -455,7 +471,8 @@ gve_status gve_adam_step(gve_ctx* ctx, gve_params* p, const float* d_grad) {
   TRY(set_device(ctx));
   TRY(ensure_dloss(ctx));
   p->t += 1;
-  TRY_HIP(ctx, gve::launch_update(2, p->theta, p->m, p->v, p->acc, d_grad, nullptr, p->n, p->t,
+  TRY_HIP(ctx, gve::launch_update(2, p->theta, p->m, p->v, p->acc, nullptr, nullptr, d_grad,
+                                  nullptr, p->n, p->t,
                                   ctx->opt, clamp_counter(ctx), ctx->stream));
   ctx->stats.iterations = p->t;
   return GVE_OK;
@@ -513,15 +530,17 @@ gve_status gve_refine(gve_ctx* ctx, gve_params* p, const float* d_field, gve_gri
     TRY(bin(ctx, p, g, &bn));
     TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)bn.bg.nbricks));
     float* bl = static_cast<float*>(ctx->ws.brick_loss.ptr);
+    float* part = nullptr;
+    TRY(partials_for(ctx, bn.npairs, &part));
     if (timing) TRY_HIP(ctx, hipEventRecord(ev[1], s));
     TRY_HIP(ctx, gve::launch_fused(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, d_field,
-                                   p->acc, p->n, bl, s));
+                                   p->acc, p->n, part, p->offset, bl, s));
     if (timing) TRY_HIP(ctx, hipEventRecord(ev[2], s));
     double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
     TRY_HIP(ctx, gve::launch_loss_reduce(bl, bn.bg.nbricks, dl + 16, hist + it, s));
     p->t += 1;
-    TRY_HIP(ctx, gve::launch_update(1, p->theta, p->m, p->v, p->acc, nullptr, nullptr, p->n, p->t,
-                                    ctx->opt, clamp_counter(ctx), s));
+    TRY_HIP(ctx, gve::launch_update(1, p->theta, p->m, p->v, p->acc, part, p->offset, nullptr,
+                                    nullptr, p->n, p->t, ctx->opt, clamp_counter(ctx), s));
     if (timing) TRY_HIP(ctx, hipEventRecord(ev[3], s));
   }
   ctx->stats.iterations = p->t;

@@ -50,6 +50,7 @@ struct Workspace {
   Scratch grad_tmp;              // per-iteration loss history of gve_refine
   Scratch alloc;                 // allocation scratch (block counts, indices, states)
   Scratch voxf;                  // float [M] gradient magnitude, then U
+  Scratch partials;              // float [T][10] per-(primitive, brick) gradient sums
   void* h_pinned = nullptr;      // pinned host staging (64 bytes)
 };
 
@@ -120,10 +121,13 @@ bool brick_shape_supported(int bxy, int bz);
 hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid,
                           const uint32_t* brick_start, gve_grid g, BrickGeom bg, float k,
                           float* out, hipStream_t s);
+// part == nullptr: float atomics into acc [10][n].  Otherwise each (primitive,
+// brick) pair stores its ten sums to part[(offset[gid] + rank) * 10 + slot],
+// rank = the brick's position in the primitive's emitted brick range.
 hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid,
                         const uint32_t* brick_start, gve_grid g, BrickGeom bg, float k,
-                        const float* field, float* acc, int64_t n, float* brick_loss,
-                        hipStream_t s);
+                        const float* field, float* acc, int64_t n, float* part,
+                        const uint32_t* offset, float* brick_loss, hipStream_t s);
 hipError_t launch_count(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
                         gve_grid g, BrickGeom bg, float k, unsigned long long* counts,
                         hipStream_t s);
@@ -162,10 +166,12 @@ size_t normalize_tmp_floats();
 hipError_t normalize_field(float* f, int64_t M, float* tmp, hipStream_t s);
 
 // mode 0: chain rule -> grad_out ([11][n]); mode 1: chain rule + Adam;
-// mode 2: Adam from grad_in.  Zeroes acc in modes 0 and 1.
+// mode 2: Adam from grad_in.  In modes 0 and 1 the ten sums come from acc
+// (zeroed after use) or, when part is given, from the primitive's partials
+// part[offset[i] .. offset[i+1]) summed in order.
 hipError_t launch_update(int mode, float* theta, float* m, float* v, float* acc,
-                         const float* grad_in, float* grad_out, int64_t n, int64_t t,
-                         const gve_options& opt, unsigned long long* clamp_count,
-                         hipStream_t s);
+                         const float* part, const uint32_t* offset, const float* grad_in,
+                         float* grad_out, int64_t n, int64_t t, const gve_options& opt,
+                         unsigned long long* clamp_count, hipStream_t s);
 
 }  // namespace gve

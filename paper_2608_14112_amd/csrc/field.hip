@@ -18,9 +18,11 @@
 //               L = sum (Vhat - V)^2, then for every primitive of the brick the
 //               ten sums of the analytic gradient (e = r G, g = c e,
 //               d = p - mu): sum e, sum g d (3), sum g d d^T (6 unique),
-//               reduced over the workgroup with cross-lane shuffles and LDS and
-//               added to the primitive's accumulators with one float atomic
-//               each.  Per column only sum e, sum e t, sum e t^2 are needed
+//               reduced over the workgroup with cross-lane permutes and LDS,
+//               then either added to the primitive's accumulators with float
+//               atomics, or (deterministic mode) stored to the pair's own slot
+//               of a partials array that the update kernel sums per primitive
+//               in a fixed order.  Per column only sum e, sum e t, sum e t^2 are needed
 //               because dx, dy and dz - t are constant along it.
 #include "common.h"
 
@@ -92,6 +94,7 @@ __device__ inline int reduce10_slot(int k, int row) {
 struct ColumnSetup {
   float qxy, t0;
   int za, zb;
+  uint32_t zmask;  // bit zz set when brick offset zz lies in the z-range of the box
 };
 
 template <int BZ>
@@ -99,6 +102,8 @@ __device__ inline ColumnSetup column_setup(const Record& r, float px, float py, 
   ColumnSetup s;
   s.za = max(r.lo[2] - iz0, 0);
   s.zb = min(r.hi[2] - iz0, BZ - 1);
+  // bits za..zb (BZ <= 32; 2u << 31 wraps to 0, giving all ones)
+  s.zmask = (s.zb >= s.za) ? (((2u << s.zb) - 1u) & ~((1u << s.za) - 1u)) : 0u;
   const float dx = px - r.mu[0];
   const float dy = py - r.mu[1];
   s.qxy = (r.s[0] * dx + 2.0f * r.s[1] * dy) * dx + r.s[2] * dy * dy;
@@ -133,7 +138,7 @@ __device__ inline void accumulate_brick(const Record* __restrict__ rec,
     if (!column_hit(s, col_in, thr)) continue;
 #pragma unroll
     for (int zz = 0; zz < BZ; ++zz) {
-      if (zz >= s.za && zz <= s.zb) {
+      if ((s.zmask >> zz) & 1u) {
         const float q = quad_at(s, r.azz, s.t0 + (float)zz);
         if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
           const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
@@ -173,6 +178,17 @@ __global__ __launch_bounds__(BXY* BXY) void k_forward(const Record* __restrict__
   }
 }
 
+// Slot of the (primitive, brick) pair in the partials array: the primitive's
+// first pair plus the brick's rank in its emitted brick range (z, y, x order).
+template <int BXY, int BZ>
+__device__ inline uint32_t pair_slot(const Record& r, const uint32_t* __restrict__ offset,
+                                     uint32_t gid, int bx, int by, int bz) {
+  const int rbx = bx - r.lo[0] / BXY, rby = by - r.lo[1] / BXY, rbz = bz - r.lo[2] / BZ;
+  const int nbx_g = r.hi[0] / BXY - r.lo[0] / BXY + 1;
+  const int nby_g = r.hi[1] / BXY - r.lo[1] / BXY + 1;
+  return offset[gid] + (uint32_t)((rbz * nby_g + rby) * nbx_g + rbx);
+}
+
 template <int BXY, int BZ>
 __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ rec,
                                                 const uint32_t* __restrict__ pair_gid,
@@ -180,6 +196,8 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
                                                 gve_grid g, BrickGeom bg, float thr,
                                                 const float* __restrict__ field,
                                                 float* __restrict__ gacc, int64_t n,
+                                                float* __restrict__ part,
+                                                const uint32_t* __restrict__ offset,
                                                 float* __restrict__ brick_loss) {
   constexpr int kWaves = (BXY * BXY + 63) / 64;
   __shared__ float red[kWaves][10];
@@ -231,14 +249,19 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
     const Record r = load_record(rec, gid);
     const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
     const bool hit = column_hit(s, col_in, thr);
-    if (kWaves == 1 && !hit) continue;
+    if (kWaves == 1 && !hit) {
+      // a pair whose support misses every column still owns a partials slot
+      if (part && lane < 10)
+        part[(size_t)pair_slot<BXY, BZ>(r, offset, gid, bx, by, bz) * 10 + lane] = 0.0f;
+      continue;
+    }
     float v[10];
     {
       float se = 0.0f, st = 0.0f, stt = 0.0f;
       if (hit) {
 #pragma unroll
         for (int zz = 0; zz < BZ; ++zz) {
-          if (zz >= s.za && zz <= s.zb) {
+          if ((s.zmask >> zz) & 1u) {
             const float t = s.t0 + (float)zz;
             const float q = quad_at(s, r.azz, t);
             if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
@@ -273,7 +296,16 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
     float o[3];
     wave_reduce10(v, o);
     if (kWaves == 1) {
-      if ((lane & 15) == 0) {
+      if (part) {
+        const uint32_t slot_base = pair_slot<BXY, BZ>(r, offset, gid, bx, by, bz);
+        if ((lane & 15) == 0) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const int slot = reduce10_slot(k, row);
+            if (slot >= 0) part[(size_t)slot_base * 10 + slot] = o[k];
+          }
+        }
+      } else if ((lane & 15) == 0) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const int slot = reduce10_slot(k, row);
@@ -292,7 +324,11 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
       if (threadIdx.x < 10) {
         float t = 0.0f;
         for (int w = 0; w < kWaves; ++w) t += red[w][threadIdx.x];
-        if (t != 0.0f) unsafeAtomicAdd(&gacc[(int64_t)threadIdx.x * n + gid], t);
+        if (part) {
+          part[(size_t)pair_slot<BXY, BZ>(r, offset, gid, bx, by, bz) * 10 + threadIdx.x] = t;
+        } else if (t != 0.0f) {
+          unsafeAtomicAdd(&gacc[(int64_t)threadIdx.x * n + gid], t);
+        }
       }
       __syncthreads();
     }
@@ -401,13 +437,14 @@ hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid, const uin
 
 hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
                         gve_grid g, BrickGeom bg, float k, const float* field, float* acc,
-                        int64_t n, float* brick_loss, hipStream_t s) {
+                        int64_t n, float* part, const uint32_t* offset, float* brick_loss,
+                        hipStream_t s) {
   const float thr = -kHalfLog2e * k * k;
   const dim3 grid((unsigned)bg.nbricks);
 #define GVE_CASE(XY, Z)                                                                       \
   if (bg.Bxy == XY && bg.Bz == Z) {                                                           \
     hipLaunchKernelGGL((k_fused<XY, Z>), grid, dim3(XY * XY), 0, s, rec, pair_gid, brick_start, \
-                       g, bg, thr, field, acc, n, brick_loss);                                  \
+                       g, bg, thr, field, acc, n, part, offset, brick_loss);                    \
     return hipGetLastError();                                                                 \
   }
   GVE_BRICK_SHAPES(GVE_CASE)

@@ -1,8 +1,10 @@
 // Chain rule from the brick kernels' per-primitive sums to the 11 parameters,
 // fused with the bias-corrected Adam step (Sec. III-F cites Kingma and Ba).
 //
-// Inputs per primitive (accumulated by the fused brick kernel, e = r G,
-// g = c e, d = p - mu):  S_e = sum e,  S_gd = sum g d,  D = sum g d d^T.
+// Inputs per primitive (from the fused brick kernel, e = r G, g = c e,
+// d = p - mu):  S_e = sum e,  S_gd = sum g d,  D = sum g d d^T, either
+// accumulated by atomics or summed here over the primitive's per-brick
+// partials in emission order (deterministic).
 //   dL/dc    = S_e
 //   dL/dmu   = P S_gd                      (P = R S^-2 R^T)
 //   dL/dl_j  = s_j^-2 (R^T D R)_jj
@@ -22,6 +24,8 @@ struct AdamCoef {
 __global__ __launch_bounds__(kThreads) void k_update(int mode, float* __restrict__ theta,
                                                      float* __restrict__ m, float* __restrict__ v,
                                                      float* __restrict__ acc,
+                                                     const float* __restrict__ part,
+                                                     const uint32_t* __restrict__ offset,
                                                      const float* __restrict__ grad_in,
                                                      float* __restrict__ grad_out, int64_t n,
                                                      AdamCoef ac,
@@ -37,10 +41,20 @@ __global__ __launch_bounds__(kThreads) void k_update(int mode, float* __restrict
       for (int a = 0; a < 11; ++a) gr[a] = grad_in[a * n + i];
     } else {
       float s[10];
+      if (part) {
 #pragma unroll
-      for (int a = 0; a < 10; ++a) {
-        s[a] = acc[a * n + i];
-        acc[a * n + i] = 0.0f;
+        for (int a = 0; a < 10; ++a) s[a] = 0.0f;
+        const uint32_t pe = offset[i + 1];
+        for (uint32_t p = offset[i]; p < pe; ++p) {
+#pragma unroll
+          for (int a = 0; a < 10; ++a) s[a] += part[(size_t)p * 10 + a];
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 10; ++a) {
+          s[a] = acc[a * n + i];
+          acc[a * n + i] = 0.0f;
+        }
       }
       float qw = th[3], qx = th[4], qy = th[5], qz = th[6];
       const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
@@ -133,8 +147,9 @@ __global__ __launch_bounds__(kThreads) void k_update(int mode, float* __restrict
 }  // namespace
 
 hipError_t launch_update(int mode, float* theta, float* m, float* v, float* acc,
-                         const float* grad_in, float* grad_out, int64_t n, int64_t t,
-                         const gve_options& opt, unsigned long long* clamp_count, hipStream_t s) {
+                         const float* part, const uint32_t* offset, const float* grad_in,
+                         float* grad_out, int64_t n, int64_t t, const gve_options& opt,
+                         unsigned long long* clamp_count, hipStream_t s) {
   AdamCoef ac;
   ac.lr = opt.lr;
   ac.b1 = opt.beta1;
@@ -146,8 +161,8 @@ hipError_t launch_update(int mode, float* theta, float* m, float* v, float* acc,
   ac.lmin = opt.ell_min;
   ac.lmax = opt.ell_max;
   const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_update, dim3(blocks), dim3(kThreads), 0, s, mode, theta, m, v, acc,
-                     grad_in, grad_out, n, ac, clamp_count);
+  hipLaunchKernelGGL(k_update, dim3(blocks), dim3(kThreads), 0, s, mode, theta, m, v, acc, part,
+                     offset, grad_in, grad_out, n, ac, clamp_count);
   return hipGetLastError();
 }
 

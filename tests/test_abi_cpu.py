@@ -36,7 +36,7 @@ def test_default_options_and_status_strings():
     import paper_2608_14112_amd as g
 
     o = g.default_options()
-    assert o.k == 3.0 and o.brick == 8 and o.brick_z == 32
+    assert o.k == 3.0 and o.brick == 8 and o.brick_z == 32 and o.deterministic == 1
     assert abs(o.lr - 8e-3) < 1e-9 and abs(o.beta1 - 0.9) < 1e-7 and abs(o.beta2 - 0.999) < 1e-7
     assert math.isinf(o.ell_min) and math.isinf(o.ell_max)
     for s in range(7):
@@ -64,7 +64,7 @@ def test_null_arguments_are_rejected():
     ("k", -1.0, 1), ("k", float("nan"), 1), ("k", 0.0, 1), ("brick", 4, 6), ("brick", 7, 6),
     ("brick_z", 4, 6), ("brick_z", 24, 6),
     ("lr", -1.0, 1), ("beta1", 1.0, 1), ("beta2", -0.1, 1), ("eps", 0.0, 1),
-    ("ell_min", 3.0, 1),
+    ("ell_min", 3.0, 1), ("deterministic", 2, 1),
 ])
 def test_bad_options_fail_before_any_device_call(field, value, status):
     import paper_2608_14112_amd as g

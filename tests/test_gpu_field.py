@@ -128,9 +128,9 @@ def test_edge_cases():
 
 # ----------------------------------------------------------------------------- gradient
 
-def _loss_grad_gpu(g, torch, params, field, grid, k, brick):
+def _loss_grad_gpu(g, torch, params, field, grid, k, brick, deterministic=True):
     bxy, bz = brick if isinstance(brick, tuple) else (brick, brick)
-    ctx = g.Context(k=k, brick=bxy, brick_z=bz)
+    ctx = g.Context(k=k, brick=bxy, brick_z=bz, deterministic=deterministic)
     p = g.Params(ctx, params.shape[1]).upload(params.astype(np.float32))
     f = torch.from_numpy(np.ascontiguousarray(field, dtype=np.float32)).cuda()
     grad = torch.empty((11, params.shape[1]), device="cuda", dtype=torch.float32)
@@ -138,18 +138,29 @@ def _loss_grad_gpu(g, torch, params, field, grid, k, brick):
     return L, grad.cpu().numpy()
 
 
+@pytest.mark.parametrize("deterministic", [True, False])
 @pytest.mark.parametrize("brick", SHAPES)
 @pytest.mark.parametrize("k", [3.0, 5.0])
-def test_loss_grad_matches_oracle(brick, k):
+def test_loss_grad_matches_oracle(brick, k, deterministic):
     g, torch = _lib()
     grid = F.Grid(30, 26, 22, 1, -3, 2)
     params = _case(40, grid, 10, scale_range=(0.8, 3.5))
     field = np.random.default_rng(11).uniform(-0.3, 1.0, size=grid.shape).astype(np.float32)
-    print(f"loss_grad k={k} B={brick}", flush=True)
-    L, grad = _loss_grad_gpu(g, torch, params, field, grid, k, brick)
+    print(f"loss_grad k={k} B={brick} det={deterministic}", flush=True)
+    L, grad = _loss_grad_gpu(g, torch, params, field, grid, k, brick, deterministic)
     Lr, gr = F.loss_grad(params, field.astype(np.float64), grid, k)
     assert abs(L - Lr) <= 1e-5 * Lr
     check_grad(grad, gr)
+
+
+def test_deterministic_gradient_is_bitwise_reproducible():
+    g, torch = _lib()
+    grid = F.Grid(40, 36, 44)
+    params = _case(120, grid, 13, scale_range=(0.8, 4.0))
+    field = np.random.default_rng(14).uniform(size=grid.shape).astype(np.float32)
+    L1, g1 = _loss_grad_gpu(g, torch, params, field, grid, 3.0, (8, 32), True)
+    L2, g2 = _loss_grad_gpu(g, torch, params, field, grid, 3.0, (8, 32), True)
+    assert L1 == L2 and np.array_equal(g1, g2)
 
 
 def test_loss_grad_tiny_workload():
@@ -184,7 +195,8 @@ def test_adam_step_matches_oracle():
     assert np.max(np.abs(got - ref)) < 1e-6 * (1 + np.max(np.abs(ref)))
 
 
-def test_refine_trajectory_matches_oracle():
+@pytest.mark.parametrize("deterministic", [True, False])
+def test_refine_trajectory_matches_oracle(deterministic):
     g, torch = _lib()
     grid = F.Grid(24, 24, 24)
     gen = S.random_params(12, 24, seed=21, scale_range=(1.5, 3.0))
@@ -193,7 +205,7 @@ def test_refine_trajectory_matches_oracle():
     start[0:3] += np.random.default_rng(1).normal(0, 0.5, size=(3, 12))
     start[10] *= 0.7
     start = start.astype(np.float32).astype(np.float64)
-    ctx = g.Context(k=3.0, brick=8, lr=1e-2)
+    ctx = g.Context(k=3.0, brick=8, lr=1e-2, deterministic=deterministic)
     p = g.Params(ctx, 12).upload(start.astype(np.float32))
     f = torch.from_numpy(field).cuda()
     losses = g.refine(ctx, p, f, g.Grid(24, 24, 24), 20)
