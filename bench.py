@@ -38,6 +38,27 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 METRIC = "fwd+bwd+Adam s/iter at 1024^3 x 1.4M Gaussians; time-to-PSNR warm vs plain"
 
 
+def measured_traffic(brick, brick_z, size, budget):
+    """HBM bytes per fused launch from the committed counter summary, if it was
+    taken on the current kernel source and this workload; else None."""
+    import glob
+    import hashlib
+
+    if (brick, brick_z, size, budget) != (8, 32, 1024, 1_400_000):
+        return None
+    src = os.path.join(ROOT, "paper_2608_14112_amd", "csrc", "field.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "k_fused_8x8x32_*counters.md")):
+        rec = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("|", "#", " ")):
+                key, _, val = line.partition(":")
+                rec[key.split(" (")[0].strip()] = val.strip()
+        if rec.get("kernel_source_sha256_16") == sha and "traffic_bytes_per_launch" in rec:
+            return int(rec["traffic_bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(field_t, params_np, size, k, block, seed):
     """Oracle (float64 NumPy, one core) on a block^3 sub-volume of the workload."""
     import numpy as np
@@ -166,7 +187,7 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(args.brick, args.brick_z, n, args.budget),
             "kernel": "k_fused",
             "kernel_ms": fused_ms,
             "flops_per_pair": FLOPS_PER_PAIR,

@@ -225,6 +225,61 @@ gve_status gve_set_timing(gve_ctx* ctx, int32_t enable);
 gve_status gve_count_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, int64_t* h_in_support,
                            int64_t* h_candidates);
 
+/*
+ * Learned warm start.  The paper has no learned component; this network and
+ * its inputs are defined by this library (readings of the shapes it is given):
+ * a multilayer perceptron 16 -> 128 -> 128 -> 11 with exact-erf GELU,
+ * evaluated and trained with bfloat16 operands on the matrix cores and float32
+ * accumulation, float32 master weights and Adam.  Inputs are 16 features per
+ * allocated primitive (gve_features), outputs a standardised correction of its
+ * 11 parameters.  The flat layout of gve_mlp_export is W1[128][16], b1[128],
+ * W2[128][128], b2[128], W3[11][128], b3[11] (GVE_MLP_NWEIGHT floats), then the
+ * feature mean[16] and std[16] and target mean[11] and std[11].
+ */
+#define GVE_MLP_NWEIGHT 20107
+#define GVE_MLP_NFLAT (GVE_MLP_NWEIGHT + 54)
+typedef struct gve_mlp gve_mlp;
+
+/* He-uniform weights from `seed`, zero biases, identity standardisation. */
+gve_status gve_mlp_create(gve_ctx* ctx, uint64_t seed, gve_mlp** out);
+gve_status gve_mlp_destroy(gve_mlp* m);
+/* Copy the network to / from a host array of GVE_MLP_NFLAT floats (synchronises). */
+gve_status gve_mlp_export(gve_ctx* ctx, const gve_mlp* m, float* h_flat);
+gve_status gve_mlp_import(gve_ctx* ctx, gve_mlp* m, const float* h_flat);
+/* Network on standardised inputs d_X [n][16] -> d_Y [n][11] (device, caller-owned). */
+gve_status gve_mlp_forward(gve_ctx* ctx, const gve_mlp* m, const float* d_X, int64_t n, float* d_Y);
+/* Mean squared error of the network on standardised (d_X, d_T) and its gradient
+ * d_grad [GVE_MLP_NWEIGHT] (device; may be NULL); *h_loss if not NULL. */
+gve_status gve_mlp_loss_grad(gve_ctx* ctx, const gve_mlp* m, const float* d_X, const float* d_T,
+                             int64_t n, float* d_grad, double* h_loss);
+/* Train on raw features d_X [n][16] and raw targets d_T [n][11]: sets the
+ * standardisation from the data, then `epochs` passes of Adam (lr) over
+ * shuffled mini-batches of `batch` rows (shuffle seeded by `seed`).
+ * h_epoch_loss (optional) receives the mean batch loss of every epoch. */
+gve_status gve_mlp_train(gve_ctx* ctx, gve_mlp* m, const float* d_X, const float* d_T, int64_t n,
+                         int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                         double* h_epoch_loss);
+/* Features of an allocated primitive set on its field (see gve_allocate:
+ * n_detail and g99 come from its gve_alloc_info): log1p of the 7^3
+ * structure-tensor eigenvalues / g99^2 at the seed voxel round(mu) (3), the
+ * eigenvectors e1, e2, e3 (9), |grad V| / g99 at the seed (1), mean and
+ * variance of V over the k-sigma box (2), detail flag (1).  d_X [n][16]. */
+gve_status gve_features(gve_ctx* ctx, const gve_params* p, const float* d_field, gve_grid g,
+                        int64_t n_detail, double g99, float* d_X);
+/* Training targets: refined - allocated parameters [n][11] with the refined
+ * quaternion normalised and sign-aligned to the allocated one. */
+gve_status gve_targets(gve_ctx* ctx, const gve_params* alloc, const gve_params* refined,
+                       float* d_T);
+/* Apply the network's correction to an allocated set: theta += alpha * delta
+ * for alpha in {1, 1/2, 1/4}; keeps the first alpha whose loss L on d_field is
+ * below the unchanged set's, otherwise leaves p unchanged (the plain
+ * allocation is the fallback).  *applied = 0 (fallback), 1, 2 or 3 (which
+ * alpha); h_losses (optional, 4 doubles) = L before and for each alpha tried
+ * (NaN if not tried).  Resets p's Adam state.  Synchronises. */
+gve_status gve_warmstart(gve_ctx* ctx, const gve_mlp* m, gve_params* p, const float* d_field,
+                         gve_grid g, int64_t n_detail, double g99, int32_t* applied,
+                         double* h_losses);
+
 /* Counters of the last call (see gve_stats). */
 gve_status gve_get_stats(const gve_ctx* ctx, gve_stats* out);
 

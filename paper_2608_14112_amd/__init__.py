@@ -104,6 +104,18 @@ _SIGS = {
                      ctypes.POINTER(AllocInfoC)],
     "gve_normalize": [_vp, _vp, _i64],
     "gve_set_timing": [_vp, ctypes.c_int32],
+    "gve_mlp_create": [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)],
+    "gve_mlp_destroy": [_vp],
+    "gve_mlp_export": [_vp, _vp, _vp],
+    "gve_mlp_import": [_vp, _vp, _vp],
+    "gve_mlp_forward": [_vp, _vp, _vp, _i64, _vp],
+    "gve_mlp_loss_grad": [_vp, _vp, _vp, _vp, _i64, _vp, ctypes.POINTER(ctypes.c_double)],
+    "gve_mlp_train": [_vp, _vp, _vp, _vp, _i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                      ctypes.c_uint64, _vp],
+    "gve_features": [_vp, _vp, _vp, GridC, _i64, ctypes.c_double, _vp],
+    "gve_targets": [_vp, _vp, _vp, _vp],
+    "gve_warmstart": [_vp, _vp, _vp, _vp, GridC, _i64, ctypes.c_double,
+                      ctypes.POINTER(ctypes.c_int32), _vp],
     "gve_count_pairs": [_vp, _vp, GridC, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
 }
 for _name, _args in _SIGS.items():
@@ -365,3 +377,126 @@ def count_pairs(ctx: Context, params: Params, grid: Grid):
     _check(_lib.gve_count_pairs(ctx.handle, params.handle, grid.c(), ctypes.byref(a),
                                 ctypes.byref(b)), ctx.handle)
     return a.value, b.value
+
+
+MLP_NWEIGHT = 20107
+MLP_NFLAT = MLP_NWEIGHT + 54
+MLP_LAYOUT = (("W1", (128, 16)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)),
+              ("W3", (11, 128)), ("b3", (11,)))
+
+
+class MLP:
+    """The warm-start network (gve_mlp): 16 -> 128 -> 128 -> 11, GELU."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        self.ctx = ctx
+        h = _vp()
+        _check(_lib.gve_mlp_create(ctx.handle, ctypes.c_uint64(int(seed)), ctypes.byref(h)),
+               ctx.handle)
+        self.handle = h
+
+    def export(self):
+        """Flat float32 array: weights (MLP_LAYOUT order) then feature/target mean and std."""
+        a = np.empty(MLP_NFLAT, dtype=np.float32)
+        _check(_lib.gve_mlp_export(self.ctx.handle, self.handle, a.ctypes.data_as(_vp)),
+               self.ctx.handle)
+        return a
+
+    def load(self, flat):
+        a = np.ascontiguousarray(np.asarray(flat, dtype=np.float32).reshape(MLP_NFLAT))
+        _check(_lib.gve_mlp_import(self.ctx.handle, self.handle, a.ctypes.data_as(_vp)),
+               self.ctx.handle)
+
+    def tensors(self):
+        """Weights as a dict of float64 arrays plus the standardisation statistics."""
+        a = self.export().astype(np.float64)
+        out, off = {}, 0
+        for name, shape in MLP_LAYOUT:
+            size = int(np.prod(shape))
+            out[name] = a[off:off + size].reshape(shape)
+            off += size
+        st = a[MLP_NWEIGHT:]
+        out["fmean"], out["fstd"], out["tmean"], out["tstd"] = st[:16], st[16:32], st[32:43], st[43:]
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gve_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mlp_forward(ctx: Context, mlp: MLP, X):
+    """gve_mlp_forward on standardised X (float32 cuda [n, 16]) -> [n, 11]."""
+    import torch
+
+    n = X.shape[0]
+    Y = torch.empty((n, 11), device=X.device, dtype=torch.float32)
+    _check(_lib.gve_mlp_forward(ctx.handle, mlp.handle, _ptr(X, torch.float32, n * 16), _i64(n),
+                                _ptr(Y)), ctx.handle)
+    return Y
+
+
+def mlp_loss_grad(ctx: Context, mlp: MLP, X, T):
+    """gve_mlp_loss_grad: (loss, flat gradient [MLP_NWEIGHT] cuda tensor)."""
+    import torch
+
+    n = X.shape[0]
+    g = torch.empty(MLP_NWEIGHT, device=X.device, dtype=torch.float32)
+    L = ctypes.c_double()
+    _check(_lib.gve_mlp_loss_grad(ctx.handle, mlp.handle, _ptr(X, torch.float32, n * 16),
+                                  _ptr(T, torch.float32, n * 11), _i64(n), _ptr(g),
+                                  ctypes.byref(L)), ctx.handle)
+    return L.value, g
+
+
+def mlp_train(ctx: Context, mlp: MLP, X, T, epochs, batch=4096, lr=1e-3, seed=0):
+    """gve_mlp_train on raw features / targets; returns the per-epoch mean loss."""
+    import torch
+
+    n = X.shape[0]
+    hist = np.zeros(max(int(epochs), 1))
+    _check(_lib.gve_mlp_train(ctx.handle, mlp.handle, _ptr(X, torch.float32, n * 16),
+                              _ptr(T, torch.float32, n * 11), _i64(n), ctypes.c_int32(int(epochs)),
+                              ctypes.c_int32(int(batch)), ctypes.c_float(lr),
+                              ctypes.c_uint64(int(seed)), hist.ctypes.data_as(_vp)), ctx.handle)
+    return hist[:epochs]
+
+
+def features(ctx: Context, params: Params, field, grid: Grid, n_detail: int, g99: float):
+    """gve_features -> float32 cuda [n, 16]."""
+    import torch
+
+    X = torch.empty((params.n, 16), device=field.device, dtype=torch.float32)
+    _check(_lib.gve_features(ctx.handle, params.handle,
+                             _ptr(field, torch.float32, grid.nx * grid.ny * grid.nz), grid.c(),
+                             _i64(int(n_detail)), ctypes.c_double(float(g99)), _ptr(X)), ctx.handle)
+    return X
+
+
+def targets(ctx: Context, alloc: Params, refined: Params, device="cuda"):
+    """gve_targets -> float32 cuda [n, 11]."""
+    import torch
+
+    T = torch.empty((alloc.n, 11), device=device, dtype=torch.float32)
+    _check(_lib.gve_targets(ctx.handle, alloc.handle, refined.handle, _ptr(T)), ctx.handle)
+    return T
+
+
+def warmstart(ctx: Context, mlp: MLP, params: Params, field, grid: Grid, n_detail: int,
+              g99: float):
+    """gve_warmstart: returns (applied, losses[4])."""
+    import torch
+
+    applied = ctypes.c_int32()
+    L = np.zeros(4)
+    _check(_lib.gve_warmstart(ctx.handle, mlp.handle, params.handle,
+                              _ptr(field, torch.float32, grid.nx * grid.ny * grid.nz), grid.c(),
+                              _i64(int(n_detail)), ctypes.c_double(float(g99)),
+                              ctypes.byref(applied), L.ctypes.data_as(_vp)), ctx.handle)
+    return applied.value, L

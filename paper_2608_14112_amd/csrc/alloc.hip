@@ -21,6 +21,7 @@
 //   weights             : one truncated evaluation U = sum a_i G_i, then
 //                         kappa = <U, V> / <U, U> scales every weight.
 #include "common.h"
+#include "devmath.h"
 
 namespace gve {
 namespace {
@@ -44,34 +45,6 @@ __device__ inline uint64_t hash_bits(uint64_t seed, uint64_t stream, uint64_t id
 // (top 53 bits + 1) * 2^-53: uniform in (0, 1], exact in double.
 __device__ inline double uniform01(uint64_t seed, uint64_t stream, uint64_t idx) {
   return (double)((hash_bits(seed, stream, idx) >> 11) + 1ull) * 0x1.0p-53;
-}
-
-struct Dims {
-  int64_t nx, ny, nz;
-};
-
-__device__ inline float half_diff(const float* __restrict__ f, int64_t v, int64_t i, int64_t n,
-                                  int64_t stride) {
-  if (n == 1) return 0.0f;
-  if (i == 0) return f[v + stride] - f[v];
-  if (i == n - 1) return f[v] - f[v - stride];
-  return 0.5f * (f[v + stride] - f[v - stride]);
-}
-
-__device__ inline void grad_parts(const float* __restrict__ f, Dims d, int64_t i, int64_t j,
-                                  int64_t k, float* gx, float* gy, float* gz) {
-  const int64_t v = i + d.nx * (j + d.ny * k);
-  *gx = half_diff(f, v, i, d.nx, 1);
-  *gy = half_diff(f, v, j, d.ny, d.nx);
-  *gz = half_diff(f, v, k, d.nz, d.nx * d.ny);
-}
-
-__device__ inline float grad_mag32(const float* __restrict__ f, Dims d, int64_t v) {
-  const int64_t i = v % d.nx, j = (v / d.nx) % d.ny, k = v / (d.nx * d.ny);
-  float gx, gy, gz;
-  grad_parts(f, d, i, j, k, &gx, &gy, &gz);
-  const double x = gx, y = gy, z = gz;
-  return (float)sqrt((x * x + y * y) + z * z);
 }
 
 template <typename T>
@@ -309,38 +282,6 @@ __global__ __launch_bounds__(1024) void k_median(const double* __restrict__ best
       __syncthreads();
     }
   if (threadIdx.x == 0) *out = (m >= 1) ? sqrt(v[(m - 1) / 2]) : 1.0;
-}
-
-// Cyclic Jacobi on a symmetric 3x3 matrix (double); eigenvectors in V's columns.
-__device__ inline void jacobi3(double A[3][3], double V[3][3]) {
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) V[a][b] = (a == b) ? 1.0 : 0.0;
-  for (int sweep = 0; sweep < 32; ++sweep) {
-    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
-    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
-    if (off <= 1e-32 * dia || off == 0.0) break;
-    for (int pq = 0; pq < 3; ++pq) {
-      const int p = (pq == 2) ? 1 : 0;
-      const int q = (pq == 0) ? 1 : 2;
-      const double apq = A[p][q];
-      if (apq == 0.0) continue;
-      const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
-      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-      A[p][p] -= t * apq;
-      A[q][q] += t * apq;
-      A[p][q] = A[q][p] = 0.0;
-      const int r = 3 - p - q;
-      const double arp = A[r][p], arq = A[r][q];
-      A[r][p] = A[p][r] = c * arp - s * arq;
-      A[r][q] = A[q][r] = s * arp + c * arq;
-      for (int k = 0; k < 3; ++k) {
-        const double vp = V[k][p], vq = V[k][q];
-        V[k][p] = c * vp - s * vq;
-        V[k][q] = s * vp + c * vq;
-      }
-    }
-  }
 }
 
 __device__ inline void quat_from_R(const double R[3][3], double q[4]) {

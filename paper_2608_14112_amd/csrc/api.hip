@@ -1,10 +1,12 @@
 // C ABI of libgve.so: argument validation, device memory, and the order in
 // which the binning, field and update kernels are queued on the caller's
 // stream.  Declarations and contracts are in include/gve.h.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "common.h"
 
@@ -297,7 +299,8 @@ gve_status gve_destroy(gve_ctx* ctx) {
   auto& ws = ctx->ws;
   Scratch* all[] = {&ws.keys[0], &ws.keys[1], &ws.vals[0], &ws.vals[1], &ws.brick_start,
                     &ws.brick_loss, &ws.scan_tmp, &ws.sort_hist, &ws.dloss, &ws.clamp_count,
-                    &ws.grad_tmp, &ws.alloc, &ws.voxf, &ws.partials};
+                    &ws.grad_tmp, &ws.alloc, &ws.voxf, &ws.partials, &ws.mlp,
+                    &ws.sat, &ws.feat, &ws.theta_base};
   for (Scratch* s : all)
     if (s->ptr) hipFree(s->ptr);
   if (ws.h_pinned) hipHostFree(ws.h_pinned);
@@ -717,6 +720,367 @@ gve_status gve_allocate(gve_ctx* ctx, const float* d_field, gve_grid g, int64_t 
 gve_status gve_get_stats(const gve_ctx* ctx, gve_stats* out) {
   if (!ctx || !out) return GVE_ERR_INVALID_ARGUMENT;
   *out = ctx->stats;
+  return GVE_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Learned warm start
+// ===========================================================================
+
+struct gve_mlp {
+  int device = 0;
+  float* w = nullptr;      // [GVE_MLP_NWEIGHT] float32 master weights
+  float* m = nullptr;      // Adam moments
+  float* v = nullptr;
+  float* stats = nullptr;  // fmean[16] fstd[16] tmean[11] tstd[11]
+  int64_t t = 0;
+};
+
+namespace {
+
+constexpr int kDin = 16, kDh = 128, kDout = 11;
+constexpr int64_t kW1 = 0, kB1 = 2048, kW2 = 2176, kB2 = 18560, kW3 = 18688, kB3 = 20096;
+constexpr int64_t kMlpRows = 65536;  // rows per forward / backward chunk
+static_assert(kB3 + kDout == GVE_MLP_NWEIGHT, "weight layout");
+
+struct MlpBuf {
+  float *Xs, *Ts, *Z1, *H1, *Z2, *H2, *Y, *dY, *grad, *split;
+  size_t split_floats;
+  double *part, *acc;
+};
+
+gve_status mlp_buffers(gve_ctx* ctx, int64_t rows, int64_t nacc, MlpBuf* b) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t r = (size_t)rows;
+  const size_t split_floats = (size_t)((rows + 511) / 512) * kDh * kDh;
+  const size_t oXs = take(4 * r * kDin), oTs = take(4 * r * kDout), oZ1 = take(4 * r * kDh),
+               oH1 = take(4 * r * kDh), oZ2 = take(4 * r * kDh), oH2 = take(4 * r * kDh),
+               oY = take(4 * r * kDout), odY = take(4 * r * kDout), og = take(4 * GVE_MLP_NWEIGHT),
+               osp = take(4 * split_floats), opart = take(8 * 64), oacc = take(8 * (size_t)nacc);
+  TRY(ensure(ctx, ctx->ws.mlp, off));
+  char* base = static_cast<char*>(ctx->ws.mlp.ptr);
+  auto F32 = [&](size_t o) { return reinterpret_cast<float*>(base + o); };
+  b->Xs = F32(oXs); b->Ts = F32(oTs); b->Z1 = F32(oZ1); b->H1 = F32(oH1); b->Z2 = F32(oZ2);
+  b->H2 = F32(oH2); b->Y = F32(oY); b->dY = F32(odY); b->grad = F32(og); b->split = F32(osp);
+  b->split_floats = split_floats;
+  b->part = reinterpret_cast<double*>(base + opart);
+  b->acc = reinterpret_cast<double*>(base + oacc);
+  return GVE_OK;
+}
+
+// Y = network(Xs) for `rows` standardised inputs; activations kept in b.
+gve_status mlp_fwd(gve_ctx* ctx, const gve_mlp* m, const float* Xs, int64_t rows, MlpBuf& b,
+                   float* Y) {
+  hipStream_t s = ctx->stream;
+  const int R = (int)rows;
+  TRY_HIP(ctx, gve::mlp_gemm(false, true, 1, R, kDh, kDin, Xs, kDin, m->w + kW1, kDin, b.Z1, kDh,
+                             m->w + kB1, b.H1, nullptr, 0, s));
+  TRY_HIP(ctx, gve::mlp_gemm(false, true, 1, R, kDh, kDh, b.H1, kDh, m->w + kW2, kDh, b.Z2, kDh,
+                             m->w + kB2, b.H2, nullptr, 0, s));
+  TRY_HIP(ctx, gve::mlp_gemm(false, true, 0, R, kDout, kDh, b.H2, kDh, m->w + kW3, kDh, Y, kDout,
+                             m->w + kB3, nullptr, nullptr, 0, s));
+  return GVE_OK;
+}
+
+// Gradients of the mean squared error into b.grad, given b.dY (= dL/dY).
+gve_status mlp_bwd(gve_ctx* ctx, const gve_mlp* m, const float* Xs, int64_t rows, MlpBuf& b) {
+  hipStream_t s = ctx->stream;
+  const int R = (int)rows;
+  float* g = b.grad;
+  TRY_HIP(ctx, gve::mlp_gemm(true, false, 0, kDout, kDh, R, b.dY, kDout, b.H2, kDh, g + kW3, kDh,
+                             nullptr, nullptr, b.split, b.split_floats, s));
+  TRY_HIP(ctx, gve::mlp_colsum(b.dY, R, kDout, g + kB3, s));
+  // dH2 reuses H2's buffer after dW3 has consumed it (stream order)
+  float* dH2 = b.H2;
+  TRY_HIP(ctx, gve::mlp_gemm(false, false, 0, R, kDh, kDout, b.dY, kDout, m->w + kW3, kDh, dH2, kDh,
+                             nullptr, nullptr, nullptr, 0, s));
+  TRY_HIP(ctx, gve::mlp_gelu_back(dH2, b.Z2, rows * kDh, s));
+  TRY_HIP(ctx, gve::mlp_gemm(true, false, 0, kDh, kDh, R, dH2, kDh, b.H1, kDh, g + kW2, kDh,
+                             nullptr, nullptr, b.split, b.split_floats, s));
+  TRY_HIP(ctx, gve::mlp_colsum(dH2, R, kDh, g + kB2, s));
+  float* dH1 = b.H1;
+  TRY_HIP(ctx, gve::mlp_gemm(false, false, 0, R, kDh, kDh, dH2, kDh, m->w + kW2, kDh, dH1, kDh,
+                             nullptr, nullptr, nullptr, 0, s));
+  TRY_HIP(ctx, gve::mlp_gelu_back(dH1, b.Z1, rows * kDh, s));
+  TRY_HIP(ctx, gve::mlp_gemm(true, false, 0, kDh, kDin, R, dH1, kDh, Xs, kDin, g + kW1, kDin,
+                             nullptr, nullptr, b.split, b.split_floats, s));
+  TRY_HIP(ctx, gve::mlp_colsum(dH1, R, kDh, g + kB1, s));
+  return GVE_OK;
+}
+
+uint64_t host_mix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Loss L of p on the field (forward + fused pass), read back to the host.
+gve_status eval_loss(gve_ctx* ctx, const gve_params* p, const float* d_field, const gve_grid& g,
+                     double* out) {
+  double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
+  float* part = nullptr;
+  TRY(loss_and_sums(ctx, p, d_field, g, dl, &part));
+  if (!part) TRY_HIP(ctx, gve::fill_f32(const_cast<gve_params*>(p)->acc, 10 * p->n, 0.0f, ctx->stream));
+  TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, dl, sizeof(double), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *out = *static_cast<double*>(ctx->ws.h_pinned);
+  return GVE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gve_status gve_mlp_create(gve_ctx* ctx, uint64_t seed, gve_mlp** out) {
+  if (!ctx || !out) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  TRY(set_device(ctx));
+  gve_mlp* m = new (std::nothrow) gve_mlp();
+  if (!m) return GVE_ERR_OUT_OF_MEMORY;
+  m->device = ctx->device;
+  hipError_t e = hipMalloc(&m->w, sizeof(float) * GVE_MLP_NWEIGHT);
+  if (e == hipSuccess) e = hipMalloc(&m->m, sizeof(float) * GVE_MLP_NWEIGHT);
+  if (e == hipSuccess) e = hipMalloc(&m->v, sizeof(float) * GVE_MLP_NWEIGHT);
+  if (e == hipSuccess) e = hipMalloc(&m->stats, sizeof(float) * 54);
+  if (e != hipSuccess) {
+    gve_mlp_destroy(m);
+    return from_hip(ctx, e, "gve_mlp_create");
+  }
+  std::vector<float> h(GVE_MLP_NFLAT, 0.0f);
+  // He-uniform: U(-b, b), b = sqrt(6 / fan_in); uniform from a counter hash
+  auto fill = [&](int64_t off, int64_t count, int fan_in, uint64_t stream) {
+    const double bnd = std::sqrt(6.0 / fan_in);
+    for (int64_t i = 0; i < count; ++i) {
+      const uint64_t r = host_mix64(host_mix64(seed ^ (stream * 0xD1B54A32D192ED03ull)) ^ (uint64_t)i);
+      const double u = (double)((r >> 11) + 1) * 0x1.0p-53;
+      h[off + i] = (float)((2.0 * u - 1.0) * bnd);
+    }
+  };
+  fill(kW1, kB1 - kW1, kDin, 11);
+  fill(kW2, kB2 - kW2, kDh, 12);
+  fill(kW3, kB3 - kW3, kDh, 13);
+  for (int c = 0; c < 16; ++c) h[GVE_MLP_NWEIGHT + 16 + c] = 1.0f;
+  for (int c = 0; c < 11; ++c) h[GVE_MLP_NWEIGHT + 32 + 11 + c] = 1.0f;
+  *out = m;
+  const gve_status st = gve_mlp_import(ctx, m, h.data());
+  if (st != GVE_OK) {
+    gve_mlp_destroy(m);
+    *out = nullptr;
+  }
+  return st;
+}
+
+gve_status gve_mlp_destroy(gve_mlp* m) {
+  if (!m) return GVE_ERR_INVALID_ARGUMENT;
+  hipSetDevice(m->device);
+  hipDeviceSynchronize();
+  void* bufs[] = {m->w, m->m, m->v, m->stats};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  delete m;
+  return GVE_OK;
+}
+
+gve_status gve_mlp_export(gve_ctx* ctx, const gve_mlp* m, float* h_flat) {
+  if (!ctx || !m || !h_flat) return GVE_ERR_INVALID_ARGUMENT;
+  TRY(set_device(ctx));
+  TRY_HIP(ctx, hipMemcpyAsync(h_flat, m->w, sizeof(float) * GVE_MLP_NWEIGHT,
+                              hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipMemcpyAsync(h_flat + GVE_MLP_NWEIGHT, m->stats, sizeof(float) * 54,
+                              hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return GVE_OK;
+}
+
+gve_status gve_mlp_import(gve_ctx* ctx, gve_mlp* m, const float* h_flat) {
+  if (!ctx || !m || !h_flat) return GVE_ERR_INVALID_ARGUMENT;
+  TRY(set_device(ctx));
+  TRY_HIP(ctx, hipMemcpyAsync(m->w, h_flat, sizeof(float) * GVE_MLP_NWEIGHT,
+                              hipMemcpyHostToDevice, ctx->stream));
+  TRY_HIP(ctx, hipMemcpyAsync(m->stats, h_flat + GVE_MLP_NWEIGHT, sizeof(float) * 54,
+                              hipMemcpyHostToDevice, ctx->stream));
+  TRY_HIP(ctx, gve::fill_f32(m->m, GVE_MLP_NWEIGHT, 0.0f, ctx->stream));
+  TRY_HIP(ctx, gve::fill_f32(m->v, GVE_MLP_NWEIGHT, 0.0f, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  m->t = 0;
+  return GVE_OK;
+}
+
+gve_status gve_mlp_forward(gve_ctx* ctx, const gve_mlp* m, const float* d_X, int64_t n, float* d_Y) {
+  if (!ctx || !m) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  if (!d_X || !d_Y || n < 1) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "need d_X, d_Y and n >= 1");
+  TRY(set_device(ctx));
+  MlpBuf b;
+  TRY(mlp_buffers(ctx, std::min(n, kMlpRows), 1, &b));
+  for (int64_t r0 = 0; r0 < n; r0 += kMlpRows) {
+    const int64_t rows = std::min(kMlpRows, n - r0);
+    TRY(mlp_fwd(ctx, m, d_X + r0 * kDin, rows, b, d_Y + r0 * kDout));
+  }
+  return GVE_OK;
+}
+
+gve_status gve_mlp_loss_grad(gve_ctx* ctx, const gve_mlp* m, const float* d_X, const float* d_T,
+                             int64_t n, float* d_grad, double* h_loss) {
+  if (!ctx || !m) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  if (!d_X || !d_T || n < 1) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "need d_X, d_T and n >= 1");
+  if (n > kMlpRows) return fail(ctx, GVE_ERR_UNSUPPORTED, "at most 65536 rows per call");
+  TRY(set_device(ctx));
+  MlpBuf b;
+  TRY(mlp_buffers(ctx, n, 1, &b));
+  hipStream_t s = ctx->stream;
+  TRY(mlp_fwd(ctx, m, d_X, n, b, b.Y));
+  const double inv = 1.0 / ((double)n * kDout);
+  TRY_HIP(ctx, gve::fill_u64(reinterpret_cast<unsigned long long*>(b.acc), 1, s));
+  TRY_HIP(ctx, gve::mlp_mse_grad(b.Y, d_T, n * kDout, (float)inv, b.dY, b.part, b.acc, inv, s));
+  if (d_grad) {
+    TRY(mlp_bwd(ctx, m, d_X, n, b));
+    TRY_HIP(ctx, hipMemcpyAsync(d_grad, b.grad, sizeof(float) * GVE_MLP_NWEIGHT,
+                                hipMemcpyDeviceToDevice, s));
+  }
+  if (h_loss) {
+    TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, b.acc, 8, hipMemcpyDeviceToHost, s));
+    TRY_HIP(ctx, hipStreamSynchronize(s));
+    *h_loss = *static_cast<double*>(ctx->ws.h_pinned);
+  }
+  return GVE_OK;
+}
+
+gve_status gve_mlp_train(gve_ctx* ctx, gve_mlp* m, const float* d_X, const float* d_T, int64_t n,
+                         int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                         double* h_epoch_loss) {
+  if (!ctx || !m) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  if (!d_X || !d_T || n < 1 || epochs < 0 || batch < 1 || batch > kMlpRows || !(lr >= 0.0f) ||
+      n >= ((int64_t)1 << 31))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT,
+                "need d_X, d_T, 1 <= n < 2^31, epochs >= 0, 1 <= batch <= 65536, lr >= 0");
+  TRY(set_device(ctx));
+  hipStream_t s = ctx->stream;
+  MlpBuf b;
+  TRY(mlp_buffers(ctx, batch, std::max(epochs, 1), &b));
+  float* fmean = m->stats;
+  float* fstd = m->stats + 16;
+  float* tmean = m->stats + 32;
+  float* tstd = m->stats + 43;
+  TRY_HIP(ctx, gve::mlp_colstats(d_X, n, kDin, fmean, fstd, s));
+  TRY_HIP(ctx, gve::mlp_colstats(d_T, n, kDout, tmean, tstd, s));
+  TRY_HIP(ctx, gve::fill_u64(reinterpret_cast<unsigned long long*>(b.acc), std::max(epochs, 1), s));
+  // shuffle buffers: the pair ping-pong buffers of the binning are reused
+  auto& ws = ctx->ws;
+  for (int i = 0; i < 2; ++i) {
+    TRY(ensure(ctx, ws.keys[i], sizeof(uint32_t) * (size_t)n));
+    TRY(ensure(ctx, ws.vals[i], sizeof(uint32_t) * (size_t)n));
+  }
+  TRY(ensure(ctx, ws.sort_hist, gve::sort_hist_bytes(n)));
+  uint32_t* keys[2] = {static_cast<uint32_t*>(ws.keys[0].ptr), static_cast<uint32_t*>(ws.keys[1].ptr)};
+  uint32_t* vals[2] = {static_cast<uint32_t*>(ws.vals[0].ptr), static_cast<uint32_t*>(ws.vals[1].ptr)};
+  const int64_t nb = (n + batch - 1) / batch;
+  for (int32_t ep = 0; ep < epochs; ++ep) {
+    TRY_HIP(ctx, gve::mlp_perm_keys(keys[0], vals[0], n, seed, (uint64_t)ep, s));
+    int which = 0;
+    TRY_HIP(ctx, gve::radix_sort_pairs(keys, vals, n, 32, ws.sort_hist.ptr, &which, s));
+    const uint32_t* perm = vals[which];
+    for (int64_t bi = 0; bi < nb; ++bi) {
+      const int64_t r0 = bi * batch;
+      const int64_t rows = std::min((int64_t)batch, n - r0);
+      TRY_HIP(ctx, gve::mlp_standardize(d_X, perm + r0, rows, kDin, fmean, fstd, b.Xs, s));
+      TRY_HIP(ctx, gve::mlp_standardize(d_T, perm + r0, rows, kDout, tmean, tstd, b.Ts, s));
+      TRY(mlp_fwd(ctx, m, b.Xs, rows, b, b.Y));
+      const double inv = 1.0 / ((double)rows * kDout);
+      TRY_HIP(ctx, gve::mlp_mse_grad(b.Y, b.Ts, rows * kDout, (float)inv, b.dY, b.part, b.acc + ep,
+                                     inv / (double)nb, s));
+      TRY(mlp_bwd(ctx, m, b.Xs, rows, b));
+      m->t += 1;
+      TRY_HIP(ctx, gve::mlp_adam(m->w, m->m, m->v, b.grad, GVE_MLP_NWEIGHT, lr, 0.9f, 0.999f, 1e-8f,
+                                 m->t, s));
+    }
+  }
+  if (h_epoch_loss && epochs > 0) {
+    TRY_HIP(ctx, hipMemcpyAsync(h_epoch_loss, b.acc, sizeof(double) * (size_t)epochs,
+                                hipMemcpyDeviceToHost, s));
+  }
+  TRY_HIP(ctx, hipStreamSynchronize(s));
+  return GVE_OK;
+}
+
+gve_status gve_features(gve_ctx* ctx, const gve_params* p, const float* d_field, gve_grid g,
+                        int64_t n_detail, double g99, float* d_X) {
+  TRY(check_ctx_params(ctx, p));
+  if (!d_field || !d_X) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "d_field and d_X are required");
+  if (n_detail < 0 || n_detail > p->n || !(g99 >= 0.0))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "need 0 <= n_detail <= n and g99 >= 0");
+  TRY(validate_grid(ctx, g));
+  TRY(set_device(ctx));
+  const int64_t M = g.nx * g.ny * g.nz;
+  TRY(ensure(ctx, ctx->ws.sat, 2 * sizeof(double) * (size_t)M));
+  double* s1 = static_cast<double*>(ctx->ws.sat.ptr);
+  double* s2 = s1 + M;
+  TRY_HIP(ctx, gve::mlp_sat(d_field, g, s1, s2, ctx->stream));
+  TRY_HIP(ctx, gve::mlp_features(d_field, p->theta, p->n, n_detail, g, g99, ctx->opt.k, s1, s2, d_X,
+                                 ctx->stream));
+  return GVE_OK;
+}
+
+gve_status gve_targets(gve_ctx* ctx, const gve_params* alloc, const gve_params* refined,
+                       float* d_T) {
+  TRY(check_ctx_params(ctx, alloc));
+  if (!refined || !d_T) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "refined and d_T are required");
+  if (refined->n != alloc->n) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "sizes differ");
+  TRY(set_device(ctx));
+  TRY_HIP(ctx, gve::mlp_targets(alloc->theta, refined->theta, alloc->n, d_T, ctx->stream));
+  return GVE_OK;
+}
+
+gve_status gve_warmstart(gve_ctx* ctx, const gve_mlp* m, gve_params* p, const float* d_field,
+                         gve_grid g, int64_t n_detail, double g99, int32_t* applied,
+                         double* h_losses) {
+  TRY(check_ctx_params(ctx, p));
+  if (!m || !d_field || !applied)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "network, field and applied are required");
+  TRY(validate_grid(ctx, g));
+  TRY(set_device(ctx));
+  hipStream_t s = ctx->stream;
+  const int64_t n = p->n;
+  TRY(ensure_dloss(ctx));
+  TRY(ensure(ctx, ctx->ws.feat, sizeof(float) * (size_t)n * (kDin + kDout)));
+  TRY(ensure(ctx, ctx->ws.theta_base, sizeof(float) * 11 * (size_t)n));
+  float* X = static_cast<float*>(ctx->ws.feat.ptr);
+  float* Y = X + (size_t)n * kDin;
+  float* base = static_cast<float*>(ctx->ws.theta_base.ptr);
+  TRY(gve_features(ctx, p, d_field, g, n_detail, g99, X));
+  TRY_HIP(ctx, gve::mlp_standardize(X, nullptr, n, kDin, m->stats, m->stats + 16, X, s));
+  TRY(gve_mlp_forward(ctx, m, X, n, Y));
+  TRY_HIP(ctx, hipMemcpyAsync(base, p->theta, sizeof(float) * 11 * (size_t)n,
+                              hipMemcpyDeviceToDevice, s));
+  double L[4] = {NAN, NAN, NAN, NAN};
+  TRY(eval_loss(ctx, p, d_field, g, &L[0]));
+  const float alphas[3] = {1.0f, 0.5f, 0.25f};
+  int32_t chosen = 0;
+  for (int a = 0; a < 3 && !chosen; ++a) {
+    TRY_HIP(ctx, gve::mlp_apply_delta(p->theta, base, Y, n, m->stats + 32, m->stats + 43,
+                                      alphas[a], s));
+    TRY(eval_loss(ctx, p, d_field, g, &L[a + 1]));
+    if (std::isfinite(L[a + 1]) && L[a + 1] < L[0]) chosen = a + 1;
+  }
+  if (!chosen)
+    TRY_HIP(ctx, hipMemcpyAsync(p->theta, base, sizeof(float) * 11 * (size_t)n,
+                                hipMemcpyDeviceToDevice, s));
+  TRY(gve_params_reset_adam(ctx, p));
+  TRY_HIP(ctx, hipStreamSynchronize(s));
+  *applied = chosen;
+  if (h_losses)
+    for (int i = 0; i < 4; ++i) h_losses[i] = L[i];
   return GVE_OK;
 }
 

@@ -51,6 +51,10 @@ struct Workspace {
   Scratch alloc;                 // allocation scratch (block counts, indices, states)
   Scratch voxf;                  // float [M] gradient magnitude, then U
   Scratch partials;              // float [T][10] per-(primitive, brick) gradient sums
+  Scratch mlp;                   // warm-start network activations and gradients
+  Scratch sat;                   // double [2][M] summed-area tables of V and V^2
+  Scratch feat;                  // float [n][16] features, then [n][11] network output
+  Scratch theta_base;            // float [11][n] parameters before the warm start
   void* h_pinned = nullptr;      // pinned host staging (64 bytes)
 };
 
@@ -164,6 +168,30 @@ hipError_t alloc_weights(const float* U, const float* f, int64_t M, float* c_row
                          double* tmp, hipStream_t s);
 size_t normalize_tmp_floats();
 hipError_t normalize_field(float* f, int64_t M, float* tmp, hipStream_t s);
+
+// ---- warm-start network (mlp.hip) --------------------------------------------
+hipError_t mlp_gemm(bool ta, bool tb, int epi, int M, int N, int K, const float* A, int lda,
+                    const float* B, int ldb, float* C, int ldc, const float* bias, float* C2,
+                    float* split_tmp, size_t split_tmp_floats, hipStream_t s);
+hipError_t mlp_gelu_back(float* dH, const float* Z, int64_t n, hipStream_t s);
+hipError_t mlp_colsum(const float* X, int rows, int cols, float* out, hipStream_t s);
+hipError_t mlp_mse_grad(const float* Y, const float* T, int64_t n, float scale, float* dY,
+                        double* part, double* acc_out, double acc_scale, hipStream_t s);
+hipError_t mlp_adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1,
+                    float b2, float eps, int64_t t, hipStream_t s);
+hipError_t mlp_colstats(const float* X, int64_t rows, int cols, float* mean, float* stdv,
+                        hipStream_t s);
+hipError_t mlp_standardize(const float* X, const uint32_t* perm, int64_t rows, int cols,
+                           const float* mean, const float* stdv, float* out, hipStream_t s);
+hipError_t mlp_perm_keys(uint32_t* keys, uint32_t* vals, int64_t n, uint64_t seed, uint64_t epoch,
+                         hipStream_t s);
+hipError_t mlp_sat(const float* f, const gve_grid& g, double* s1, double* s2, hipStream_t s);
+hipError_t mlp_features(const float* f, const float* theta, int64_t n, int64_t n_detail,
+                        const gve_grid& g, double g99, float k, const double* s1, const double* s2,
+                        float* X, hipStream_t s);
+hipError_t mlp_targets(const float* ta, const float* tr, int64_t n, float* T, hipStream_t s);
+hipError_t mlp_apply_delta(float* theta, const float* base, const float* Y, int64_t n,
+                           const float* tmean, const float* tstd, float alpha, hipStream_t s);
 
 // mode 0: chain rule -> grad_out ([11][n]); mode 1: chain rule + Adam;
 // mode 2: Adam from grad_in.  In modes 0 and 1 the ten sums come from acc
