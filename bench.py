@@ -83,6 +83,102 @@ def cpu_baseline(field_t, params_np, size, k, block, seed):
     return dt, pairs, int(keep.sum())
 
 
+def warm_start_bench(args):
+    """Time-to-PSNR of warm-started vs plain refinement at equal final PSNR.
+
+    Training pairs (allocation -> refined) come from the encoder itself on the
+    tiny mixture (64^3, 2,048 Gaussians, 20 iterations, lr 1e-3), mid spectral
+    fields (256^3, 65,536 Gaussians) and the paper-scale fronts field (1024^3,
+    1.4M Gaussians); the evaluation uses unseen-seed 512^3 fronts fields with
+    262,144 Gaussians.  Both arms start from the same allocation; the warm arm's
+    time includes features, network inference and the fallback check.
+    """
+    import numpy as np
+    import torch
+
+    import paper_2608_14112_amd as g
+    import paper_2608_14112_amd.warm as W
+    from synth import fields as S
+
+    torch.cuda.set_device(0)
+    t_all = time.perf_counter()
+    iters_train = args.ws_train_iters
+    pairs = []
+
+    def ctx_for(n, lr):
+        return g.Context(k=args.k, brick=args.brick, brick_z=args.brick_z, lr=lr,
+                         ell_min=math.log(0.25), ell_max=math.log(max(n / 16.0, 0.25)))
+
+    for s in range(10):
+        f, _ = S.tiny_mixture(seed=500 + s, normalize=True)
+        ft = torch.from_numpy(f).cuda()
+        pairs.append(W.training_pairs(ctx_for(64, 1e-3), ft, g.Grid(64, 64, 64), 2048, 500 + s, 20))
+    for s in range(9):
+        ft = S.spectral_field((256, 256, 256), 600 + s, device="cuda")
+        pairs.append(W.training_pairs(ctx_for(256, args.lr), ft, g.Grid(256, 256, 256), 65536,
+                                      600 + s, iters_train))
+        del ft
+    ft = S.fronts_field(1024, args.seed, device="cuda")
+    pairs.append(W.training_pairs(ctx_for(1024, args.lr), ft, g.Grid(1024, 1024, 1024), 1_400_000,
+                                  args.seed, iters_train))
+    del ft
+    torch.cuda.empty_cache()
+    t_pairs = time.perf_counter() - t_all
+    ctx = ctx_for(512, args.lr)
+    t0 = time.perf_counter()
+    mlp, hist, npairs = W.train_network(ctx, pairs, epochs=args.ws_epochs, batch=4096, lr=1e-3,
+                                        seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del pairs
+    print(f"[bench] warm start: {npairs} pairs in {t_pairs:.1f}s, training {t_train:.1f}s, "
+          f"loss {hist[0]:.4f} -> {hist[-1]:.4f}", file=sys.stderr, flush=True)
+    grid = g.Grid(512, 512, 512)
+    runs = []
+    for sched in args.ws_schedules:
+        for es in (9001, 9002, 9003):
+            f = S.fronts_field(512, es, device="cuda")
+            plain = W.plain_run(ctx, f, grid, 262_144, es, sched)
+            warm = W.warm_run(ctx, mlp, f, grid, 262_144, es, plain["loss_final"], sched)
+            plain.pop("info")
+            runs.append({"schedule": sched, "seed": es, "plain": plain, "warm": warm})
+            print(f"[bench] schedule {sched} seed {es}: plain {plain['seconds']:.2f}s "
+                  f"{plain['psnr_final']:.2f} dB; warm {warm['seconds']:.2f}s "
+                  f"{warm['iterations']} it ({warm['psnr_start']:.2f} -> {warm['psnr_final']:.2f} dB, "
+                  f"applied {warm['applied']})", file=sys.stderr, flush=True)
+            del f
+    summary = {}
+    for sched in args.ws_schedules:
+        rs = [r for r in runs if r["schedule"] == sched]
+        sp = np.array([r["plain"]["seconds"] for r in rs])
+        sw = np.array([r["warm"]["seconds"] for r in rs])
+        it = np.array([r["warm"]["iterations"] for r in rs])
+        summary[str(sched)] = {"plain_s_mean": float(sp.mean()), "warm_s_mean": float(sw.mean()),
+                               "speedup_mean": float((sp / sw).mean()),
+                               "speedup_min": float((sp / sw).min()),
+                               "speedup_max": float((sp / sw).max()),
+                               "warm_iterations_mean": float(it.mean()),
+                               "all_reached": all(r["warm"]["reached"] for r in rs)}
+    out = {
+        "metric": "time-to-PSNR warm vs plain (speedup at equal final PSNR)",
+        "value": summary[str(args.ws_schedules[0])]["speedup_mean"],
+        "unit": "x",
+        "higher_is_better": True,
+        "n_gpus": 1,
+        "dtype": "f32 (network bf16 on MFMA, fp32 accumulation)",
+        "data": "synthetic",
+        "config": {"workload": "train: 10x mixture 64^3 / 2,048, 9x spectral 256^3 / 65,536, "
+                               "1x fronts 1024^3 / 1.4M; eval: fronts 512^3 / 262,144, unseen seeds",
+                   "train_iterations": iters_train, "epochs": args.ws_epochs,
+                   "schedules": args.ws_schedules, "pairs": npairs},
+        "summary": summary,
+        "network_loss": {"first_epoch": float(hist[0]), "last_epoch": float(hist[-1])},
+        "seconds": {"pairs": t_pairs, "training": t_train},
+        "runs": runs,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,12 +195,19 @@ def main():
     ap.add_argument("--atomics", action="store_true",
                     help="accumulate gradient sums with float atomics instead of per-pair slots")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="run the warm-start time-to-PSNR comparison instead")
+    ap.add_argument("--ws-train-iters", type=int, default=300)
+    ap.add_argument("--ws-epochs", type=int, default=20)
+    ap.add_argument("--ws-schedules", type=int, nargs="+", default=[300, 2000])
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit(f"bench.py: --gpus {args.gpus} requested, but this encoder is measured on one "
                  "GPU only; multi-GPU runs are not part of this build.")
 
-    import numpy as np
+    if args.warm_start:
+        return warm_start_bench(args)
+
     import torch
 
     import paper_2608_14112_amd as g
