@@ -161,6 +161,14 @@ gve_status gve_evaluate(gve_ctx* ctx, const gve_params* p, gve_grid g, float* d_
 gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field, gve_grid g,
                          float* d_grad, double* h_loss);
 
+/* Vector-Jacobian product of the truncated field: d_grad [11][n] (device,
+ * caller-owned) = sum_p u(p) dVhat(p)/dtheta for an upstream gradient
+ * u = d_upstream [nz][ny][nx] (device float32), the truncation indicator held
+ * fixed.  With u = 2 (Vhat - V) this is gve_loss_grad's gradient.  It backs
+ * automatic differentiation of gve_evaluate.  Asynchronous. */
+gve_status gve_vjp(gve_ctx* ctx, const gve_params* p, const float* d_upstream, gve_grid g,
+                   float* d_grad);
+
 /* One bias-corrected Adam step on p from the caller's gradient d_grad [11][n]
  * (float32 device), followed by the optional log-scale clamp. */
 gve_status gve_adam_step(gve_ctx* ctx, gve_params* p, const float* d_grad);
@@ -209,6 +217,43 @@ gve_status gve_allocate(gve_ctx* ctx, const float* d_field, gve_grid g, int64_t 
 /* Min-max normalisation of a device float32 field of n values to [0, 1] in
  * place (Sec. III-B).  A constant field becomes 0.  Asynchronous. */
 gve_status gve_normalize(gve_ctx* ctx, float* d_field, int64_t n);
+
+/*
+ * Full-precision export (Sec. III-H, Sec. III-I eq:size): a fixed header of
+ * GVE_EXPORT_HEADER bytes followed by 48 bytes per primitive: twelve float32
+ * (position 3, log-scale 3, quaternion w x y z 4, scalar attribute a, weight
+ * w), so S_enc = 48 N + H.  This library's single weight c maps to a = c,
+ * w = 1.  The header holds a magic "GVE1", version 1, N, the grid (6 int64),
+ * k, the value range [vmin, vmax] of the normalised field (Sec. III-B), and a
+ * default 256-entry RGBA float32 transfer-function table (grey ramp, opacity
+ * equal to the value; the renderer applies its own, Sec. III-D) at byte 256;
+ * the rest of the header is reserved (zero).  The header's size is the H that
+ * the compression ratios printed in Sec. V-A/V-B imply (7,000 bytes).
+ * gve_export writes exactly gve_export_size(n) bytes into h_buf (host,
+ * caller-owned, at least that size).  gve_import creates a gve_params from
+ * such a buffer (a*w becomes c) and returns its grid; INVALID_ARGUMENT for
+ * a malformed buffer.  Both synchronise.
+ */
+#define GVE_EXPORT_HEADER 7000
+size_t gve_export_size(int64_t n);
+gve_status gve_export(gve_ctx* ctx, const gve_params* p, gve_grid g, float vmin, float vmax,
+                      void* h_buf, size_t buf_bytes);
+gve_status gve_import(gve_ctx* ctx, const void* h_buf, size_t buf_bytes, gve_params** out,
+                      gve_grid* g_out);
+
+/*
+ * Checkpoint / resume (Sec. III-H: periodic checkpoints hold the full
+ * primitive state and accumulated timing, so an interrupted run resumes
+ * without repeating allocation).  The buffer holds parameters, both Adam
+ * moments, the Adam step and the caller's accumulated seconds; resuming and
+ * refining continues exactly as an uninterrupted run (bitwise with
+ * deterministic gradients).  Sizes from gve_checkpoint_size(n).
+ */
+size_t gve_checkpoint_size(int64_t n);
+gve_status gve_checkpoint_save(gve_ctx* ctx, const gve_params* p, double elapsed_s, void* h_buf,
+                               size_t buf_bytes);
+gve_status gve_checkpoint_load(gve_ctx* ctx, const void* h_buf, size_t buf_bytes,
+                               gve_params** out, double* elapsed_s);
 
 /* Enable (1) or disable (0) the per-stage HIP-event timers of gve_refine.
  * Timing records events between the stages of every iteration; it does not

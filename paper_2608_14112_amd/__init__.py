@@ -98,6 +98,12 @@ _SIGS = {
     "gve_evaluate": [_vp, _vp, GridC, _vp],
     "gve_loss_grad": [_vp, _vp, _vp, GridC, _vp, ctypes.POINTER(ctypes.c_double)],
     "gve_adam_step": [_vp, _vp, _vp],
+    "gve_vjp": [_vp, _vp, _vp, GridC, _vp],
+    "gve_export": [_vp, _vp, GridC, ctypes.c_float, ctypes.c_float, _vp, ctypes.c_size_t],
+    "gve_import": [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp), ctypes.POINTER(GridC)],
+    "gve_checkpoint_save": [_vp, _vp, ctypes.c_double, _vp, ctypes.c_size_t],
+    "gve_checkpoint_load": [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp),
+                            ctypes.POINTER(ctypes.c_double)],
     "gve_refine": [_vp, _vp, _vp, GridC, ctypes.c_int32, _vp],
     "gve_get_stats": [_vp, ctypes.POINTER(StatsC)],
     "gve_allocate": [_vp, _vp, GridC, _i64, ctypes.c_uint64, ctypes.POINTER(_vp),
@@ -127,7 +133,13 @@ _lib.gve_status_string.restype = ctypes.c_char_p
 _lib.gve_last_error.argtypes = [_vp]
 _lib.gve_last_error.restype = ctypes.c_char_p
 
-EXPORTED = tuple(_SIGS) + ("gve_status_string", "gve_last_error")
+for _name in ("gve_export_size", "gve_checkpoint_size"):
+    getattr(_lib, _name).argtypes = [_i64]
+    getattr(_lib, _name).restype = ctypes.c_size_t
+
+EXPORTED = tuple(_SIGS) + ("gve_status_string", "gve_last_error", "gve_export_size",
+                           "gve_checkpoint_size")
+EXPORT_HEADER = 7000
 
 
 def _check(status, ctx_handle=None):
@@ -297,10 +309,13 @@ class Params:
             pass
 
 
-def evaluate(ctx: Context, params: Params, grid: Grid, out):
-    """gve_evaluate: truncated field on ``grid`` into ``out`` (float32 cuda [nz, ny, nx])."""
+def evaluate(ctx: Context, params: Params, grid: Grid, out=None):
+    """gve_evaluate: truncated field on ``grid`` into ``out`` (float32 cuda [nz, ny, nx];
+    allocated when not given)."""
     import torch
 
+    if out is None:
+        out = torch.empty(grid.shape, device="cuda", dtype=torch.float32)
     _check(_lib.gve_evaluate(ctx.handle, params.handle, grid.c(),
                              _ptr(out, torch.float32, grid.nx * grid.ny * grid.nz)), ctx.handle)
     return out
@@ -316,6 +331,18 @@ def loss_grad(ctx: Context, params: Params, field, grid: Grid, grad=None, want_l
     _check(_lib.gve_loss_grad(ctx.handle, params.handle, _ptr(field, torch.float32, n), grid.c(),
                               gp, ctypes.byref(L) if want_loss else None), ctx.handle)
     return L.value if want_loss else None
+
+
+def vjp(ctx: Context, params: Params, upstream, grid: Grid, grad=None):
+    """gve_vjp: sum_p upstream(p) dVhat(p)/dtheta as a [11, n] float32 cuda tensor."""
+    import torch
+
+    if grad is None:
+        grad = torch.empty((NPARAM, params.n), device=upstream.device, dtype=torch.float32)
+    _check(_lib.gve_vjp(ctx.handle, params.handle,
+                        _ptr(upstream, torch.float32, grid.nx * grid.ny * grid.nz), grid.c(),
+                        _ptr(grad, torch.float32, NPARAM * params.n)), ctx.handle)
+    return grad
 
 
 def adam_step(ctx: Context, params: Params, grad):
@@ -500,3 +527,45 @@ def warmstart(ctx: Context, mlp: MLP, params: Params, field, grid: Grid, n_detai
                               _i64(int(n_detail)), ctypes.c_double(float(g99)),
                               ctypes.byref(applied), L.ctypes.data_as(_vp)), ctx.handle)
     return applied.value, L
+
+
+def export_bytes(ctx: Context, params: Params, grid: Grid, vmin=0.0, vmax=1.0) -> bytes:
+    """gve_export: the 48-byte-per-primitive encoding with its fixed header."""
+    size = _lib.gve_export_size(_i64(params.n))
+    buf = ctypes.create_string_buffer(size)
+    _check(_lib.gve_export(ctx.handle, params.handle, grid.c(), ctypes.c_float(vmin),
+                           ctypes.c_float(vmax), ctypes.cast(buf, _vp), ctypes.c_size_t(size)),
+           ctx.handle)
+    return buf.raw
+
+
+def import_bytes(ctx: Context, data: bytes):
+    """gve_import: (Params, Grid) from an export."""
+    h = _vp()
+    gc = GridC()
+    buf = ctypes.create_string_buffer(data, len(data))
+    _check(_lib.gve_import(ctx.handle, ctypes.cast(buf, _vp), ctypes.c_size_t(len(data)),
+                           ctypes.byref(h), ctypes.byref(gc)), ctx.handle)
+    n = ctypes.c_int64()
+    _check(_lib.gve_params_size(h, ctypes.byref(n)))
+    return Params(ctx, n.value, _handle=h), Grid(gc.nx, gc.ny, gc.nz, gc.x0, gc.y0, gc.z0)
+
+
+def checkpoint_bytes(ctx: Context, params: Params, elapsed_s=0.0) -> bytes:
+    size = _lib.gve_checkpoint_size(_i64(params.n))
+    buf = ctypes.create_string_buffer(size)
+    _check(_lib.gve_checkpoint_save(ctx.handle, params.handle, ctypes.c_double(elapsed_s),
+                                    ctypes.cast(buf, _vp), ctypes.c_size_t(size)), ctx.handle)
+    return buf.raw
+
+
+def checkpoint_load(ctx: Context, data: bytes):
+    """(Params with Adam state and step, elapsed seconds) from a checkpoint."""
+    h = _vp()
+    el = ctypes.c_double()
+    buf = ctypes.create_string_buffer(data, len(data))
+    _check(_lib.gve_checkpoint_load(ctx.handle, ctypes.cast(buf, _vp), ctypes.c_size_t(len(data)),
+                                    ctypes.byref(h), ctypes.byref(el)), ctx.handle)
+    n = ctypes.c_int64()
+    _check(_lib.gve_params_size(h, ctypes.byref(n)))
+    return Params(ctx, n.value, _handle=h), el.value

@@ -468,6 +468,29 @@ gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field
   return GVE_OK;
 }
 
+gve_status gve_vjp(gve_ctx* ctx, const gve_params* p, const float* d_upstream, gve_grid g,
+                   float* d_grad) {
+  TRY(check_ctx_params(ctx, p));
+  if (!d_upstream || !d_grad)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "d_upstream and d_grad are required");
+  TRY(validate_grid(ctx, g));
+  TRY(set_device(ctx));
+  TRY(ensure_dloss(ctx));
+  gve_params* pm = const_cast<gve_params*>(p);
+  Binned bn;
+  TRY(bin(ctx, p, g, &bn));
+  TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)bn.bg.nbricks));
+  float* part = nullptr;
+  TRY(partials_for(ctx, bn.npairs, &part));
+  if (!part) TRY_HIP(ctx, gve::fill_f32(pm->acc, 10 * p->n, 0.0f, ctx->stream));
+  TRY_HIP(ctx, gve::launch_fused(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, d_upstream,
+                                 pm->acc, p->n, part, p->offset,
+                                 static_cast<float*>(ctx->ws.brick_loss.ptr), ctx->stream, true));
+  TRY_HIP(ctx, gve::launch_update(0, pm->theta, pm->m, pm->v, pm->acc, part, p->offset, nullptr,
+                                  d_grad, p->n, p->t, ctx->opt, nullptr, ctx->stream));
+  return GVE_OK;
+}
+
 gve_status gve_adam_step(gve_ctx* ctx, gve_params* p, const float* d_grad) {
   TRY(check_ctx_params(ctx, p));
   if (!d_grad) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "d_grad is NULL");
@@ -478,6 +501,171 @@ gve_status gve_adam_step(gve_ctx* ctx, gve_params* p, const float* d_grad) {
                                   nullptr, p->n, p->t,
                                   ctx->opt, clamp_counter(ctx), ctx->stream));
   ctx->stats.iterations = p->t;
+  return GVE_OK;
+}
+
+namespace {
+
+struct ExportHeader {
+  char magic[4];
+  uint32_t version;
+  int64_t n;
+  int64_t grid[6];
+  float k, vmin, vmax, pad;
+};
+static_assert(sizeof(ExportHeader) <= 256, "export header");
+constexpr int64_t kMaxRecords = (int64_t)1 << 40;  // keeps every size product in range
+constexpr size_t kLutOffset = 256;  // 256 RGBA float32 = 4096 bytes
+static_assert(kLutOffset + 4096 <= GVE_EXPORT_HEADER, "export header size");
+
+struct CheckpointHeader {
+  char magic[4];
+  uint32_t version;
+  int64_t n;
+  int64_t t;
+  double elapsed;
+};
+
+}  // namespace
+
+size_t gve_export_size(int64_t n) { return GVE_EXPORT_HEADER + 48 * (size_t)(n > 0 ? n : 0); }
+
+gve_status gve_export(gve_ctx* ctx, const gve_params* p, gve_grid g, float vmin, float vmax,
+                      void* h_buf, size_t buf_bytes) {
+  TRY(check_ctx_params(ctx, p));
+  if (!h_buf || buf_bytes < gve_export_size(p->n))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "buffer smaller than gve_export_size(n)");
+  TRY(set_device(ctx));
+  const int64_t n = p->n;
+  std::vector<float> theta((size_t)11 * n);
+  TRY_HIP(ctx, hipMemcpyAsync(theta.data(), p->theta, sizeof(float) * theta.size(),
+                              hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  char* out = static_cast<char*>(h_buf);
+  std::memset(out, 0, GVE_EXPORT_HEADER);
+  ExportHeader h{};
+  std::memcpy(h.magic, "GVE1", 4);
+  h.version = 1;
+  h.n = n;
+  const int64_t gv[6] = {g.nx, g.ny, g.nz, g.x0, g.y0, g.z0};
+  for (int i = 0; i < 6; ++i) h.grid[i] = gv[i];
+  h.k = ctx->opt.k;
+  h.vmin = vmin;
+  h.vmax = vmax;
+  std::memcpy(out, &h, sizeof h);
+  float lut[1024];
+  for (int i = 0; i < 256; ++i) {
+    const float v = (float)i / 255.0f;
+    lut[4 * i + 0] = v; lut[4 * i + 1] = v; lut[4 * i + 2] = v; lut[4 * i + 3] = v;
+  }
+  std::memcpy(out + kLutOffset, lut, sizeof lut);
+  // the caller's buffer need not be float-aligned: build records, then copy
+  std::vector<float> rec((size_t)12 * n);
+  for (int64_t i = 0; i < n; ++i) {
+    float* r = rec.data() + 12 * i;
+    r[0] = theta[0 * n + i]; r[1] = theta[1 * n + i]; r[2] = theta[2 * n + i];
+    r[3] = theta[7 * n + i]; r[4] = theta[8 * n + i]; r[5] = theta[9 * n + i];
+    r[6] = theta[3 * n + i]; r[7] = theta[4 * n + i]; r[8] = theta[5 * n + i];
+    r[9] = theta[6 * n + i];
+    r[10] = theta[10 * n + i];  // scalar attribute a = c
+    r[11] = 1.0f;               // weight w
+  }
+  std::memcpy(out + GVE_EXPORT_HEADER, rec.data(), sizeof(float) * rec.size());
+  return GVE_OK;
+}
+
+gve_status gve_import(gve_ctx* ctx, const void* h_buf, size_t buf_bytes, gve_params** out,
+                      gve_grid* g_out) {
+  if (!ctx || !out) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  if (!h_buf || buf_bytes < GVE_EXPORT_HEADER)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "buffer shorter than the export header");
+  ExportHeader h;
+  std::memcpy(&h, h_buf, sizeof h);
+  if (std::memcmp(h.magic, "GVE1", 4) != 0 || h.version != 1 || h.n < 1 || h.n > kMaxRecords ||
+      buf_bytes < gve_export_size(h.n))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "not a version-1 export of the stated size");
+  const int64_t n = h.n;
+  std::vector<float> rec((size_t)12 * n);
+  std::memcpy(rec.data(), static_cast<const char*>(h_buf) + GVE_EXPORT_HEADER,
+              sizeof(float) * rec.size());
+  std::vector<float> theta((size_t)11 * n);
+  for (int64_t i = 0; i < n; ++i) {
+    const float* r = rec.data() + 12 * i;
+    theta[0 * n + i] = r[0]; theta[1 * n + i] = r[1]; theta[2 * n + i] = r[2];
+    theta[7 * n + i] = r[3]; theta[8 * n + i] = r[4]; theta[9 * n + i] = r[5];
+    theta[3 * n + i] = r[6]; theta[4 * n + i] = r[7]; theta[5 * n + i] = r[8];
+    theta[6 * n + i] = r[9];
+    theta[10 * n + i] = r[10] * r[11];
+  }
+  gve_params* p = nullptr;
+  TRY(gve_params_create(ctx, n, &p));
+  const gve_status st = gve_params_upload(ctx, p, theta.data());
+  if (st != GVE_OK) {
+    gve_params_destroy(p);
+    return st;
+  }
+  if (g_out) *g_out = gve_grid{h.grid[0], h.grid[1], h.grid[2], h.grid[3], h.grid[4], h.grid[5]};
+  *out = p;
+  return GVE_OK;
+}
+
+size_t gve_checkpoint_size(int64_t n) {
+  return sizeof(CheckpointHeader) + 3 * 11 * sizeof(float) * (size_t)(n > 0 ? n : 0);
+}
+
+gve_status gve_checkpoint_save(gve_ctx* ctx, const gve_params* p, double elapsed_s, void* h_buf,
+                               size_t buf_bytes) {
+  TRY(check_ctx_params(ctx, p));
+  if (!h_buf || buf_bytes < gve_checkpoint_size(p->n))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "buffer smaller than gve_checkpoint_size(n)");
+  TRY(set_device(ctx));
+  CheckpointHeader h{};
+  std::memcpy(h.magic, "GVC1", 4);
+  h.version = 1;
+  h.n = p->n;
+  h.t = p->t;
+  h.elapsed = elapsed_s;
+  char* out = static_cast<char*>(h_buf);
+  std::memcpy(out, &h, sizeof h);
+  const size_t block = 11 * sizeof(float) * (size_t)p->n;
+  char* body = out + sizeof h;
+  TRY_HIP(ctx, hipMemcpyAsync(body, p->theta, block, hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipMemcpyAsync(body + block, p->m, block, hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipMemcpyAsync(body + 2 * block, p->v, block, hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return GVE_OK;
+}
+
+gve_status gve_checkpoint_load(gve_ctx* ctx, const void* h_buf, size_t buf_bytes,
+                               gve_params** out, double* elapsed_s) {
+  if (!ctx || !out) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  if (!h_buf || buf_bytes < sizeof(CheckpointHeader))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "buffer shorter than the checkpoint header");
+  CheckpointHeader h;
+  std::memcpy(&h, h_buf, sizeof h);
+  if (std::memcmp(h.magic, "GVC1", 4) != 0 || h.version != 1 || h.n < 1 || h.n > kMaxRecords ||
+      h.t < 0 ||
+      buf_bytes < gve_checkpoint_size(h.n))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "not a version-1 checkpoint of the stated size");
+  TRY(set_device(ctx));
+  gve_params* p = nullptr;
+  TRY(gve_params_create(ctx, h.n, &p));
+  const size_t block = 11 * sizeof(float) * (size_t)h.n;
+  const char* body = static_cast<const char*>(h_buf) + sizeof h;
+  hipError_t e = hipMemcpyAsync(p->theta, body, block, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->m, body + block, block, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->v, body + 2 * block, block, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    gve_params_destroy(p);
+    return from_hip(ctx, e, "gve_checkpoint_load");
+  }
+  p->t = h.t;
+  if (elapsed_s) *elapsed_s = h.elapsed;
+  *out = p;
   return GVE_OK;
 }
 

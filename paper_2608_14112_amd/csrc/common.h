@@ -131,7 +131,8 @@ hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid,
 hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid,
                         const uint32_t* brick_start, gve_grid g, BrickGeom bg, float k,
                         const float* field, float* acc, int64_t n, float* part,
-                        const uint32_t* offset, float* brick_loss, hipStream_t s);
+                        const uint32_t* offset, float* brick_loss, hipStream_t s,
+                        bool vjp = false);
 hipError_t launch_count(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
                         gve_grid g, BrickGeom bg, float k, unsigned long long* counts,
                         hipStream_t s);

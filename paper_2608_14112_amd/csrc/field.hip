@@ -189,7 +189,11 @@ __device__ inline uint32_t pair_slot(const Record& r, const uint32_t* __restrict
   return offset[gid] + (uint32_t)((rbz * nby_g + rby) * nbx_g + rbx);
 }
 
-template <int BXY, int BZ>
+// VJP = false: residual r = 2 (Vhat - V) from the forward pass and the target
+// `field`, loss share to brick_loss.  VJP = true: no forward pass; r is read
+// from `field` (an upstream gradient dl/dVhat), so the ten sums give the
+// vector-Jacobian product sum_p r(p) dVhat(p)/dtheta.
+template <int BXY, int BZ, bool VJP>
 __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ rec,
                                                 const uint32_t* __restrict__ pair_gid,
                                                 const uint32_t* __restrict__ brick_start,
@@ -218,31 +222,36 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
   float res[BZ];
 #pragma unroll
   for (int zz = 0; zz < BZ; ++zz) res[zz] = 0.0f;
-  accumulate_brick<BZ>(rec, pair_gid, j0, j1, px, py, pz0, iz0, col_in, thr, res);
-
-  // residual and this brick's share of the loss
-  float lsum = 0.0f;
   const size_t plane = (size_t)g.nx * (size_t)g.ny;
   const size_t base = (size_t)ix + (size_t)g.nx * (size_t)iy;
+  if (VJP) {
 #pragma unroll
-  for (int zz = 0; zz < BZ; ++zz) {
-    float r = 0.0f;
-    if (col_in && iz0 + zz < g.nz) {
-      const float d = res[zz] - field[base + plane * (size_t)(iz0 + zz)];
-      lsum = fmaf(d, d, lsum);
-      r = 2.0f * d;
+    for (int zz = 0; zz < BZ; ++zz)
+      if (col_in && iz0 + zz < g.nz) res[zz] = field[base + plane * (size_t)(iz0 + zz)];
+  } else {
+    accumulate_brick<BZ>(rec, pair_gid, j0, j1, px, py, pz0, iz0, col_in, thr, res);
+    // residual and this brick's share of the loss
+    float lsum = 0.0f;
+#pragma unroll
+    for (int zz = 0; zz < BZ; ++zz) {
+      float r = 0.0f;
+      if (col_in && iz0 + zz < g.nz) {
+        const float d = res[zz] - field[base + plane * (size_t)(iz0 + zz)];
+        lsum = fmaf(d, d, lsum);
+        r = 2.0f * d;
+      }
+      res[zz] = r;
     }
-    res[zz] = r;
+    lsum = wave_sum(lsum);
+    if (lane == 0) red[wave][0] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float t = 0.0f;
+      for (int w = 0; w < kWaves; ++w) t += red[w][0];
+      brick_loss[b] = t;
+    }
+    __syncthreads();
   }
-  lsum = wave_sum(lsum);
-  if (lane == 0) red[wave][0] = lsum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float t = 0.0f;
-    for (int w = 0; w < kWaves; ++w) t += red[w][0];
-    brick_loss[b] = t;
-  }
-  __syncthreads();
 
   for (uint32_t j = j0; j < j1; ++j) {
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
@@ -438,13 +447,17 @@ hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid, const uin
 hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
                         gve_grid g, BrickGeom bg, float k, const float* field, float* acc,
                         int64_t n, float* part, const uint32_t* offset, float* brick_loss,
-                        hipStream_t s) {
+                        hipStream_t s, bool vjp) {
   const float thr = -kHalfLog2e * k * k;
   const dim3 grid((unsigned)bg.nbricks);
 #define GVE_CASE(XY, Z)                                                                       \
   if (bg.Bxy == XY && bg.Bz == Z) {                                                           \
-    hipLaunchKernelGGL((k_fused<XY, Z>), grid, dim3(XY * XY), 0, s, rec, pair_gid, brick_start, \
-                       g, bg, thr, field, acc, n, part, offset, brick_loss);                    \
+    if (vjp)                                                                                  \
+      hipLaunchKernelGGL((k_fused<XY, Z, true>), grid, dim3(XY * XY), 0, s, rec, pair_gid,      \
+                         brick_start, g, bg, thr, field, acc, n, part, offset, brick_loss);     \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_fused<XY, Z, false>), grid, dim3(XY * XY), 0, s, rec, pair_gid,     \
+                         brick_start, g, bg, thr, field, acc, n, part, offset, brick_loss);     \
     return hipGetLastError();                                                                 \
   }
   GVE_BRICK_SHAPES(GVE_CASE)

@@ -76,3 +76,19 @@ def test_bad_options_fail_before_any_device_call(field, value, status):
     h = ctypes.c_void_p()
     assert g._lib.gve_create(ctypes.byref(h), ctypes.byref(o), None) == status
     assert not h.value
+
+
+def test_export_and_checkpoint_sizes():
+    import paper_2608_14112_amd as g
+    from oracle import field as F
+
+    lib = ctypes.CDLL(g.LIB_PATH)
+    lib.gve_export_size.argtypes = [ctypes.c_int64]
+    lib.gve_export_size.restype = ctypes.c_size_t
+    lib.gve_checkpoint_size.argtypes = [ctypes.c_int64]
+    lib.gve_checkpoint_size.restype = ctypes.c_size_t
+    for n in (1, 2000, 1_400_000):
+        assert lib.gve_export_size(n) == F.encoded_bytes(n, g.EXPORT_HEADER)
+        assert lib.gve_checkpoint_size(n) == 32 + 3 * 44 * n
+    assert lib.gve_export_size(0) == g.EXPORT_HEADER
+    assert lib.gve_export_size(-5) == g.EXPORT_HEADER
