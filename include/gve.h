@@ -74,7 +74,14 @@ typedef struct gve_grid {
  * (primitive, brick) pair writes its gradient sums to its own slot and the
  * update sums them per primitive in a fixed order, so gradients are bitwise
  * reproducible and no atomics are issued (default); 0 = float atomics.
+ * schedule: the order in which workgroups take bricks (results are identical
+ * under every schedule): GVE_SCHED_INDEX one workgroup per brick in brick
+ * order (default); GVE_SCHED_XCD one workgroup per brick with consecutive
+ * bricks kept on one XCD; GVE_SCHED_QUEUE a persistent launch whose
+ * workgroups take bricks from a work queue, heaviest first.  gve_autotune
+ * measures which is fastest for a workload.
  */
+enum { GVE_SCHED_INDEX = 0, GVE_SCHED_XCD = 1, GVE_SCHED_QUEUE = 2 };
 typedef struct gve_options {
   float k;
   int32_t brick;
@@ -82,6 +89,7 @@ typedef struct gve_options {
   float ell_min, ell_max;
   int32_t brick_z;
   int32_t deterministic;
+  int32_t schedule;
 } gve_options;
 
 /* Counters of the most recent evaluation / refinement iteration. */
@@ -269,6 +277,66 @@ gve_status gve_set_timing(gve_ctx* ctx, int32_t enable);
  */
 gve_status gve_count_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, int64_t* h_in_support,
                            int64_t* h_candidates);
+
+/*
+ * Batched volumes: many uneven volumes (bricks of a larger domain, or
+ * timesteps) binned together and refined in one launch per stage, every
+ * (volume, brick) tile a work item of the same kernels (the work of each
+ * volume is exactly that of a separate call).  A batch holds the volumes'
+ * grids and one parameter set of sum(counts) primitives: volume i owns the
+ * columns [prim_off[i], prim_off[i+1]) of the [11][N] layout and may only be
+ * reached by its own primitives.  Fields and outputs are one concatenated
+ * device buffer: volume i's voxels (x fastest) start at vox_off[i].  All
+ * volumes share the Adam step counter.
+ *   gve_batch_create: n_items >= 1 volumes with counts[i] >= 1 primitives
+ *     (host arrays); parameters start at zero (set them with
+ *     gve_batch_set_item or through gve_batch_params).
+ *   gve_batch_params: the batch's parameter set (borrowed: valid until
+ *     gve_batch_destroy; do not destroy it).
+ *   gve_batch_offsets: prim_off and vox_off, n_items + 1 entries each (host).
+ *   gve_batch_set_item: copy src (count[item] primitives) into volume item's
+ *     columns and zero their Adam moments.  gve_batch_get_item: the reverse
+ *     (dst's Adam state is left as is).  Both asynchronous.
+ *   gve_batch_evaluate / gve_batch_loss_grad / gve_batch_refine /
+ *   gve_batch_count_pairs: as the single-volume calls, over every volume;
+ *   h_loss holds one loss per volume (refine: [iters][n_items]); counts are
+ *   totals over the volumes.
+ */
+typedef struct gve_batch gve_batch;
+gve_status gve_batch_create(gve_ctx* ctx, int32_t n_items, const gve_grid* h_grids,
+                            const int64_t* h_counts, gve_batch** out);
+void gve_batch_destroy(gve_batch* b);
+gve_status gve_batch_params(gve_batch* b, gve_params** out);
+gve_status gve_batch_offsets(const gve_batch* b, int64_t* h_prim_off, int64_t* h_vox_off);
+gve_status gve_batch_set_item(gve_ctx* ctx, gve_batch* b, int32_t item, const gve_params* src);
+gve_status gve_batch_get_item(gve_ctx* ctx, const gve_batch* b, int32_t item, gve_params* dst);
+gve_status gve_batch_evaluate(gve_ctx* ctx, const gve_batch* b, float* d_out);
+gve_status gve_batch_loss_grad(gve_ctx* ctx, const gve_batch* b, const float* d_fields,
+                               float* d_grad, double* h_loss);
+gve_status gve_batch_refine(gve_ctx* ctx, gve_batch* b, const float* d_fields, int32_t iters,
+                            double* h_loss);
+gve_status gve_batch_count_pairs(gve_ctx* ctx, const gve_batch* b, int64_t* h_in_support,
+                                 int64_t* h_candidates);
+
+/*
+ * Autotuner: times the fused pass (binning + fused kernel + loss) under
+ * every brick shape and schedule on the caller's workload (b == NULL: the
+ * single volume p, d_field, g; otherwise the batch b, d_fields) for `reps`
+ * passes each after one warm-up pass, keeps the fastest in the context's
+ * options, and writes one entry per candidate to h_table (up to table_len;
+ * *n_written = number written).  Parameters and Adam state are unchanged.
+ * Results are cached in the context under a key of (volumes, voxels,
+ * primitives, box coverage per voxel at 8x8x8, each rounded to a power of
+ * two or half-power); a later call whose workload has the same key applies
+ * the cached choice without timing and reports *n_written = 0.  Synchronises.
+ */
+typedef struct gve_tune_entry {
+  int32_t brick, brick_z, schedule;
+  float ms;  /* median over the reps */
+} gve_tune_entry;
+gve_status gve_autotune(gve_ctx* ctx, const gve_params* p, const float* d_field, gve_grid g,
+                        const gve_batch* b, int32_t reps, gve_tune_entry* h_table,
+                        int32_t table_len, int32_t* n_written);
 
 /*
  * Learned warm start.  The paper has no learned component; this network and

@@ -58,7 +58,16 @@ class OptionsC(ctypes.Structure):
     _fields_ = [("k", ctypes.c_float), ("brick", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("ell_min", ctypes.c_float), ("ell_max", ctypes.c_float),
-                ("brick_z", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
+                ("brick_z", ctypes.c_int32), ("deterministic", ctypes.c_int32),
+                ("schedule", ctypes.c_int32)]
+
+
+class TuneEntryC(ctypes.Structure):
+    _fields_ = [("brick", ctypes.c_int32), ("brick_z", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
+SCHED_INDEX, SCHED_XCD, SCHED_QUEUE = 0, 1, 2
 
 
 class StatsC(ctypes.Structure):
@@ -123,6 +132,17 @@ _SIGS = {
     "gve_warmstart": [_vp, _vp, _vp, _vp, GridC, _i64, ctypes.c_double,
                       ctypes.POINTER(ctypes.c_int32), _vp],
     "gve_count_pairs": [_vp, _vp, GridC, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+    "gve_batch_create": [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(_vp)],
+    "gve_batch_params": [_vp, ctypes.POINTER(_vp)],
+    "gve_batch_offsets": [_vp, _vp, _vp],
+    "gve_batch_set_item": [_vp, _vp, ctypes.c_int32, _vp],
+    "gve_batch_get_item": [_vp, _vp, ctypes.c_int32, _vp],
+    "gve_batch_evaluate": [_vp, _vp, _vp],
+    "gve_batch_loss_grad": [_vp, _vp, _vp, _vp, _vp],
+    "gve_batch_refine": [_vp, _vp, _vp, ctypes.c_int32, _vp],
+    "gve_batch_count_pairs": [_vp, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+    "gve_autotune": [_vp, _vp, _vp, GridC, _vp, ctypes.c_int32, _vp, ctypes.c_int32,
+                     ctypes.POINTER(ctypes.c_int32)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -136,9 +156,11 @@ _lib.gve_last_error.restype = ctypes.c_char_p
 for _name in ("gve_export_size", "gve_checkpoint_size"):
     getattr(_lib, _name).argtypes = [_i64]
     getattr(_lib, _name).restype = ctypes.c_size_t
+_lib.gve_batch_destroy.argtypes = [_vp]
+_lib.gve_batch_destroy.restype = None
 
 EXPORTED = tuple(_SIGS) + ("gve_status_string", "gve_last_error", "gve_export_size",
-                           "gve_checkpoint_size")
+                           "gve_checkpoint_size", "gve_batch_destroy")
 EXPORT_HEADER = 7000
 
 
@@ -193,14 +215,16 @@ class Context:
 
     def __init__(self, k=3.0, brick=8, lr=8e-3, beta1=0.9, beta2=0.999, eps=1e-8,
                  ell_min=-math.inf, ell_max=math.inf, brick_z=None, deterministic=True,
-                 stream=None):
+                 schedule=None, stream=None):
         import torch
 
         if brick_z is None:                       # library default shape 8 x 8 x 32
             brick_z = 32 if brick in (0, 8) else 0
+        if schedule is None:
+            schedule = default_options().schedule
         self._torch_stream = stream if stream is not None else torch.cuda.current_stream()
         o = OptionsC(k, brick, lr, beta1, beta2, eps, ell_min, ell_max, brick_z,
-                     1 if deterministic else 0)
+                     1 if deterministic else 0, schedule)
         h = _vp()
         st = _lib.gve_create(ctypes.byref(h), ctypes.byref(o),
                              _vp(self._torch_stream.cuda_stream))
@@ -243,9 +267,10 @@ class Context:
 class Params:
     """A fixed-budget primitive set: device [11][n] parameters plus Adam state."""
 
-    def __init__(self, ctx: Context, n: int, _handle=None):
+    def __init__(self, ctx: Context, n: int, _handle=None, _owned=True):
         self.ctx = ctx
         self.n = int(n)
+        self._owned = _owned
         if _handle is not None:
             self.handle = _handle
             return
@@ -299,7 +324,8 @@ class Params:
 
     def close(self):
         if getattr(self, "handle", None):
-            _lib.gve_params_destroy(self.handle)
+            if self._owned:
+                _lib.gve_params_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -569,3 +595,122 @@ def checkpoint_load(ctx: Context, data: bytes):
     n = ctypes.c_int64()
     _check(_lib.gve_params_size(h, ctypes.byref(n)))
     return Params(ctx, n.value, _handle=h), el.value
+
+
+class Batch:
+    """gve_batch: many volumes binned and refined together.
+
+    ``grids`` is a list of Grid, ``counts`` the primitives of each.  Fields and
+    outputs are one concatenated float32 cuda buffer (``voxel_offsets``);
+    parameters are one [11, sum(counts)] set (``prim_offsets``).
+    """
+
+    def __init__(self, ctx: Context, grids, counts):
+        self.ctx = ctx
+        self.grids = list(grids)
+        n = len(self.grids)
+        g = (GridC * n)(*[gr.c() for gr in self.grids])
+        c = (ctypes.c_int64 * n)(*[int(x) for x in counts])
+        h = _vp()
+        _check(_lib.gve_batch_create(ctx.handle, ctypes.c_int32(n), ctypes.cast(g, _vp),
+                                     ctypes.cast(c, _vp), ctypes.byref(h)), ctx.handle)
+        self.handle = h
+        po = np.zeros(n + 1, dtype=np.int64)
+        vo = np.zeros(n + 1, dtype=np.int64)
+        _check(_lib.gve_batch_offsets(h, po.ctypes.data_as(_vp), vo.ctypes.data_as(_vp)))
+        self.prim_offsets, self.voxel_offsets = po, vo
+        ph = _vp()
+        _check(_lib.gve_batch_params(h, ctypes.byref(ph)))
+        self.params = Params(ctx, int(po[-1]), _handle=ph, _owned=False)
+
+    @property
+    def n_items(self):
+        return len(self.grids)
+
+    def set_item(self, i, params: Params):
+        _check(_lib.gve_batch_set_item(self.ctx.handle, self.handle, ctypes.c_int32(i),
+                                       params.handle), self.ctx.handle)
+
+    def get_item(self, i, params: Params):
+        _check(_lib.gve_batch_get_item(self.ctx.handle, self.handle, ctypes.c_int32(i),
+                                       params.handle), self.ctx.handle)
+        return params
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.params.handle = None
+            _lib.gve_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_evaluate(ctx: Context, batch: Batch, out=None):
+    import torch
+
+    m = int(batch.voxel_offsets[-1])
+    if out is None:
+        out = torch.empty(m, device="cuda", dtype=torch.float32)
+    _check(_lib.gve_batch_evaluate(ctx.handle, batch.handle, _ptr(out, torch.float32, m)),
+           ctx.handle)
+    return out
+
+
+def batch_loss_grad(ctx: Context, batch: Batch, fields, grad=None):
+    """Per-volume losses (numpy [n_items]); fills grad ([11, N] float32 cuda) if given."""
+    import torch
+
+    m = int(batch.voxel_offsets[-1])
+    losses = np.zeros(batch.n_items, dtype=np.float64)
+    gp = _ptr(grad, torch.float32, NPARAM * batch.params.n) if grad is not None else None
+    _check(_lib.gve_batch_loss_grad(ctx.handle, batch.handle, _ptr(fields, torch.float32, m), gp,
+                                    losses.ctypes.data_as(_vp)), ctx.handle)
+    return losses
+
+
+def batch_refine(ctx: Context, batch: Batch, fields, iters: int, want_losses=True):
+    """Returns the per-volume loss before each update, [iters, n_items]."""
+    import torch
+
+    m = int(batch.voxel_offsets[-1])
+    hist = np.zeros((max(int(iters), 1), batch.n_items), dtype=np.float64) if want_losses else None
+    _check(_lib.gve_batch_refine(ctx.handle, batch.handle, _ptr(fields, torch.float32, m),
+                                 ctypes.c_int32(int(iters)),
+                                 hist.ctypes.data_as(_vp) if want_losses else None), ctx.handle)
+    return hist[:iters] if want_losses else None
+
+
+def batch_count_pairs(ctx: Context, batch: Batch):
+    a, b = _i64(), _i64()
+    _check(_lib.gve_batch_count_pairs(ctx.handle, batch.handle, ctypes.byref(a), ctypes.byref(b)),
+           ctx.handle)
+    return a.value, b.value
+
+
+def autotune(ctx: Context, field, params: Params = None, grid: Grid = None, batch: Batch = None,
+             reps=3):
+    """gve_autotune: pick the fastest brick shape and schedule for this workload.
+
+    Returns a list of (brick, brick_z, schedule, ms) per candidate timed (empty
+    when the context's cache already held the answer); the context keeps the
+    choice.
+    """
+    import torch
+
+    table = (TuneEntryC * 16)()
+    nw = ctypes.c_int32()
+    if batch is not None:
+        fp = _ptr(field, torch.float32, int(batch.voxel_offsets[-1]))
+        st = _lib.gve_autotune(ctx.handle, None, fp, GridC(), batch.handle, ctypes.c_int32(reps),
+                               ctypes.cast(table, _vp), 16, ctypes.byref(nw))
+    else:
+        fp = _ptr(field, torch.float32, grid.nx * grid.ny * grid.nz)
+        st = _lib.gve_autotune(ctx.handle, params.handle, fp, grid.c(), None,
+                               ctypes.c_int32(reps), ctypes.cast(table, _vp), 16,
+                               ctypes.byref(nw))
+    _check(st, ctx.handle)
+    return [(e.brick, e.brick_z, e.schedule, e.ms) for e in table[:nw.value]]

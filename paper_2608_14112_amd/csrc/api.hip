@@ -26,6 +26,20 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
     p[i] = 0ull;
 }
 
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// Zero columns [off, off + cnt) of an [rows][ld] float array.
+__global__ void k_zero_cols(float* __restrict__ p, int64_t ld, int64_t off, int64_t cnt, int rows) {
+  const int64_t total = cnt * rows;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[(i / cnt) * ld + off + i % cnt] = 0.0f;
+}
+
 gve_status fail(const gve_ctx* ctx, gve_status st, const std::string& msg) {
   if (ctx) const_cast<gve_ctx*>(ctx)->last_error = msg;
   return st;
@@ -93,6 +107,8 @@ gve_status validate_options(const gve_ctx* ctx, const gve_options& o) {
     return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "eps must be finite and > 0");
   if (o.deterministic != 0 && o.deterministic != 1)
     return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "deterministic must be 0 or 1");
+  if (o.schedule < GVE_SCHED_INDEX || o.schedule > GVE_SCHED_QUEUE)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "schedule must be 0, 1 or 2");
   if (std::isnan(o.ell_min) || std::isnan(o.ell_max) || o.ell_min > o.ell_max)
     return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "ell_min must be <= ell_max");
   return GVE_OK;
@@ -120,27 +136,72 @@ int bits_for(int64_t nbricks) {
   return b;
 }
 
+// A set of volumes and the primitive ranges that belong to each.
+struct Vol {
+  const gve_grid* grids;
+  const int64_t* prim_off;  // [n + 1]
+  int n;
+};
+
 struct Binned {
   gve::BrickGeom bg;
+  const gve::ItemDesc* items = nullptr;  // device
+  int nitems = 0;
+  gve::Schedule sched;
   const uint32_t* gid = nullptr;
   const uint32_t* start = nullptr;
   int64_t npairs = 0;
 };
 
-// prep -> scan -> emit -> radix sort -> brick ranges.  Reads the pair count
-// back to the host (one small synchronising copy) to size the pair buffers.
-gve_status bin(gve_ctx* ctx, const gve_params* p, const gve_grid& g, Binned* out) {
+// Volume descriptors on the device for the current brick shape.  The upload
+// is followed by a synchronisation, so the host copy (which the device copy
+// mirrors) is never rewritten while a transfer from it is pending.
+gve_status upload_items(gve_ctx* ctx, const Vol& vol, int Bxy, int Bz, int64_t* nbricks) {
+  std::vector<gve::ItemDesc> h((size_t)vol.n);
+  *nbricks = gve::build_items(vol.grids, vol.prim_off, vol.n, Bxy, Bz, h.data());
+  const bool same = h.size() == ctx->items_host.size() && ctx->ws.items.ptr &&
+                    std::memcmp(h.data(), ctx->items_host.data(),
+                                sizeof(gve::ItemDesc) * h.size()) == 0;
+  if (same) return GVE_OK;
+  TRY(ensure(ctx, ctx->ws.items, sizeof(gve::ItemDesc) * h.size()));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->items_host.swap(h);
+  TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.items.ptr, ctx->items_host.data(),
+                              sizeof(gve::ItemDesc) * ctx->items_host.size(),
+                              hipMemcpyHostToDevice, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return GVE_OK;
+}
+
+int resident_groups(gve_ctx* ctx, int bxy, int bz) {
+  auto key = std::make_pair(bxy, bz);
+  auto it = ctx->resident.find(key);
+  if (it != ctx->resident.end()) return it->second;
+  const int r = gve::fused_resident_groups(bxy, bz, ctx->device);
+  ctx->resident[key] = r;
+  return r;
+}
+
+// prep -> scan -> emit -> radix sort -> brick ranges (-> heaviest-first
+// order for the queue schedule).  Reads the pair count back to the host (one
+// small synchronising copy) to size the pair buffers.
+gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* out) {
   hipStream_t s = ctx->stream;
   auto& ws = ctx->ws;
   const int64_t n = p->n;
-  gve::BrickGeom bg = gve::brick_geometry(g, brick_xy(ctx), brick_z(ctx));
+  gve::BrickGeom bg;
+  bg.Bxy = brick_xy(ctx);
+  bg.Bz = brick_z(ctx);
+  TRY(upload_items(ctx, vol, bg.Bxy, bg.Bz, &bg.nbricks));
   if (bg.nbricks >= ((int64_t)1 << 31))
     return fail(ctx, GVE_ERR_UNSUPPORTED, "too many bricks for 32-bit brick keys");
+  const gve::ItemDesc* items = static_cast<const gve::ItemDesc*>(ws.items.ptr);
   TRY(ensure(ctx, ws.scan_tmp, gve::scan_tmp_bytes(n + 1)));
   TRY(ensure_dloss(ctx));
   unsigned long long* total = reinterpret_cast<unsigned long long*>(ws.dloss.ptr) + 1;
   TRY_HIP(ctx, gve::fill_u64(total, 1, s));
-  TRY_HIP(ctx, gve::launch_prep(p->theta, n, g, ctx->opt.k, bg, p->rec, p->count, total, s));
+  TRY_HIP(ctx, gve::launch_prep(p->theta, n, items, vol.n, ctx->opt.k, bg, p->rec, p->count,
+                                total, s));
   TRY_HIP(ctx, gve::scan_exclusive_u32(p->count, p->offset, n, ws.scan_tmp.ptr, s));
   TRY_HIP(ctx, hipMemcpyAsync(ws.h_pinned, total, sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, s));
@@ -154,23 +215,76 @@ gve_status bin(gve_ctx* ctx, const gve_params* p, const gve_grid& g, Binned* out
     TRY(ensure(ctx, ws.keys[b], pair_bytes));
     TRY(ensure(ctx, ws.vals[b], pair_bytes));
   }
-  TRY(ensure(ctx, ws.sort_hist, gve::sort_hist_bytes((int64_t)T)));
+  const bool queue = ctx->opt.schedule == GVE_SCHED_QUEUE;
+  TRY(ensure(ctx, ws.sort_hist,
+             gve::sort_hist_bytes(std::max<int64_t>((int64_t)T, queue ? bg.nbricks : 0))));
   TRY(ensure(ctx, ws.brick_start, sizeof(uint32_t) * (size_t)(bg.nbricks + 1)));
   uint32_t* keys[2] = {static_cast<uint32_t*>(ws.keys[0].ptr), static_cast<uint32_t*>(ws.keys[1].ptr)};
   uint32_t* vals[2] = {static_cast<uint32_t*>(ws.vals[0].ptr), static_cast<uint32_t*>(ws.vals[1].ptr)};
-  TRY_HIP(ctx, gve::launch_emit(p->rec, p->offset, n, bg, keys[0], vals[0], s));
+  TRY_HIP(ctx, gve::launch_emit(p->rec, p->offset, n, items, vol.n, bg, keys[0], vals[0], s));
   int which = 0;
   TRY_HIP(ctx, gve::radix_sort_pairs(keys, vals, (int64_t)T, bits_for(bg.nbricks), ws.sort_hist.ptr,
                                      &which, s));
   uint32_t* start = static_cast<uint32_t*>(ws.brick_start.ptr);
   TRY_HIP(ctx, gve::launch_ranges(keys[which], (int64_t)T, bg.nbricks, start, s));
+  out->sched = gve::Schedule();
+  out->sched.kind = ctx->opt.schedule;
+  if (queue) {
+    const size_t ob = sizeof(uint32_t) * (size_t)std::max<int64_t>(bg.nbricks, 1);
+    for (int b = 0; b < 2; ++b) {
+      TRY(ensure(ctx, ws.order_keys[b], ob));
+      TRY(ensure(ctx, ws.order_vals[b], ob));
+    }
+    TRY(ensure(ctx, ws.queue, 256));
+    uint32_t* ok[2] = {static_cast<uint32_t*>(ws.order_keys[0].ptr),
+                       static_cast<uint32_t*>(ws.order_keys[1].ptr)};
+    uint32_t* ov[2] = {static_cast<uint32_t*>(ws.order_vals[0].ptr),
+                       static_cast<uint32_t*>(ws.order_vals[1].ptr)};
+    TRY_HIP(ctx, gve::launch_order_keys(start, bg.nbricks, ok[0], ov[0], s));
+    int ow = 0;
+    TRY_HIP(ctx, gve::radix_sort_pairs(ok, ov, bg.nbricks, 6, ws.sort_hist.ptr, &ow, s));
+    out->sched.order = ov[ow];
+    out->sched.counter = static_cast<uint32_t*>(ws.queue.ptr);
+    out->sched.persistent_groups = resident_groups(ctx, bg.Bxy, bg.Bz);
+    if (out->sched.persistent_groups <= 0)
+      return fail(ctx, GVE_ERR_DEVICE, "occupancy query for the persistent launch failed");
+  }
   out->bg = bg;
+  out->items = items;
+  out->nitems = vol.n;
   out->gid = vals[which];
   out->start = start;
   out->npairs = (int64_t)T;
   ctx->stats.n_primitives = n;
   ctx->stats.n_bricks = bg.nbricks;
   ctx->stats.n_overlaps = (int64_t)T;
+  return GVE_OK;
+}
+
+gve_status bin(gve_ctx* ctx, const gve_params* p, const gve_grid& g, Binned* out) {
+  const int64_t off[2] = {0, p->n};
+  return bin_vol(ctx, p, Vol{&g, off, 1}, out);
+}
+
+// Launch the fused kernel over a binning (resets the queue counter first).
+gve_status fused(gve_ctx* ctx, const gve_params* p, const Binned& bn, const float* d_field,
+                 float* part, float* brick_loss, bool vjp) {
+  if (bn.sched.kind == gve::kSchedQueue)
+    TRY_HIP(ctx, gve::fill_u32(bn.sched.counter, 1, ctx->stream));
+  TRY_HIP(ctx, gve::launch_fused(p->rec, bn.gid, bn.start, bn.items, bn.nitems, bn.bg,
+                                 ctx->opt.k, d_field, p->acc, p->n, part, p->offset, brick_loss,
+                                 bn.sched, ctx->stream, vjp));
+  return GVE_OK;
+}
+
+// Loss of every volume of a binning into out[0 .. nitems).
+gve_status losses(gve_ctx* ctx, const Binned& bn, const float* brick_loss, double* out) {
+  double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
+  if (bn.nitems == 1)
+    TRY_HIP(ctx, gve::launch_loss_reduce(brick_loss, bn.bg.nbricks, dl + 16, out, ctx->stream));
+  else
+    TRY_HIP(ctx, gve::launch_item_loss(brick_loss, bn.items, bn.nitems, bn.bg.nbricks, out,
+                                       ctx->stream));
   return GVE_OK;
 }
 
@@ -195,21 +309,26 @@ gve_status partials_for(gve_ctx* ctx, int64_t npairs, float** part) {
   return GVE_OK;
 }
 
-// Fused forward + squared error + backward into p->acc, loss into dloss[0].
-gve_status loss_and_sums(gve_ctx* ctx, const gve_params* p, const float* d_field, const gve_grid& g,
-                         double* d_loss_out, float** part_out) {
+// Fused forward + squared error + backward into p->acc (or the partials),
+// the loss of each volume into d_loss_out[0 .. vol.n).
+gve_status loss_and_sums_vol(gve_ctx* ctx, const gve_params* p, const float* d_field, const Vol& vol,
+                             double* d_loss_out, float** part_out) {
   Binned bn;
-  TRY(bin(ctx, p, g, &bn));
-  TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)bn.bg.nbricks));
+  TRY(bin_vol(ctx, p, vol, &bn));
+  TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)std::max<int64_t>(bn.bg.nbricks, 1)));
   float* bl = static_cast<float*>(ctx->ws.brick_loss.ptr);
   float* part = nullptr;
   TRY(partials_for(ctx, bn.npairs, &part));
   *part_out = part;
-  TRY_HIP(ctx, gve::launch_fused(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, d_field, p->acc,
-                                 p->n, part, p->offset, bl, ctx->stream));
-  double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
-  TRY_HIP(ctx, gve::launch_loss_reduce(bl, bn.bg.nbricks, dl + 16, d_loss_out, ctx->stream));
+  TRY(fused(ctx, p, bn, d_field, part, bl, false));
+  TRY(losses(ctx, bn, bl, d_loss_out));
   return GVE_OK;
+}
+
+gve_status loss_and_sums(gve_ctx* ctx, const gve_params* p, const float* d_field, const gve_grid& g,
+                         double* d_loss_out, float** part_out) {
+  const int64_t off[2] = {0, p->n};
+  return loss_and_sums_vol(ctx, p, d_field, Vol{&g, off, 1}, d_loss_out, part_out);
 }
 
 unsigned long long* clamp_counter(gve_ctx* ctx) {
@@ -225,6 +344,13 @@ hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t fill_u32(uint32_t* p, int64_t n, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 
@@ -266,6 +392,7 @@ gve_status gve_default_options(gve_options* opt) {
   opt->ell_min = -INFINITY;
   opt->ell_max = INFINITY;
   opt->brick_z = 32;
+  opt->schedule = GVE_SCHED_INDEX;
   opt->deterministic = 1;
   return GVE_OK;
 }
@@ -300,7 +427,8 @@ gve_status gve_destroy(gve_ctx* ctx) {
   Scratch* all[] = {&ws.keys[0], &ws.keys[1], &ws.vals[0], &ws.vals[1], &ws.brick_start,
                     &ws.brick_loss, &ws.scan_tmp, &ws.sort_hist, &ws.dloss, &ws.clamp_count,
                     &ws.grad_tmp, &ws.alloc, &ws.voxf, &ws.partials, &ws.mlp,
-                    &ws.sat, &ws.feat, &ws.theta_base};
+                    &ws.sat, &ws.feat, &ws.theta_base, &ws.items, &ws.order_keys[0],
+                    &ws.order_keys[1], &ws.order_vals[0], &ws.order_vals[1], &ws.queue};
   for (Scratch* s : all)
     if (s->ptr) hipFree(s->ptr);
   if (ws.h_pinned) hipHostFree(ws.h_pinned);
@@ -434,8 +562,8 @@ gve_status gve_evaluate(gve_ctx* ctx, const gve_params* p, gve_grid g, float* d_
   TRY(set_device(ctx));
   Binned bn;
   TRY(bin(ctx, p, g, &bn));
-  TRY_HIP(ctx, gve::launch_forward(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, d_out,
-                                   ctx->stream));
+  TRY_HIP(ctx, gve::launch_forward(p->rec, bn.gid, bn.start, bn.items, bn.nitems, bn.bg,
+                                   ctx->opt.k, d_out, bn.sched, ctx->stream));
   return GVE_OK;
 }
 
@@ -479,13 +607,11 @@ gve_status gve_vjp(gve_ctx* ctx, const gve_params* p, const float* d_upstream, g
   gve_params* pm = const_cast<gve_params*>(p);
   Binned bn;
   TRY(bin(ctx, p, g, &bn));
-  TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)bn.bg.nbricks));
+  TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)std::max<int64_t>(bn.bg.nbricks, 1)));
   float* part = nullptr;
   TRY(partials_for(ctx, bn.npairs, &part));
   if (!part) TRY_HIP(ctx, gve::fill_f32(pm->acc, 10 * p->n, 0.0f, ctx->stream));
-  TRY_HIP(ctx, gve::launch_fused(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, d_upstream,
-                                 pm->acc, p->n, part, p->offset,
-                                 static_cast<float*>(ctx->ws.brick_loss.ptr), ctx->stream, true));
+  TRY(fused(ctx, p, bn, d_upstream, part, static_cast<float*>(ctx->ws.brick_loss.ptr), true));
   TRY_HIP(ctx, gve::launch_update(0, pm->theta, pm->m, pm->v, pm->acc, part, p->offset, nullptr,
                                   d_grad, p->n, p->t, ctx->opt, nullptr, ctx->stream));
   return GVE_OK;
@@ -686,7 +812,8 @@ gve_status gve_count_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, int64_
   TRY(bin(ctx, p, g, &bn));
   unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ctx->ws.dloss.ptr) + 4;
   TRY_HIP(ctx, gve::fill_u64(cnt, 2, ctx->stream));
-  TRY_HIP(ctx, gve::launch_count(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, cnt, ctx->stream));
+  TRY_HIP(ctx, gve::launch_count(p->rec, bn.gid, bn.start, bn.items, bn.nitems, bn.bg, ctx->opt.k,
+                                 cnt, ctx->stream));
   TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, cnt, 16, hipMemcpyDeviceToHost, ctx->stream));
   TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
   *h_in_support = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[0];
@@ -694,15 +821,15 @@ gve_status gve_count_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, int64_
   return GVE_OK;
 }
 
-gve_status gve_refine(gve_ctx* ctx, gve_params* p, const float* d_field, gve_grid g,
+namespace {
+
+// `iters` fused iterations over a volume set; h_loss_hist [iters][vol.n].
+gve_status refine_vol(gve_ctx* ctx, gve_params* p, const float* d_field, const Vol& vol,
                       int32_t iters, double* h_loss_hist) {
-  TRY(check_ctx_params(ctx, p));
-  if (!d_field) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "d_field is NULL");
-  if (iters < 0) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "iters must be >= 0");
-  TRY(validate_grid(ctx, g));
   TRY(set_device(ctx));
   TRY(ensure_dloss(ctx));
-  TRY(ensure(ctx, ctx->ws.grad_tmp, sizeof(double) * (size_t)(iters > 0 ? iters : 1)));
+  const size_t nl = (size_t)vol.n * (size_t)(iters > 0 ? iters : 1);
+  TRY(ensure(ctx, ctx->ws.grad_tmp, sizeof(double) * nl));
   double* hist = static_cast<double*>(ctx->ws.grad_tmp.ptr);
   TRY_HIP(ctx, gve::fill_f32(p->acc, 10 * p->n, 0.0f, ctx->stream));
   const bool timing = ctx->timing && iters > 0;
@@ -718,17 +845,16 @@ gve_status gve_refine(gve_ctx* ctx, gve_params* p, const float* d_field, gve_gri
     hipEvent_t* ev = timing ? &ctx->events[4 * (size_t)it] : nullptr;
     if (timing) TRY_HIP(ctx, hipEventRecord(ev[0], s));
     Binned bn;
-    TRY(bin(ctx, p, g, &bn));
-    TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)bn.bg.nbricks));
+    TRY(bin_vol(ctx, p, vol, &bn));
+    TRY(ensure(ctx, ctx->ws.brick_loss,
+               sizeof(float) * (size_t)std::max<int64_t>(bn.bg.nbricks, 1)));
     float* bl = static_cast<float*>(ctx->ws.brick_loss.ptr);
     float* part = nullptr;
     TRY(partials_for(ctx, bn.npairs, &part));
     if (timing) TRY_HIP(ctx, hipEventRecord(ev[1], s));
-    TRY_HIP(ctx, gve::launch_fused(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, d_field,
-                                   p->acc, p->n, part, p->offset, bl, s));
+    TRY(fused(ctx, p, bn, d_field, part, bl, false));
     if (timing) TRY_HIP(ctx, hipEventRecord(ev[2], s));
-    double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
-    TRY_HIP(ctx, gve::launch_loss_reduce(bl, bn.bg.nbricks, dl + 16, hist + it, s));
+    TRY(losses(ctx, bn, bl, hist + (size_t)it * vol.n));
     p->t += 1;
     TRY_HIP(ctx, gve::launch_update(1, p->theta, p->m, p->v, p->acc, part, p->offset, nullptr,
                                     nullptr, p->n, p->t, ctx->opt, clamp_counter(ctx), s));
@@ -754,21 +880,33 @@ gve_status gve_refine(gve_ctx* ctx, gve_params* p, const float* d_field, gve_gri
   if (iters > 0) {
     TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, clamp_counter(ctx), sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, ctx->stream));
-    double last = 0.0;
     if (h_loss_hist) {
-      TRY_HIP(ctx, hipMemcpyAsync(h_loss_hist, hist, sizeof(double) * (size_t)iters,
-                                  hipMemcpyDeviceToHost, ctx->stream));
+      TRY_HIP(ctx, hipMemcpyAsync(h_loss_hist, hist, sizeof(double) * nl, hipMemcpyDeviceToHost,
+                                  ctx->stream));
     }
     TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->stats.n_clamped = (int64_t) * static_cast<unsigned long long*>(ctx->ws.h_pinned);
     if (h_loss_hist) {
-      last = h_loss_hist[iters - 1];
+      double last = 0.0;
+      for (int i = 0; i < vol.n; ++i) last += h_loss_hist[(size_t)(iters - 1) * vol.n + i];
       ctx->stats.last_loss = last;
-      for (int32_t it = 0; it < iters; ++it)
-        if (!std::isfinite(h_loss_hist[it])) return fail(ctx, GVE_ERR_NUMERIC, "loss is not finite");
+      for (size_t i = 0; i < nl; ++i)
+        if (!std::isfinite(h_loss_hist[i])) return fail(ctx, GVE_ERR_NUMERIC, "loss is not finite");
     }
   }
   return GVE_OK;
+}
+
+}  // namespace
+
+gve_status gve_refine(gve_ctx* ctx, gve_params* p, const float* d_field, gve_grid g,
+                      int32_t iters, double* h_loss_hist) {
+  TRY(check_ctx_params(ctx, p));
+  if (!d_field) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "d_field is NULL");
+  if (iters < 0) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "iters must be >= 0");
+  TRY(validate_grid(ctx, g));
+  const int64_t off[2] = {0, p->n};
+  return refine_vol(ctx, p, d_field, Vol{&g, off, 1}, iters, h_loss_hist);
 }
 
 gve_status gve_normalize(gve_ctx* ctx, float* d_field, int64_t n) {
@@ -881,7 +1019,8 @@ gve_status gve_allocate(gve_ctx* ctx, const float* d_field, gve_grid g, int64_t 
   Binned bn;
   st = bin(ctx, p, g, &bn);
   if (st != GVE_OK) return cleanup(st);
-  TRY_A(gve::launch_forward(p->rec, bn.gid, bn.start, g, bn.bg, ctx->opt.k, g32, s));
+  TRY_A(gve::launch_forward(p->rec, bn.gid, bn.start, bn.items, bn.nitems, bn.bg, ctx->opt.k, g32,
+                            bn.sched, s));
   TRY_A(gve::alloc_weights(g32, d_field, M, p->theta + 10 * budget, budget, F64(o_dot), s));
 #undef TRY_A
   // report
@@ -1273,3 +1412,335 @@ gve_status gve_warmstart(gve_ctx* ctx, const gve_mlp* m, gve_params* p, const fl
 }
 
 }  // extern "C"
+
+// ---- batched volumes ------------------------------------------------------------
+
+struct gve_batch {
+  int device = 0;
+  std::vector<gve_grid> grids;
+  std::vector<int64_t> prim_off, vox_off;  // [n_items + 1]
+  gve_params* params = nullptr;
+};
+
+namespace {
+
+Vol vol_of(const gve_batch* b) {
+  return Vol{b->grids.data(), b->prim_off.data(), (int)b->grids.size()};
+}
+
+gve_status check_batch(const gve_ctx* ctx, const gve_batch* b) {
+  if (!ctx) return GVE_ERR_INVALID_ARGUMENT;
+  const_cast<gve_ctx*>(ctx)->last_error.clear();
+  if (!b) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "batch is NULL");
+  if (b->device != ctx->device)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "batch and context are on different devices");
+  return GVE_OK;
+}
+
+}  // namespace
+
+gve_status gve_batch_create(gve_ctx* ctx, int32_t n_items, const gve_grid* h_grids,
+                            const int64_t* h_counts, gve_batch** out) {
+  if (!ctx || !out) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  if (n_items < 1 || n_items > (1 << 20) || !h_grids || !h_counts)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "need 1 <= n_items <= 2^20, grids and counts");
+  int64_t prims = 0, vox = 0;
+  for (int32_t i = 0; i < n_items; ++i) {
+    TRY(validate_grid(ctx, h_grids[i]));
+    if (h_counts[i] < 1) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "every count must be >= 1");
+    prims += h_counts[i];
+    vox += h_grids[i].nx * h_grids[i].ny * h_grids[i].nz;
+    if (prims >= ((int64_t)1 << 31))
+      return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "more than 2^31 - 1 primitives in the batch");
+    if (vox > ((int64_t)1 << 36)) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "batch too large");
+  }
+  gve_batch* b = new (std::nothrow) gve_batch();
+  if (!b) return GVE_ERR_OUT_OF_MEMORY;
+  b->device = ctx->device;
+  b->grids.assign(h_grids, h_grids + n_items);
+  b->prim_off.assign((size_t)n_items + 1, 0);
+  b->vox_off.assign((size_t)n_items + 1, 0);
+  for (int32_t i = 0; i < n_items; ++i) {
+    b->prim_off[i + 1] = b->prim_off[i] + h_counts[i];
+    b->vox_off[i + 1] = b->vox_off[i] + h_grids[i].nx * h_grids[i].ny * h_grids[i].nz;
+  }
+  const gve_status st = gve_params_create(ctx, prims, &b->params);
+  if (st != GVE_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return GVE_OK;
+}
+
+void gve_batch_destroy(gve_batch* b) {
+  if (!b) return;
+  if (b->params) gve_params_destroy(b->params);
+  delete b;
+}
+
+gve_status gve_batch_params(gve_batch* b, gve_params** out) {
+  if (!b || !out) return GVE_ERR_INVALID_ARGUMENT;
+  *out = b->params;
+  return GVE_OK;
+}
+
+gve_status gve_batch_offsets(const gve_batch* b, int64_t* h_prim_off, int64_t* h_vox_off) {
+  if (!b) return GVE_ERR_INVALID_ARGUMENT;
+  if (h_prim_off) std::copy(b->prim_off.begin(), b->prim_off.end(), h_prim_off);
+  if (h_vox_off) std::copy(b->vox_off.begin(), b->vox_off.end(), h_vox_off);
+  return GVE_OK;
+}
+
+namespace {
+
+gve_status item_copy(gve_ctx* ctx, const gve_batch* b, int32_t item, gve_params* other,
+                     bool into_batch) {
+  TRY(check_batch(ctx, b));
+  if (!other) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "params is NULL");
+  if (item < 0 || item >= (int32_t)b->grids.size())
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "item out of range");
+  const int64_t off = b->prim_off[item], cnt = b->prim_off[item + 1] - off;
+  if (other->n != cnt)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "params size differs from the item's count");
+  TRY(set_device(ctx));
+  const int64_t N = b->params->n;
+  const size_t w = sizeof(float) * (size_t)cnt, ld = sizeof(float) * (size_t)N;
+  float* bt = b->params->theta + off;
+  if (into_batch) {
+    TRY_HIP(ctx, hipMemcpy2DAsync(bt, ld, other->theta, w, w, 11, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+    const int64_t blocks = std::min<int64_t>((11 * cnt + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_cols, dim3((unsigned)blocks), dim3(256), 0, ctx->stream,
+                       b->params->m, N, off, cnt, 11);
+    TRY_HIP(ctx, hipGetLastError());
+    hipLaunchKernelGGL(k_zero_cols, dim3((unsigned)blocks), dim3(256), 0, ctx->stream,
+                       b->params->v, N, off, cnt, 11);
+    TRY_HIP(ctx, hipGetLastError());
+  } else {
+    TRY_HIP(ctx, hipMemcpy2DAsync(other->theta, w, bt, ld, w, 11, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+  }
+  return GVE_OK;
+}
+
+}  // namespace
+
+gve_status gve_batch_set_item(gve_ctx* ctx, gve_batch* b, int32_t item, const gve_params* src) {
+  return item_copy(ctx, b, item, const_cast<gve_params*>(src), true);
+}
+
+gve_status gve_batch_get_item(gve_ctx* ctx, const gve_batch* b, int32_t item, gve_params* dst) {
+  return item_copy(ctx, b, item, dst, false);
+}
+
+gve_status gve_batch_evaluate(gve_ctx* ctx, const gve_batch* b, float* d_out) {
+  TRY(check_batch(ctx, b));
+  if (!d_out) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "d_out is NULL");
+  TRY(set_device(ctx));
+  Binned bn;
+  TRY(bin_vol(ctx, b->params, vol_of(b), &bn));
+  TRY_HIP(ctx, gve::launch_forward(b->params->rec, bn.gid, bn.start, bn.items, bn.nitems, bn.bg,
+                                   ctx->opt.k, d_out, bn.sched, ctx->stream));
+  return GVE_OK;
+}
+
+gve_status gve_batch_loss_grad(gve_ctx* ctx, const gve_batch* b, const float* d_fields,
+                               float* d_grad, double* h_loss) {
+  TRY(check_batch(ctx, b));
+  if (!d_fields) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "d_fields is NULL");
+  TRY(set_device(ctx));
+  TRY(ensure_dloss(ctx));
+  gve_params* pm = b->params;
+  const int ni = (int)b->grids.size();
+  TRY(ensure(ctx, ctx->ws.grad_tmp, sizeof(double) * (size_t)ni));
+  double* dl = static_cast<double*>(ctx->ws.grad_tmp.ptr);
+  TRY_HIP(ctx, gve::fill_f32(pm->acc, 10 * pm->n, 0.0f, ctx->stream));
+  float* part = nullptr;
+  TRY(loss_and_sums_vol(ctx, pm, d_fields, vol_of(b), dl, &part));
+  if (d_grad) {
+    TRY_HIP(ctx, gve::launch_update(0, pm->theta, pm->m, pm->v, pm->acc, part, pm->offset, nullptr,
+                                    d_grad, pm->n, pm->t, ctx->opt, nullptr, ctx->stream));
+  } else {
+    TRY_HIP(ctx, gve::fill_f32(pm->acc, 10 * pm->n, 0.0f, ctx->stream));
+  }
+  if (h_loss) {
+    TRY_HIP(ctx, hipMemcpyAsync(h_loss, dl, sizeof(double) * (size_t)ni, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double tot = 0.0;
+    for (int i = 0; i < ni; ++i) tot += h_loss[i];
+    ctx->stats.last_loss = tot;
+    if (!std::isfinite(tot)) return fail(ctx, GVE_ERR_NUMERIC, "loss is not finite");
+  }
+  return GVE_OK;
+}
+
+gve_status gve_batch_refine(gve_ctx* ctx, gve_batch* b, const float* d_fields, int32_t iters,
+                            double* h_loss) {
+  TRY(check_batch(ctx, b));
+  if (!d_fields) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "d_fields is NULL");
+  if (iters < 0) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "iters must be >= 0");
+  return refine_vol(ctx, b->params, d_fields, vol_of(b), iters, h_loss);
+}
+
+gve_status gve_batch_count_pairs(gve_ctx* ctx, const gve_batch* b, int64_t* h_in_support,
+                                 int64_t* h_candidates) {
+  TRY(check_batch(ctx, b));
+  if (!h_in_support || !h_candidates)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "output pointers are required");
+  TRY(set_device(ctx));
+  Binned bn;
+  TRY(bin_vol(ctx, b->params, vol_of(b), &bn));
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ctx->ws.dloss.ptr) + 4;
+  TRY_HIP(ctx, gve::fill_u64(cnt, 2, ctx->stream));
+  TRY_HIP(ctx, gve::launch_count(b->params->rec, bn.gid, bn.start, bn.items, bn.nitems, bn.bg,
+                                 ctx->opt.k, cnt, ctx->stream));
+  TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, cnt, 16, hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *h_in_support = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[0];
+  *h_candidates = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[1];
+  return GVE_OK;
+}
+
+// ---- autotuner -----------------------------------------------------------------
+
+namespace {
+
+// Restores the context's options on every exit unless committed.
+struct OptionsGuard {
+  gve_ctx* ctx;
+  gve_options saved;
+  bool keep = false;
+  explicit OptionsGuard(gve_ctx* c) : ctx(c), saved(c->opt) {}
+  ~OptionsGuard() {
+    if (!keep) ctx->opt = saved;
+  }
+};
+
+// One timed unit of the tuner: binning + fused kernel + per-volume loss.
+gve_status tune_pass(gve_ctx* ctx, const gve_params* p, const float* d_field, const Vol& vol) {
+  Binned bn;
+  TRY(bin_vol(ctx, p, vol, &bn));
+  TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)std::max<int64_t>(bn.bg.nbricks, 1)));
+  float* bl = static_cast<float*>(ctx->ws.brick_loss.ptr);
+  float* part = nullptr;
+  TRY(partials_for(ctx, bn.npairs, &part));
+  TRY(fused(ctx, p, bn, d_field, part, bl, false));
+  TRY(ensure(ctx, ctx->ws.grad_tmp, sizeof(double) * (size_t)vol.n));
+  TRY(losses(ctx, bn, bl, static_cast<double*>(ctx->ws.grad_tmp.ptr)));
+  return GVE_OK;
+}
+
+int bucket(double x, double per_octave) {
+  return (int)std::lround(std::log2(std::max(x, 1e-6)) * per_octave);
+}
+
+}  // namespace
+
+gve_status gve_autotune(gve_ctx* ctx, const gve_params* p, const float* d_field, gve_grid g,
+                        const gve_batch* b, int32_t reps, gve_tune_entry* h_table,
+                        int32_t table_len, int32_t* n_written) {
+  if (!ctx) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  if (n_written) *n_written = 0;
+  if (!d_field) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "field is NULL");
+  if (reps < 1 || reps > 1000) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "reps must be in [1, 1000]");
+  if (table_len < 0 || (table_len > 0 && !h_table))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "table_len > 0 needs a table");
+  const int64_t single_off[2] = {0, p ? p->n : 0};
+  Vol vol;
+  gve_params* P;
+  int64_t M = 0;
+  if (b) {
+    TRY(check_batch(ctx, b));
+    vol = vol_of(b);
+    P = b->params;
+    M = b->vox_off.back();
+  } else {
+    TRY(check_ctx_params(ctx, p));
+    TRY(validate_grid(ctx, g));
+    vol = Vol{&g, single_off, 1};
+    P = const_cast<gve_params*>(p);
+    M = g.nx * g.ny * g.nz;
+  }
+  TRY(set_device(ctx));
+  TRY(ensure_dloss(ctx));
+  OptionsGuard guard(ctx);
+  // cache key: box coverage per voxel measured at 8x8x8
+  ctx->opt.brick = 8;
+  ctx->opt.brick_z = 8;
+  ctx->opt.schedule = GVE_SCHED_INDEX;
+  {
+    Binned bn;
+    TRY(bin_vol(ctx, P, vol, &bn));
+  }
+  const double cover = (double)ctx->stats.n_overlaps * 512.0 / (double)M;
+  const std::array<int, 4> key = {vol.n, bucket((double)M, 1.0), bucket((double)P->n, 1.0),
+                                  bucket(cover, 2.0)};
+  auto hit = ctx->tuned.find(key);
+  gve_options best = guard.saved;
+  if (hit != ctx->tuned.end()) {
+    best.brick = hit->second[0];
+    best.brick_z = hit->second[1];
+    best.schedule = hit->second[2];
+    ctx->opt = best;
+    guard.keep = true;
+    return GVE_OK;
+  }
+  static const int shapes[][2] = {{8, 8}, {8, 16}, {8, 32}, {16, 16}};
+  static const int scheds[] = {GVE_SCHED_INDEX, GVE_SCHED_XCD, GVE_SCHED_QUEUE};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TRY_HIP(ctx, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(ctx, GVE_ERR_DEVICE, "hipEventCreate");
+  }
+  struct Events {
+    hipEvent_t a, b;
+    ~Events() {
+      hipEventDestroy(a);
+      hipEventDestroy(b);
+    }
+  } events{e0, e1};
+  float best_ms = INFINITY;
+  int written = 0;
+  for (const auto& sh : shapes) {
+    for (int sc : scheds) {
+      ctx->opt = guard.saved;
+      ctx->opt.brick = sh[0];
+      ctx->opt.brick_z = sh[1];
+      ctx->opt.schedule = sc;
+      TRY(tune_pass(ctx, P, d_field, vol));  // warm-up
+      std::vector<float> ms;
+      for (int32_t r = 0; r < reps; ++r) {
+        TRY_HIP(ctx, hipEventRecord(e0, ctx->stream));
+        TRY(tune_pass(ctx, P, d_field, vol));
+        TRY_HIP(ctx, hipEventRecord(e1, ctx->stream));
+        TRY_HIP(ctx, hipEventSynchronize(e1));
+        float t = 0.0f;
+        TRY_HIP(ctx, hipEventElapsedTime(&t, e0, e1));
+        ms.push_back(t);
+      }
+      std::sort(ms.begin(), ms.end());
+      const float med = ms[ms.size() / 2];
+      if (written < table_len) h_table[written++] = gve_tune_entry{sh[0], sh[1], sc, med};
+      if (med < best_ms) {
+        best_ms = med;
+        best = guard.saved;
+        best.brick = sh[0];
+        best.brick_z = sh[1];
+        best.schedule = sc;
+      }
+    }
+  }
+  // the tuning passes added their sums to the accumulators (atomics mode)
+  TRY_HIP(ctx, gve::fill_f32(P->acc, 10 * P->n, 0.0f, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->tuned[key] = {best.brick, best.brick_z, best.schedule};
+  ctx->opt = best;
+  guard.keep = true;
+  if (n_written) *n_written = written;
+  return GVE_OK;
+}

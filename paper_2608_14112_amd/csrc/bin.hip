@@ -18,8 +18,19 @@ constexpr int kThreads = 256;
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Volume of primitive i: the last item whose first primitive is <= i.
+__device__ inline int item_of_prim(const ItemDesc* __restrict__ items, int nitems, uint32_t i) {
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].prim0 <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 __device__ inline uint32_t prep_one(const float* __restrict__ theta, int64_t n, int64_t i,
-                                    gve_grid g, float k, BrickGeom bg, Record* __restrict__ rec) {
+                                    const ItemDesc& g, float k, BrickGeom bg,
+                                    Record* __restrict__ rec) {
   const float mx = theta[0 * n + i], my = theta[1 * n + i], mz = theta[2 * n + i];
   float qw = theta[3 * n + i], qx = theta[4 * n + i], qy = theta[5 * n + i],
         qz = theta[6 * n + i];
@@ -105,13 +116,14 @@ __device__ inline uint32_t prep_one(const float* __restrict__ theta, int64_t n, 
 }
 
 __global__ __launch_bounds__(kThreads) void k_prep(const float* __restrict__ theta, int64_t n,
-                                                   gve_grid g, float k, BrickGeom bg,
+                                                   const ItemDesc* __restrict__ items, int nitems,
+                                                   float k, BrickGeom bg,
                                                    Record* __restrict__ rec,
                                                    uint32_t* __restrict__ count,
                                                    unsigned long long* __restrict__ total) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   uint32_t cnt = 0;
-  if (i < n) cnt = prep_one(theta, n, i, g, k, bg, rec);
+  if (i < n) cnt = prep_one(theta, n, i, items[item_of_prim(items, nitems, (uint32_t)i)], k, bg, rec);
   if (i < n) count[i] = cnt;
   // 64-bit pair total (the scan itself is 32-bit): one atomic per wave
   unsigned long long w = cnt;
@@ -122,6 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_prep(const float* __restrict__ the
 
 __global__ __launch_bounds__(kThreads) void k_emit(const Record* __restrict__ rec,
                                                    const uint32_t* __restrict__ offset, int64_t n,
+                                                   const ItemDesc* __restrict__ items, int nitems,
                                                    BrickGeom bg, uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -129,13 +142,15 @@ __global__ __launch_bounds__(kThreads) void k_emit(const Record* __restrict__ re
   uint32_t o = offset[i];
   const uint32_t e = offset[i + 1];
   if (o == e) return;
+  const ItemDesc& it = items[item_of_prim(items, nitems, (uint32_t)i)];
   const Record& r = rec[i];
   const int bx0 = r.lo[0] / bg.Bxy, bx1 = r.hi[0] / bg.Bxy;
   const int by0 = r.lo[1] / bg.Bxy, by1 = r.hi[1] / bg.Bxy;
   const int bz0 = r.lo[2] / bg.Bz, bz1 = r.hi[2] / bg.Bz;
   for (int bz = bz0; bz <= bz1; ++bz)
     for (int by = by0; by <= by1; ++by) {
-      const uint32_t row = (uint32_t)bg.nbx * ((uint32_t)by + (uint32_t)bg.nby * (uint32_t)bz);
+      const uint32_t row =
+          it.brick0 + (uint32_t)it.nbx * ((uint32_t)by + (uint32_t)it.nby * (uint32_t)bz);
       for (int bx = bx0; bx <= bx1; ++bx) {
         keys[o] = row + (uint32_t)bx;
         vals[o] = (uint32_t)i;
@@ -158,31 +173,64 @@ __global__ __launch_bounds__(kThreads) void k_ranges(const uint32_t* __restrict_
   start[b] = (uint32_t)lo;
 }
 
-}  // namespace
-
-BrickGeom brick_geometry(const gve_grid& g, int Bxy, int Bz) {
-  BrickGeom bg;
-  bg.Bxy = Bxy;
-  bg.Bz = Bz;
-  bg.nbx = (int)((g.nx + Bxy - 1) / Bxy);
-  bg.nby = (int)((g.ny + Bxy - 1) / Bxy);
-  bg.nbz = (int)((g.nz + Bz - 1) / Bz);
-  bg.nbricks = (int64_t)bg.nbx * bg.nby * bg.nbz;
-  return bg;
+// Sort keys of the heaviest-first order: fewer leading zeros in the pair
+// count = more work, so an ascending stable sort puts heavy bricks first and
+// keeps index order within a power-of-two class.
+__global__ __launch_bounds__(kThreads) void k_order_keys(const uint32_t* __restrict__ start,
+                                                         int64_t nbricks,
+                                                         uint32_t* __restrict__ keys,
+                                                         uint32_t* __restrict__ vals) {
+  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (b >= nbricks) return;
+  keys[b] = (uint32_t)__clz((int)(start[b + 1] - start[b]));
+  vals[b] = (uint32_t)b;
 }
 
-hipError_t launch_prep(const float* theta, int64_t n, gve_grid g, float k, BrickGeom bg,
-                       Record* rec, uint32_t* count, unsigned long long* total, hipStream_t s) {
+}  // namespace
+
+int64_t build_items(const gve_grid* grids, const int64_t* prim_off, int nitems, int Bxy, int Bz,
+                    ItemDesc* out) {
+  int64_t bricks = 0, vox = 0;
+  for (int i = 0; i < nitems; ++i) {
+    const gve_grid& g = grids[i];
+    ItemDesc d{};
+    d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
+    d.x0 = g.x0; d.y0 = g.y0; d.z0 = g.z0;
+    d.vox = vox;
+    d.nbx = (int32_t)((g.nx + Bxy - 1) / Bxy);
+    d.nby = (int32_t)((g.ny + Bxy - 1) / Bxy);
+    d.nbz = (int32_t)((g.nz + Bz - 1) / Bz);
+    d.brick0 = (uint32_t)bricks;
+    d.prim0 = (uint32_t)prim_off[i];
+    out[i] = d;
+    bricks += (int64_t)d.nbx * d.nby * d.nbz;
+    vox += g.nx * g.ny * g.nz;
+  }
+  return bricks;
+}
+
+hipError_t launch_prep(const float* theta, int64_t n, const ItemDesc* items, int nitems, float k,
+                       BrickGeom bg, Record* rec, uint32_t* count, unsigned long long* total,
+                       hipStream_t s) {
   const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(kThreads), 0, s, theta, n, g, k, bg, rec, count,
-                     total);
+  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(kThreads), 0, s, theta, n, items, nitems, k, bg,
+                     rec, count, total);
   return hipGetLastError();
 }
 
-hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, BrickGeom bg,
-                       uint32_t* keys, uint32_t* vals, hipStream_t s) {
+hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, const ItemDesc* items,
+                       int nitems, BrickGeom bg, uint32_t* keys, uint32_t* vals, hipStream_t s) {
   const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, rec, offset, n, bg, keys, vals);
+  hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, rec, offset, n, items, nitems, bg,
+                     keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_order_keys(const uint32_t* brick_start, int64_t nbricks, uint32_t* keys,
+                             uint32_t* vals, hipStream_t s) {
+  const unsigned blocks = (unsigned)((nbricks + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_order_keys, dim3(blocks), dim3(kThreads), 0, s, brick_start, nbricks, keys,
+                     vals);
   return hipGetLastError();
 }
 

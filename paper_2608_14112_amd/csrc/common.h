@@ -3,8 +3,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "gve.h"
@@ -33,6 +36,20 @@ static_assert(sizeof(Record) == 64, "record must be 64 bytes");
 
 constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
 
+// One volume of a set that is binned and evaluated together (a single-volume
+// call is a set of one).  Primitives [prim0, next prim0) belong to it and
+// reach only its bricks [brick0, next brick0); its voxels start at `vox` in
+// the concatenated field and output buffers (x fastest within the volume).
+struct ItemDesc {
+  int64_t nx, ny, nz, x0, y0, z0;  // the volume's grid
+  int64_t vox;                     // first voxel in the concatenated buffers
+  int32_t nbx, nby, nbz;           // bricks per axis
+  uint32_t brick0;                 // first global brick id
+  uint32_t prim0;                  // first primitive
+  uint32_t pad;
+};
+static_assert(sizeof(ItemDesc) == 80, "ItemDesc layout");
+
 struct Scratch {
   void* ptr = nullptr;
   size_t bytes = 0;
@@ -55,6 +72,9 @@ struct Workspace {
   Scratch sat;                   // double [2][M] summed-area tables of V and V^2
   Scratch feat;                  // float [n][16] features, then [n][11] network output
   Scratch theta_base;            // float [11][n] parameters before the warm start
+  Scratch items;                 // ItemDesc [volumes] of the current binning
+  Scratch order_keys[2], order_vals[2];  // heaviest-first brick order (queue schedule)
+  Scratch queue;                 // uint32 work counter of the persistent launch
   void* h_pinned = nullptr;      // pinned host staging (64 bytes)
 };
 
@@ -69,6 +89,9 @@ struct gve_ctx {
   std::string last_error;
   bool timing = false;
   std::vector<hipEvent_t> events;  // stage-timer pool, 4 per refinement iteration
+  std::vector<gve::ItemDesc> items_host;  // copy of ws.items (what the device holds)
+  std::map<std::pair<int, int>, int> resident;  // brick shape -> resident fused workgroups
+  std::map<std::array<int, 4>, std::array<int, 3>> tuned;  // autotuner cache
 };
 
 struct gve_params {
@@ -105,41 +128,71 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int
 // columns, each lane Bz voxels of its column.
 struct BrickGeom {
   int Bxy, Bz;           // brick edges in voxels
-  int nbx, nby, nbz;     // bricks per axis
-  int64_t nbricks;
+  int64_t nbricks;       // over every volume of the set
 };
 
-BrickGeom brick_geometry(const gve_grid& g, int Bxy, int Bz);
+
+// Host: descriptors of `nitems` volumes with primitive offsets prim_off
+// [nitems + 1]; returns the total brick count.
+int64_t build_items(const gve_grid* grids, const int64_t* prim_off, int nitems, int Bxy, int Bz,
+                    ItemDesc* out);
+
+// Order in which workgroups take bricks.
+//   kSchedIndex   : one workgroup per brick, brick = workgroup id;
+//   kSchedXcd     : one workgroup per brick, consecutive bricks grouped on one
+//                   XCD (workgroups are dealt round-robin over the 8 XCDs, so
+//                   each XCD's L2 sees a contiguous run of bricks and of the
+//                   primitives they share);
+//   kSchedQueue   : persistent workgroups (as many as fit on the chip) take
+//                   bricks from a counter in `order`, heaviest first.
+enum { kSchedIndex = 0, kSchedXcd = 1, kSchedQueue = 2 };
+struct Schedule {
+  int kind = kSchedIndex;
+  const uint32_t* order = nullptr;  // kSchedQueue: queue position -> brick
+  uint32_t* counter = nullptr;      // kSchedQueue: zeroed before the launch
+  int persistent_groups = 0;        // kSchedQueue: grid size
+};
 
 // Writes rec and count for every primitive and adds the pair total to *total
 // (which the caller zeroes first).
-hipError_t launch_prep(const float* theta, int64_t n, gve_grid g, float k, BrickGeom bg,
-                       Record* rec, uint32_t* count, unsigned long long* total, hipStream_t s);
-hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, BrickGeom bg,
-                       uint32_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_prep(const float* theta, int64_t n, const ItemDesc* items, int nitems, float k,
+                       BrickGeom bg, Record* rec, uint32_t* count, unsigned long long* total,
+                       hipStream_t s);
+hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, const ItemDesc* items,
+                       int nitems, BrickGeom bg, uint32_t* keys, uint32_t* vals, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t npairs, int64_t nbricks,
                          uint32_t* brick_start, hipStream_t s);
+// Heaviest-first brick order for kSchedQueue: keys = leading zeros of the
+// brick's pair count (sorted ascending, stably), vals = brick ids.
+hipError_t launch_order_keys(const uint32_t* brick_start, int64_t nbricks, uint32_t* keys,
+                             uint32_t* vals, hipStream_t s);
 
 // Brick shapes (Bxy, Bz) the field kernels are compiled for.
 bool brick_shape_supported(int bxy, int bz);
+// Workgroups of the fused kernel that fit on the device at once.
+int fused_resident_groups(int bxy, int bz, int device);
 hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid,
-                          const uint32_t* brick_start, gve_grid g, BrickGeom bg, float k,
-                          float* out, hipStream_t s);
+                          const uint32_t* brick_start, const ItemDesc* items, int nitems,
+                          BrickGeom bg, float k, float* out, const Schedule& sc, hipStream_t s);
 // part == nullptr: float atomics into acc [10][n].  Otherwise each (primitive,
 // brick) pair stores its ten sums to part[(offset[gid] + rank) * 10 + slot],
 // rank = the brick's position in the primitive's emitted brick range.
 hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid,
-                        const uint32_t* brick_start, gve_grid g, BrickGeom bg, float k,
-                        const float* field, float* acc, int64_t n, float* part,
-                        const uint32_t* offset, float* brick_loss, hipStream_t s,
-                        bool vjp = false);
+                        const uint32_t* brick_start, const ItemDesc* items, int nitems,
+                        BrickGeom bg, float k, const float* field, float* acc, int64_t n,
+                        float* part, const uint32_t* offset, float* brick_loss,
+                        const Schedule& sc, hipStream_t s, bool vjp = false);
 hipError_t launch_count(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
-                        gve_grid g, BrickGeom bg, float k, unsigned long long* counts,
-                        hipStream_t s);
+                        const ItemDesc* items, int nitems, BrickGeom bg, float k,
+                        unsigned long long* counts, hipStream_t s);
 // Sum of brick_loss in double into *out; part holds loss_reduce_tmp_doubles().
 size_t loss_reduce_tmp_doubles();
 hipError_t launch_loss_reduce(const float* brick_loss, int64_t nbricks, double* part, double* out,
                               hipStream_t s);
+// Per-volume sums of brick_loss in double: out[i] for volume i.
+hipError_t launch_item_loss(const float* brick_loss, const ItemDesc* items, int nitems,
+                            int64_t nbricks, double* out, hipStream_t s);
+hipError_t fill_u32(uint32_t* p, int64_t n, hipStream_t s);
 
 // Small utility kernels.
 hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t s);

@@ -24,6 +24,8 @@
 //               of a partials array that the update kernel sums per primitive
 //               in a fixed order.  Per column only sum e, sum e t, sum e t^2 are needed
 //               because dx, dy and dz - t are constant along it.
+#include <algorithm>
+
 #include "common.h"
 
 namespace gve {
@@ -149,33 +151,88 @@ __device__ inline void accumulate_brick(const Record* __restrict__ rec,
   }
 }
 
+// ---- where a brick lies --------------------------------------------------------
+//
+// Global brick b belongs to the last volume whose first brick is <= b; b is
+// wave-uniform, so the search and the descriptor loads are scalar.
+__device__ inline int item_of_brick(const ItemDesc* __restrict__ items, int nitems, uint32_t b) {
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].brick0 <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The lane's voxel column in brick b.
+struct Site {
+  int bx, by, bz;      // brick coordinates within its volume
+  int iz0;             // first z of the brick (volume index)
+  int zrem;            // voxels of the volume from iz0 on (may exceed the brick)
+  float px, py, pz0;   // lane column position (world), first z
+  bool col_in;         // the column lies inside the volume
+  size_t base, plane;  // column's voxel at z = 0 in the concatenated buffers, z stride
+};
+
+template <int BXY, int BZ>
+__device__ inline Site site_of(const ItemDesc* __restrict__ items, int nitems, uint32_t b) {
+  const ItemDesc& it = items[item_of_brick(items, nitems, b)];
+  const uint32_t lb = b - it.brick0;
+  const uint32_t nbx = (uint32_t)it.nbx, nby = (uint32_t)it.nby;
+  Site s;
+  s.bx = (int)(lb % nbx);
+  s.by = (int)((lb / nbx) % nby);
+  s.bz = (int)(lb / (nbx * nby));
+  const int ix = s.bx * BXY + (int)(threadIdx.x % BXY);
+  const int iy = s.by * BXY + (int)(threadIdx.x / BXY);
+  s.iz0 = s.bz * BZ;
+  s.zrem = (int)it.nz - s.iz0;
+  s.px = (float)(it.x0 + ix);
+  s.py = (float)(it.y0 + iy);
+  s.pz0 = (float)(it.z0 + s.iz0);
+  s.col_in = ix < it.nx && iy < it.ny;
+  s.plane = (size_t)it.nx * (size_t)it.ny;
+  s.base = (size_t)it.vox + (size_t)ix + (size_t)it.nx * (size_t)iy;
+  return s;
+}
+
+// Workgroup w -> brick when consecutive bricks go to one XCD: the dispatcher
+// deals workgroups round-robin over the 8 XCDs, so XCD x = w % 8 receives the
+// contiguous block of bricks [x q + min(x, r), ...) of size q + (x < r), with
+// nb = 8 q + r (a bijection of [0, nb)).
+__device__ inline uint32_t xcd_brick(uint32_t w, uint32_t nb) {
+  const uint32_t q = nb >> 3, r = nb & 7u, x = w & 7u, k = w >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+template <int BXY, int BZ>
+__device__ __attribute__((always_inline)) inline void forward_brick(const Record* __restrict__ rec,
+                                     const uint32_t* __restrict__ pair_gid,
+                                     const uint32_t* __restrict__ brick_start,
+                                     const ItemDesc* __restrict__ items, int nitems, uint32_t b,
+                                     float thr, float* __restrict__ out) {
+  const Site st = site_of<BXY, BZ>(items, nitems, b);
+  float acc[BZ];
+#pragma unroll
+  for (int zz = 0; zz < BZ; ++zz) acc[zz] = 0.0f;
+  accumulate_brick<BZ>(rec, pair_gid, brick_start[b], brick_start[b + 1], st.px, st.py, st.pz0,
+                       st.iz0, st.col_in, thr, acc);
+  if (st.col_in) {
+#pragma unroll
+    for (int zz = 0; zz < BZ; ++zz)
+      if (zz < st.zrem) out[st.base + st.plane * (size_t)(st.iz0 + zz)] = acc[zz];
+  }
+}
+
 template <int BXY, int BZ>
 __global__ __launch_bounds__(BXY* BXY) void k_forward(const Record* __restrict__ rec,
                                                   const uint32_t* __restrict__ pair_gid,
                                                   const uint32_t* __restrict__ brick_start,
-                                                  gve_grid g, BrickGeom bg, float thr,
+                                                  const ItemDesc* __restrict__ items, int nitems,
+                                                  uint32_t nbricks, int xcd, float thr,
                                                   float* __restrict__ out) {
-  const int64_t b = blockIdx.x;
-  const int bx = (int)(b % bg.nbx);
-  const int by = (int)((b / bg.nbx) % bg.nby);
-  const int bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-  const int ix = bx * BXY + (int)(threadIdx.x % BXY);
-  const int iy = by * BXY + (int)(threadIdx.x / BXY);
-  const int iz0 = bz * BZ;
-  const float px = (float)(g.x0 + ix), py = (float)(g.y0 + iy), pz0 = (float)(g.z0 + iz0);
-  const bool col_in = ix < g.nx && iy < g.ny;
-  float acc[BZ];
-#pragma unroll
-  for (int zz = 0; zz < BZ; ++zz) acc[zz] = 0.0f;
-  accumulate_brick<BZ>(rec, pair_gid, brick_start[b], brick_start[b + 1], px, py, pz0, iz0, col_in,
-                      thr, acc);
-  if (col_in) {
-    const size_t plane = (size_t)g.nx * (size_t)g.ny;
-    const size_t base = (size_t)ix + (size_t)g.nx * (size_t)iy;
-#pragma unroll
-    for (int zz = 0; zz < BZ; ++zz)
-      if (iz0 + zz < g.nz) out[base + plane * (size_t)(iz0 + zz)] = acc[zz];
-  }
+  const uint32_t b = xcd ? xcd_brick(blockIdx.x, nbricks) : blockIdx.x;
+  forward_brick<BXY, BZ>(rec, pair_gid, brick_start, items, nitems, b, thr, out);
 }
 
 // Slot of the (primitive, brick) pair in the partials array: the primitive's
@@ -189,45 +246,38 @@ __device__ inline uint32_t pair_slot(const Record& r, const uint32_t* __restrict
   return offset[gid] + (uint32_t)((rbz * nby_g + rby) * nbx_g + rbx);
 }
 
-// VJP = false: residual r = 2 (Vhat - V) from the forward pass and the target
-// `field`, loss share to brick_loss.  VJP = true: no forward pass; r is read
-// from `field` (an upstream gradient dl/dVhat), so the ten sums give the
-// vector-Jacobian product sum_p r(p) dVhat(p)/dtheta.
+// One brick of the fused pass.  VJP = false: residual r = 2 (Vhat - V) from
+// the forward pass and the target `field`, loss share to brick_loss.
+// VJP = true: no forward pass; r is read from `field` (an upstream gradient
+// dl/dVhat), so the ten sums give the vector-Jacobian product
+// sum_p r(p) dVhat(p)/dtheta.
 template <int BXY, int BZ, bool VJP>
-__global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ rec,
-                                                const uint32_t* __restrict__ pair_gid,
-                                                const uint32_t* __restrict__ brick_start,
-                                                gve_grid g, BrickGeom bg, float thr,
-                                                const float* __restrict__ field,
-                                                float* __restrict__ gacc, int64_t n,
-                                                float* __restrict__ part,
-                                                const uint32_t* __restrict__ offset,
-                                                float* __restrict__ brick_loss) {
+__device__ __attribute__((always_inline)) inline void fused_brick(const Record* __restrict__ rec,
+                                   const uint32_t* __restrict__ pair_gid,
+                                   const uint32_t* __restrict__ brick_start,
+                                   const ItemDesc* __restrict__ items, int nitems, uint32_t b,
+                                   float thr, const float* __restrict__ field,
+                                   float* __restrict__ gacc, int64_t n, float* __restrict__ part,
+                                   const uint32_t* __restrict__ offset,
+                                   float* __restrict__ brick_loss,
+                                   float (*red)[10]) {
   constexpr int kWaves = (BXY * BXY + 63) / 64;
-  __shared__ float red[kWaves][10];
-  const int64_t b = blockIdx.x;
-  const int bx = (int)(b % bg.nbx);
-  const int by = (int)((b / bg.nbx) % bg.nby);
-  const int bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-  const int ix = bx * BXY + (int)(threadIdx.x % BXY);
-  const int iy = by * BXY + (int)(threadIdx.x / BXY);
-  const int iz0 = bz * BZ;
+  const Site st = site_of<BXY, BZ>(items, nitems, b);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int row = lane >> 4;
-  const float px = (float)(g.x0 + ix), py = (float)(g.y0 + iy), pz0 = (float)(g.z0 + iz0);
-  const bool col_in = (ix < g.nx) && (iy < g.ny);
+  const float px = st.px, py = st.py, pz0 = st.pz0;
+  const int iz0 = st.iz0;
+  const bool col_in = st.col_in;
   const uint32_t j0 = brick_start[b], j1 = brick_start[b + 1];
 
   float res[BZ];
 #pragma unroll
   for (int zz = 0; zz < BZ; ++zz) res[zz] = 0.0f;
-  const size_t plane = (size_t)g.nx * (size_t)g.ny;
-  const size_t base = (size_t)ix + (size_t)g.nx * (size_t)iy;
   if (VJP) {
 #pragma unroll
     for (int zz = 0; zz < BZ; ++zz)
-      if (col_in && iz0 + zz < g.nz) res[zz] = field[base + plane * (size_t)(iz0 + zz)];
+      if (col_in && zz < st.zrem) res[zz] = field[st.base + st.plane * (size_t)(iz0 + zz)];
   } else {
     accumulate_brick<BZ>(rec, pair_gid, j0, j1, px, py, pz0, iz0, col_in, thr, res);
     // residual and this brick's share of the loss
@@ -235,8 +285,8 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
 #pragma unroll
     for (int zz = 0; zz < BZ; ++zz) {
       float r = 0.0f;
-      if (col_in && iz0 + zz < g.nz) {
-        const float d = res[zz] - field[base + plane * (size_t)(iz0 + zz)];
+      if (col_in && zz < st.zrem) {
+        const float d = res[zz] - field[st.base + st.plane * (size_t)(iz0 + zz)];
         lsum = fmaf(d, d, lsum);
         r = 2.0f * d;
       }
@@ -261,12 +311,12 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
     if (kWaves == 1 && !hit) {
       // a pair whose support misses every column still owns a partials slot
       if (part && lane < 10)
-        part[(size_t)pair_slot<BXY, BZ>(r, offset, gid, bx, by, bz) * 10 + lane] = 0.0f;
+        part[(size_t)pair_slot<BXY, BZ>(r, offset, gid, st.bx, st.by, st.bz) * 10 + lane] = 0.0f;
       continue;
     }
     float v[10];
     {
-      float se = 0.0f, st = 0.0f, stt = 0.0f;
+      float se = 0.0f, sT = 0.0f, sTT = 0.0f;
       if (hit) {
 #pragma unroll
         for (int zz = 0; zz < BZ; ++zz) {
@@ -278,18 +328,18 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
               const float e = res[zz] * G;
               se += e;
               const float et = e * t;
-              st += et;
-              stt = fmaf(et, t, stt);
+              sT += et;
+              sTT = fmaf(et, t, sTT);
             }
           }
         }
       }
-      // back to d = p - mu: sum e dz = st + ofs se, sum e dz^2 = stt + 2 ofs st + ofs^2 se
+      // back to d = p - mu: sum e dz = sT + ofs se, sum e dz^2 = sTT + 2 ofs sT + ofs^2 se
       const float dx = px - r.mu[0];
       const float dy = py - r.mu[1];
       const float ofs = (pz0 - r.mu[2]) - s.t0;
-      const float s1 = fmaf(ofs, se, st);
-      const float s2 = fmaf(ofs, fmaf(ofs, se, 2.0f * st), stt);
+      const float s1 = fmaf(ofs, se, sT);
+      const float s2 = fmaf(ofs, fmaf(ofs, se, 2.0f * sT), sTT);
       const float cse = r.c * se, cs1 = r.c * s1;
       v[0] = se;
       v[1] = dx * cse;
@@ -306,7 +356,7 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
     wave_reduce10(v, o);
     if (kWaves == 1) {
       if (part) {
-        const uint32_t slot_base = pair_slot<BXY, BZ>(r, offset, gid, bx, by, bz);
+        const uint32_t slot_base = pair_slot<BXY, BZ>(r, offset, gid, st.bx, st.by, st.bz);
         if ((lane & 15) == 0) {
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
@@ -334,13 +384,63 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
         float t = 0.0f;
         for (int w = 0; w < kWaves; ++w) t += red[w][threadIdx.x];
         if (part) {
-          part[(size_t)pair_slot<BXY, BZ>(r, offset, gid, bx, by, bz) * 10 + threadIdx.x] = t;
+          part[(size_t)pair_slot<BXY, BZ>(r, offset, gid, st.bx, st.by, st.bz) * 10 +
+               threadIdx.x] = t;
         } else if (t != 0.0f) {
           unsafeAtomicAdd(&gacc[(int64_t)threadIdx.x * n + gid], t);
         }
       }
       __syncthreads();
     }
+  }
+}
+
+// One workgroup per brick (xcd: consecutive bricks grouped per XCD).
+template <int BXY, int BZ, bool VJP>
+__global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ rec,
+                                                const uint32_t* __restrict__ pair_gid,
+                                                const uint32_t* __restrict__ brick_start,
+                                                const ItemDesc* __restrict__ items, int nitems,
+                                                uint32_t nbricks, int xcd, float thr,
+                                                const float* __restrict__ field,
+                                                float* __restrict__ gacc, int64_t n,
+                                                float* __restrict__ part,
+                                                const uint32_t* __restrict__ offset,
+                                                float* __restrict__ brick_loss) {
+  constexpr int kWaves = (BXY * BXY + 63) / 64;
+  __shared__ float red[kWaves][10];
+  const uint32_t b = xcd ? xcd_brick(blockIdx.x, nbricks) : blockIdx.x;
+  fused_brick<BXY, BZ, VJP>(rec, pair_gid, brick_start, items, nitems, b, thr, field, gacc, n,
+                            part, offset, brick_loss, red);
+}
+
+// Persistent: each workgroup takes queue positions from *counter until they
+// run out (every workgroup reaches that exit) and processes brick
+// order[position] (heaviest first).
+template <int BXY, int BZ, bool VJP>
+__global__ __launch_bounds__(BXY* BXY) void k_fused_queue(const Record* __restrict__ rec,
+                                                      const uint32_t* __restrict__ pair_gid,
+                                                      const uint32_t* __restrict__ brick_start,
+                                                      const ItemDesc* __restrict__ items,
+                                                      int nitems, uint32_t nbricks,
+                                                      const uint32_t* __restrict__ order,
+                                                      uint32_t* __restrict__ counter, float thr,
+                                                      const float* __restrict__ field,
+                                                      float* __restrict__ gacc, int64_t n,
+                                                      float* __restrict__ part,
+                                                      const uint32_t* __restrict__ offset,
+                                                      float* __restrict__ brick_loss) {
+  constexpr int kWaves = (BXY * BXY + 63) / 64;
+  __shared__ float red[kWaves][10];
+  __shared__ uint32_t next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t w = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+    if (w >= nbricks) break;
+    fused_brick<BXY, BZ, VJP>(rec, pair_gid, brick_start, items, nitems, order[w], thr, field,
+                              gacc, n, part, offset, brick_loss, red);
   }
 }
 
@@ -352,27 +452,21 @@ template <int BXY, int BZ>
 __global__ __launch_bounds__(BXY* BXY) void k_count(const Record* __restrict__ rec,
                                                 const uint32_t* __restrict__ pair_gid,
                                                 const uint32_t* __restrict__ brick_start,
-                                                gve_grid g, BrickGeom bg, float thr,
+                                                const ItemDesc* __restrict__ items, int nitems,
+                                                float thr,
                                                 unsigned long long* __restrict__ counts) {
-  const int64_t b = blockIdx.x;
-  const int bx = (int)(b % bg.nbx);
-  const int by = (int)((b / bg.nbx) % bg.nby);
-  const int bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-  const int ix = bx * BXY + (int)(threadIdx.x % BXY);
-  const int iy = by * BXY + (int)(threadIdx.x / BXY);
-  const int iz0 = bz * BZ;
-  const float px = (float)(g.x0 + ix), py = (float)(g.y0 + iy), pz0 = (float)(g.z0 + iz0);
-  const bool col_in = ix < g.nx && iy < g.ny;
+  const uint32_t b = blockIdx.x;
+  const Site st = site_of<BXY, BZ>(items, nitems, b);
   unsigned long long nin = 0, ncand = 0;
   for (uint32_t j = brick_start[b]; j < brick_start[b + 1]; ++j) {
     const Record r = load_record(rec, __builtin_amdgcn_readfirstlane(pair_gid[j]));
-    const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
-    if (!column_hit(s, col_in, thr)) continue;
+    const ColumnSetup s = column_setup<BZ>(r, st.px, st.py, st.pz0, st.iz0);
+    if (!column_hit(s, st.col_in, thr)) continue;
     for (int zz = s.za; zz <= s.zb; ++zz) {
       const float q = quad_at(s, r.azz, s.t0 + (float)zz);
       if (__builtin_amdgcn_ballot_w64(q > thr) == 0ull) continue;
       ncand += 1;
-      nin += (col_in && iz0 + zz < g.nz && q > thr) ? 1 : 0;
+      nin += (st.col_in && zz < st.zrem && q > thr) ? 1 : 0;
     }
   }
   nin = wave_sum_u64(nin);
@@ -418,6 +512,28 @@ __global__ __launch_bounds__(kRedThreads) void k_loss_final(const double* __rest
   if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+
+// Per-volume loss: one workgroup per volume sums its bricks' losses in double
+// (fixed order, so deterministic).
+__global__ __launch_bounds__(kRedThreads) void k_item_loss(const float* __restrict__ x,
+                                                           const ItemDesc* __restrict__ items,
+                                                           int nitems, int64_t nbricks,
+                                                           double* __restrict__ out) {
+  __shared__ double sh[kRedThreads];
+  const int i = blockIdx.x;
+  const int64_t a = items[i].brick0;
+  const int64_t e = (i + 1 < nitems) ? (int64_t)items[i + 1].brick0 : nbricks;
+  double s = 0.0;
+  for (int64_t j = a + threadIdx.x; j < e; j += kRedThreads) s += (double)x[j];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = sh[0];
+}
+
 }  // namespace
 
 #define GVE_BRICK_SHAPES(X) X(8, 8) X(8, 16) X(8, 32) X(16, 16)
@@ -429,14 +545,33 @@ bool brick_shape_supported(int bxy, int bz) {
   return false;
 }
 
+int fused_resident_groups(int bxy, int bz, int device) {
+  int per_cu = 0, cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return 0;
+#define GVE_CASE(XY, Z)                                                                       \
+  if (bxy == XY && bz == Z) {                                                                 \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused_queue<XY, Z, false>,    \
+                                                     XY * XY, 0) != hipSuccess)               \
+      return 0;                                                                               \
+    return per_cu * cus;                                                                      \
+  }
+  GVE_BRICK_SHAPES(GVE_CASE)
+#undef GVE_CASE
+  return 0;
+}
+
 hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
-                          gve_grid g, BrickGeom bg, float k, float* out, hipStream_t s) {
+                          const ItemDesc* items, int nitems, BrickGeom bg, float k, float* out,
+                          const Schedule& sc, hipStream_t s) {
   const float thr = -kHalfLog2e * k * k;
+  if (bg.nbricks <= 0) return hipSuccess;
   const dim3 grid((unsigned)bg.nbricks);
+  const int xcd = sc.kind == kSchedXcd ? 1 : 0;
 #define GVE_CASE(XY, Z)                                                                       \
   if (bg.Bxy == XY && bg.Bz == Z) {                                                           \
     hipLaunchKernelGGL((k_forward<XY, Z>), grid, dim3(XY * XY), 0, s, rec, pair_gid,            \
-                       brick_start, g, bg, thr, out);                                           \
+                       brick_start, items, nitems, (uint32_t)bg.nbricks, xcd, thr, out);        \
     return hipGetLastError();                                                                 \
   }
   GVE_BRICK_SHAPES(GVE_CASE)
@@ -445,19 +580,38 @@ hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid, const uin
 }
 
 hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
-                        gve_grid g, BrickGeom bg, float k, const float* field, float* acc,
-                        int64_t n, float* part, const uint32_t* offset, float* brick_loss,
+                        const ItemDesc* items, int nitems, BrickGeom bg, float k,
+                        const float* field, float* acc, int64_t n, float* part,
+                        const uint32_t* offset, float* brick_loss, const Schedule& sc,
                         hipStream_t s, bool vjp) {
   const float thr = -kHalfLog2e * k * k;
-  const dim3 grid((unsigned)bg.nbricks);
+  if (bg.nbricks <= 0) return hipSuccess;
+  const bool queue = sc.kind == kSchedQueue;
+  if (queue && (!sc.order || !sc.counter || sc.persistent_groups <= 0)) return hipErrorInvalidValue;
+  const dim3 grid(queue ? (unsigned)std::min<int64_t>(sc.persistent_groups, bg.nbricks)
+                        : (unsigned)bg.nbricks);
+  const int xcd = sc.kind == kSchedXcd ? 1 : 0;
+  const uint32_t* order = sc.order;
+  uint32_t* counter = sc.counter;
+  const uint32_t nb = (uint32_t)bg.nbricks;
 #define GVE_CASE(XY, Z)                                                                       \
   if (bg.Bxy == XY && bg.Bz == Z) {                                                           \
-    if (vjp)                                                                                  \
+    if (queue && vjp)                                                                         \
+      hipLaunchKernelGGL((k_fused_queue<XY, Z, true>), grid, dim3(XY * XY), 0, s, rec,          \
+                         pair_gid, brick_start, items, nitems, nb, order, counter, thr, field,  \
+                         acc, n, part, offset, brick_loss);                                     \
+    else if (queue)                                                                           \
+      hipLaunchKernelGGL((k_fused_queue<XY, Z, false>), grid, dim3(XY * XY), 0, s, rec,         \
+                         pair_gid, brick_start, items, nitems, nb, order, counter, thr, field,  \
+                         acc, n, part, offset, brick_loss);                                     \
+    else if (vjp)                                                                             \
       hipLaunchKernelGGL((k_fused<XY, Z, true>), grid, dim3(XY * XY), 0, s, rec, pair_gid,      \
-                         brick_start, g, bg, thr, field, acc, n, part, offset, brick_loss);     \
+                         brick_start, items, nitems, nb, xcd, thr, field, acc, n, part, offset, \
+                         brick_loss);                                                           \
     else                                                                                      \
       hipLaunchKernelGGL((k_fused<XY, Z, false>), grid, dim3(XY * XY), 0, s, rec, pair_gid,     \
-                         brick_start, g, bg, thr, field, acc, n, part, offset, brick_loss);     \
+                         brick_start, items, nitems, nb, xcd, thr, field, acc, n, part, offset, \
+                         brick_loss);                                                           \
     return hipGetLastError();                                                                 \
   }
   GVE_BRICK_SHAPES(GVE_CASE)
@@ -466,14 +620,15 @@ hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid, const uint3
 }
 
 hipError_t launch_count(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
-                        gve_grid g, BrickGeom bg, float k, unsigned long long* counts,
-                        hipStream_t s) {
+                        const ItemDesc* items, int nitems, BrickGeom bg, float k,
+                        unsigned long long* counts, hipStream_t s) {
   const float thr = -kHalfLog2e * k * k;
+  if (bg.nbricks <= 0) return hipSuccess;
   const dim3 grid((unsigned)bg.nbricks);
 #define GVE_CASE(XY, Z)                                                                       \
   if (bg.Bxy == XY && bg.Bz == Z) {                                                           \
     hipLaunchKernelGGL((k_count<XY, Z>), grid, dim3(XY * XY), 0, s, rec, pair_gid, brick_start, \
-                       g, bg, thr, counts);                                                     \
+                       items, nitems, thr, counts);                                             \
     return hipGetLastError();                                                                 \
   }
   GVE_BRICK_SHAPES(GVE_CASE)
@@ -490,6 +645,14 @@ hipError_t launch_loss_reduce(const float* brick_loss, int64_t nbricks, double* 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kRedThreads), 0, s, part, kRedBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_item_loss(const float* brick_loss, const ItemDesc* items, int nitems,
+                            int64_t nbricks, double* out, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_item_loss, dim3((unsigned)nitems), dim3(kRedThreads), 0, s, brick_loss,
+                     items, nitems, nbricks, out);
   return hipGetLastError();
 }
 

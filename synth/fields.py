@@ -204,3 +204,92 @@ def spectrum_slope(field, kmin=2.0, kmax=None):
 def count_to_budget(shape, n):
     """Mean primitive spacing in voxels for a budget n on a grid of ``shape``."""
     return (float(np.prod(shape)) / n) ** (1.0 / 3.0)
+
+
+def mixture_field_torch(params, shape, device="cpu", noise=0.0, seed=0, reach=6.0, chunk=128):
+    """``mixture_field`` for large grids, in torch (float32 result).
+
+    Each Gaussian is summed over the cube of half-width ceil(reach * max scale)
+    voxels around its centre; beyond ``reach`` standard deviations along the
+    longest axis a term is below exp(-reach^2 / 2) (1.5e-8 |c| at 6), so the
+    sum equals the untruncated one to that level.  White noise of standard
+    deviation ``noise`` is drawn from a torch generator seeded with ``seed``.
+    """
+    import torch
+
+    nz, ny, nx = shape
+    p = torch.as_tensor(np.asarray(params, dtype=np.float64), device=device)
+    n = p.shape[1]
+    q = p[3:7] / torch.linalg.norm(p[3:7], dim=0, keepdim=True)
+    w, x, y, z = q
+    R = torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)]),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)]),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]),
+    ]).permute(2, 0, 1)                                      # [n, 3, 3]
+    inv_s = torch.exp(-p[7:10]).T                           # [n, 3]
+    h = int(np.ceil(reach * float(torch.exp(p[7:10]).max())))
+    o = torch.arange(-h, h + 1, device=device, dtype=torch.float64)
+    oz, oy, ox = torch.meshgrid(o, o, o, indexing="ij")
+    offs = torch.stack([ox.ravel(), oy.ravel(), oz.ravel()], dim=1)      # [C, 3]
+    out = torch.zeros(nz * ny * nx, device=device, dtype=torch.float64)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        mu = p[0:3, a:b].T                                   # [m, 3]
+        base = torch.floor(mu)
+        pts = base[:, None, :] + offs[None]                  # [m, C, 3]
+        d = pts - mu[:, None, :]
+        zloc = torch.einsum("mcj,mjk->mck", d, R[a:b]) * inv_s[a:b, None, :]
+        val = p[10, a:b, None] * torch.exp(-0.5 * (zloc * zloc).sum(-1))
+        ix, iy, iz = pts[..., 0].long(), pts[..., 1].long(), pts[..., 2].long()
+        ok = (ix >= 0) & (ix < nx) & (iy >= 0) & (iy < ny) & (iz >= 0) & (iz < nz)
+        idx = (ix + nx * (iy + ny * iz))[ok]
+        out.index_add_(0, idx, val[ok])
+    if noise > 0:
+        gen = torch.Generator(device=device).manual_seed(int(seed))
+        out += noise * torch.randn(out.shape, generator=gen, device=device, dtype=torch.float64)
+    return out.reshape(nz, ny, nx).to(torch.float32)
+
+
+# Allowed edge lengths and the voxel cap of the batched workload.
+BATCH_DIMS = tuple(range(96, 385, 32))
+BATCH_MAX_VOXELS = 512 * 256 * 128
+
+
+def batch_shapes(count, seed):
+    """``count`` grid shapes (nz, ny, nx), each edge drawn from BATCH_DIMS and
+    redrawn until the volume holds at most BATCH_MAX_VOXELS voxels."""
+    rng = np.random.default_rng(seed)
+    shapes = []
+    while len(shapes) < count:
+        d = rng.choice(BATCH_DIMS, size=3)
+        if int(np.prod(d)) <= BATCH_MAX_VOXELS:
+            shapes.append(tuple(int(v) for v in d))
+    return shapes
+
+
+def batch_item_field(shape, seed, device="cpu"):
+    """Volume ``seed`` of the batched workload, normalised to [0, 1]: even seeds
+    are signed Gaussian mixtures (200 per 64^3 of volume, scales 1-4 voxels,
+    weights U[-1, 1], noise 0.01), odd seeds k^-5/3 spectral fields."""
+    nz, ny, nx = shape
+    if seed % 2 == 0:
+        count = max(1, int(round(200 * nz * ny * nx / 64 ** 3)))
+        params = random_params(count, (nx, ny, nz), seed)
+        f = mixture_field_torch(params, shape, device=device, noise=0.01, seed=seed)
+        return minmax01(f).contiguous()
+    return spectral_field(shape, seed, device=device)
+
+
+def gradient_energy(field):
+    """sum |grad V|^2 with central differences (one-sided at the faces)."""
+    import torch
+
+    gz, gy, gx = torch.gradient(field.to(torch.float64))
+    return float((gx * gx + gy * gy + gz * gz).sum())
+
+
+def batch_budgets(energies, lo=8000, hi=200000):
+    """Budgets proportional to the gradient energy: hi * E / max E, within [lo, hi]."""
+    e = np.asarray(energies, dtype=np.float64)
+    return [int(v) for v in np.clip(np.round(hi * e / e.max()), lo, hi)]
