@@ -69,7 +69,7 @@ __device__ inline uint32_t prep_one(const float* __restrict__ theta, int64_t n, 
   Record r;
   r.mu[0] = mx; r.mu[1] = my; r.mu[2] = mz;
   r.c = c;
-  r.azz = -kHalfLog2e * pzz;
+  r.sz = sqrtf(kHalfLog2e * pzz);
   r.s[0] = -kHalfLog2e * syy * idet;
   r.s[1] = kHalfLog2e * sxy * idet;
   r.s[2] = -kHalfLog2e * sxx * idet;

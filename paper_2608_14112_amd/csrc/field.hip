@@ -6,12 +6,12 @@
 // primitive index) are read one at a time with wave-uniform scalar loads.
 //
 // Along a column (fixed dx, dy) the exponent is a parabola in dz (see Record):
-//     Q = qxy + azz t^2,  t = dz - (gx dx + gy dy),
+//     Q = qxy - w^2,  w = sz t,  t = dz - (gx dx + gy dy),
 // with exp(-m^2/2) = exp2(Q), and the cut m^2 < k^2 (Sec. III-C) is
-// Q > -(log2 e / 2) k^2.  t advances by exactly 1 per voxel and Q is formed
-// afresh from it (two operations), so rounding does not accumulate along the
-// column.  The loop runs over the primitive's bounding-box z-range inside the
-// brick only.
+// Q > -(log2 e / 2) k^2.  w advances by sz per voxel and is formed afresh at
+// every voxel as w0 + zz sz (one fused multiply-add), then Q = qxy - w w (a
+// second one), so rounding does not accumulate along the column.  The loop
+// runs over the primitive's bounding-box z-range inside the brick only.
 //
 //   k_forward : Vhat on the brick (Sec. III-C eq:field, truncated).
 //   k_fused   : Vhat, residual r = 2 (Vhat - V), the brick's share of
@@ -22,8 +22,9 @@
 //               then either added to the primitive's accumulators with float
 //               atomics, or (deterministic mode) stored to the pair's own slot
 //               of a partials array that the update kernel sums per primitive
-//               in a fixed order.  Per column only sum e, sum e t, sum e t^2 are needed
-//               because dx, dy and dz - t are constant along it.
+//               in a fixed order.  Per column only sum e, sum e w, sum e w^2 are
+//               needed because dx, dy and dz - t are constant along it (and
+//               t = w / sz).
 #include <algorithm>
 
 #include "common.h"
@@ -81,10 +82,14 @@ __device__ inline void wave_reduce10(const float (&v)[10], float (&out)[3]) {
   out[2] = row_sum16(fold16(w4, w4));
 }
 
-// Which of the ten sums row r of out[k] holds (-1: duplicate).
+// Which of the ten sums row r of out[k] holds (-1: duplicate): out[0] rows
+// (0, 1, 5, 6), out[1] rows (2, 3, 7, 8), out[2] rows (4, -, 9, -).  Plain
+// arithmetic, so nothing is read from memory.
 __device__ inline int reduce10_slot(int k, int row) {
-  const int m0[4] = {0, 1, 5, 6}, m1[4] = {2, 3, 7, 8}, m2[4] = {4, -1, 9, -1};
-  return k == 0 ? m0[row] : (k == 1 ? m1[row] : m2[row]);
+  const int base = row < 2 ? row : row + 3;
+  if (k == 0) return base;
+  if (k == 1) return base + 2;
+  return (row & 1) ? -1 : 4 + 5 * (row >> 1);
 }
 
 // ---- per (primitive, column) setup -------------------------------------------
@@ -94,7 +99,7 @@ __device__ inline int reduce10_slot(int k, int row) {
 // terms are <= 0, so the sum never cancels (an expansion in powers of zz about
 // the brick's first voxel would, when the vertex is far from it).
 struct ColumnSetup {
-  float qxy, t0;
+  float qxy, t0, w0;  // vertex height, t and w = sz t at the brick's first z
   int za, zb;
   uint32_t zmask;  // bit zz set when brick offset zz lies in the z-range of the box
 };
@@ -111,12 +116,24 @@ __device__ inline ColumnSetup column_setup(const Record& r, float px, float py, 
   s.qxy = (r.s[0] * dx + 2.0f * r.s[1] * dy) * dx + r.s[2] * dy * dy;
   const float ofs = r.gx * dx + r.gy * dy;
   s.t0 = (pz0 - r.mu[2]) - ofs;
+  s.w0 = r.sz * s.t0;
   return s;
 }
 
-__device__ inline float quad_at(const ColumnSetup& s, float azz, float t) {
-  return fmaf(azz * t, t, s.qxy);
+// w and Q at brick offset zz.  sz is passed in a vector register so that the
+// per-step constant zz can take the instruction's one scalar operand slot
+// (no literal operands in three-operand instructions on this target).
+__device__ inline float vreg(float x) {
+  float v;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+  return v;
 }
+
+__device__ inline float w_at(const ColumnSetup& s, float szv, int zz) {
+  return fmaf((float)zz, szv, s.w0);
+}
+
+__device__ inline float quad_w(const ColumnSetup& s, float w) { return fmaf(-w, w, s.qxy); }
 
 __device__ inline Record load_record(const Record* __restrict__ rec, uint32_t gid) {
   return rec[gid];
@@ -137,11 +154,12 @@ __device__ inline void accumulate_brick(const Record* __restrict__ rec,
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
     const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
+    const float szv = vreg(r.sz);
     if (!column_hit(s, col_in, thr)) continue;
 #pragma unroll
     for (int zz = 0; zz < BZ; ++zz) {
       if ((s.zmask >> zz) & 1u) {
-        const float q = quad_at(s, r.azz, s.t0 + (float)zz);
+        const float q = quad_w(s, w_at(s, szv, zz));
         if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
           const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
           acc[zz] = fmaf(r.c, G, acc[zz]);
@@ -240,10 +258,13 @@ __global__ __launch_bounds__(BXY* BXY) void k_forward(const Record* __restrict__
 template <int BXY, int BZ>
 __device__ inline uint32_t pair_slot(const Record& r, const uint32_t* __restrict__ offset,
                                      uint32_t gid, int bx, int by, int bz) {
-  const int rbx = bx - r.lo[0] / BXY, rby = by - r.lo[1] / BXY, rbz = bz - r.lo[2] / BZ;
-  const int nbx_g = r.hi[0] / BXY - r.lo[0] / BXY + 1;
-  const int nby_g = r.hi[1] / BXY - r.lo[1] / BXY + 1;
-  return offset[gid] + (uint32_t)((rbz * nby_g + rby) * nbx_g + rbx);
+  // box bounds are clamped to the volume, so non-negative: unsigned division
+  const uint32_t lx = (uint32_t)r.lo[0] / BXY, ly = (uint32_t)r.lo[1] / BXY,
+                 lz = (uint32_t)r.lo[2] / BZ;
+  const uint32_t nbx_g = (uint32_t)r.hi[0] / BXY - lx + 1;
+  const uint32_t nby_g = (uint32_t)r.hi[1] / BXY - ly + 1;
+  return offset[gid] + (((uint32_t)bz - lz) * nby_g + ((uint32_t)by - ly)) * nbx_g +
+         ((uint32_t)bx - lx);
 }
 
 // One brick of the fused pass.  VJP = false: residual r = 2 (Vhat - V) from
@@ -316,25 +337,30 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
     }
     float v[10];
     {
-      float se = 0.0f, sT = 0.0f, sTT = 0.0f;
+      float se = 0.0f, sW = 0.0f, sWW = 0.0f;
       if (hit) {
+        const float szv = vreg(r.sz);
 #pragma unroll
         for (int zz = 0; zz < BZ; ++zz) {
           if ((s.zmask >> zz) & 1u) {
-            const float t = s.t0 + (float)zz;
-            const float q = quad_at(s, r.azz, t);
+            const float w = w_at(s, szv, zz);
+            const float q = quad_w(s, w);
             if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
               const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
               const float e = res[zz] * G;
               se += e;
-              const float et = e * t;
-              sT += et;
-              sTT = fmaf(et, t, sTT);
+              const float ew = e * w;
+              sW += ew;
+              sWW = fmaf(ew, w, sWW);
             }
           }
         }
       }
-      // back to d = p - mu: sum e dz = sT + ofs se, sum e dz^2 = sTT + 2 ofs sT + ofs^2 se
+      // sum e t = sW / sz, sum e t^2 = sWW / sz^2; back to d = p - mu:
+      // sum e dz = sT + ofs se, sum e dz^2 = sTT + 2 ofs sT + ofs^2 se
+      const float isz = __builtin_amdgcn_rcpf(r.sz);  // 1 ulp; gradients need 1e-3
+      const float sT = sW * isz;
+      const float sTT = sWW * isz * isz;
       const float dx = px - r.mu[0];
       const float dy = py - r.mu[1];
       const float ofs = (pz0 - r.mu[2]) - s.t0;
@@ -463,7 +489,7 @@ __global__ __launch_bounds__(BXY* BXY) void k_count(const Record* __restrict__ r
     const ColumnSetup s = column_setup<BZ>(r, st.px, st.py, st.pz0, st.iz0);
     if (!column_hit(s, st.col_in, thr)) continue;
     for (int zz = s.za; zz <= s.zb; ++zz) {
-      const float q = quad_at(s, r.azz, s.t0 + (float)zz);
+      const float q = quad_w(s, w_at(s, r.sz, zz));
       if (__builtin_amdgcn_ballot_w64(q > thr) == 0ull) continue;
       ncand += 1;
       nin += (st.col_in && zz < st.zrem && q > thr) ? 1 : 0;
