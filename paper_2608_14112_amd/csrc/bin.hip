@@ -71,7 +71,7 @@ __device__ inline uint32_t prep_one(const float* __restrict__ theta, int64_t n, 
   r.c = c;
   r.sz = sqrtf(kHalfLog2e * pzz);
   r.s[0] = -kHalfLog2e * syy * idet;
-  r.s[1] = kHalfLog2e * sxy * idet;
+  r.s[1] = 2.0f * kHalfLog2e * sxy * idet;
   r.s[2] = -kHalfLog2e * sxx * idet;
   r.gx = -pxz / pzz;
   r.gy = -pyz / pzz;

@@ -21,7 +21,7 @@ namespace gve {
 // dz = gx dx + gy dy and height qxy(dx, dy) = d_xy^T S d_xy, S the Schur
 // complement -(log2 e / 2) (Sigma_xy)^{-1}:
 //     d^T A d = qxy - (sz (dz - gx dx - gy dy))^2,  sz = sqrt(-A_zz).
-//   mu[3], c, sz, s[3] = (S_xx, S_xy, S_yy), gx, gy,
+//   mu[3], c, sz, s[3] = (S_xx, 2 S_xy, S_yy), gx, gy,
 //   lo[3], hi[3] : inclusive voxel-index bounding box of the k-sigma support.
 struct alignas(64) Record {
   float mu[3];

@@ -94,12 +94,13 @@ __device__ inline int reduce10_slot(int k, int row) {
 
 // ---- per (primitive, column) setup -------------------------------------------
 //
-// With t0 = (z0 - mu_z) - (gx dx + gy dy) the column coordinate at the brick's
-// first z, Q at brick offset zz is qxy + (a_zz t) t with t = t0 + zz.  Both
-// terms are <= 0, so the sum never cancels (an expansion in powers of zz about
-// the brick's first voxel would, when the vertex is far from it).
+// With t0 = (z0 - mu_z) - (gx dx + gy dy) the column coordinate at the
+// brick's first z and w0 = sz t0, Q at brick offset zz is qxy - w w with
+// w = w0 + zz sz.  Both terms are <= 0, so the sum never cancels (an
+// expansion in powers of zz about the brick's first voxel would, when the
+// vertex is far from it).
 struct ColumnSetup {
-  float qxy, t0, w0;  // vertex height, t and w = sz t at the brick's first z
+  float qxy, t0, w0;  // vertex height, t and w at the brick's first z
   int za, zb;
   uint32_t zmask;  // bit zz set when brick offset zz lies in the z-range of the box
 };
@@ -113,9 +114,8 @@ __device__ inline ColumnSetup column_setup(const Record& r, float px, float py, 
   s.zmask = (s.zb >= s.za) ? (((2u << s.zb) - 1u) & ~((1u << s.za) - 1u)) : 0u;
   const float dx = px - r.mu[0];
   const float dy = py - r.mu[1];
-  s.qxy = (r.s[0] * dx + 2.0f * r.s[1] * dy) * dx + r.s[2] * dy * dy;
-  const float ofs = r.gx * dx + r.gy * dy;
-  s.t0 = (pz0 - r.mu[2]) - ofs;
+  s.qxy = fmaf(r.s[0], dx, r.s[1] * dy) * dx + r.s[2] * dy * dy;
+  s.t0 = (pz0 - r.mu[2]) - fmaf(r.gx, dx, r.gy * dy);
   s.w0 = r.sz * s.t0;
   return s;
 }
@@ -141,21 +141,22 @@ __device__ inline Record load_record(const Record* __restrict__ rec, uint32_t gi
 
 // True if any lane's column meets the support (the vertex of the parabola is
 // the column's largest Q); otherwise the whole (primitive, brick) is skipped.
-__device__ inline bool column_hit(const ColumnSetup& s, bool col_in, float thr) {
-  return __builtin_amdgcn_ballot_w64(col_in && s.qxy > thr) != 0ull;
+// cols = ballot of the lanes whose column lies inside the volume.
+__device__ inline bool column_hit(const ColumnSetup& s, uint64_t cols, float thr) {
+  return (__builtin_amdgcn_ballot_w64(s.qxy > thr) & cols) != 0ull;
 }
 
 template <int BZ>
 __device__ inline void accumulate_brick(const Record* __restrict__ rec,
                                         const uint32_t* __restrict__ pair_gid, uint32_t j0,
                                         uint32_t j1, float px, float py, float pz0, int iz0,
-                                        bool col_in, float thr, float (&acc)[BZ]) {
+                                        uint64_t cols, float thr, float (&acc)[BZ]) {
   for (uint32_t j = j0; j < j1; ++j) {
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
     const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
     const float szv = vreg(r.sz);
-    if (!column_hit(s, col_in, thr)) continue;
+    if (!column_hit(s, cols, thr)) continue;
 #pragma unroll
     for (int zz = 0; zz < BZ; ++zz) {
       if ((s.zmask >> zz) & 1u) {
@@ -234,7 +235,7 @@ __device__ __attribute__((always_inline)) inline void forward_brick(const Record
 #pragma unroll
   for (int zz = 0; zz < BZ; ++zz) acc[zz] = 0.0f;
   accumulate_brick<BZ>(rec, pair_gid, brick_start[b], brick_start[b + 1], st.px, st.py, st.pz0,
-                       st.iz0, st.col_in, thr, acc);
+                       st.iz0, __builtin_amdgcn_ballot_w64(st.col_in), thr, acc);
   if (st.col_in) {
 #pragma unroll
     for (int zz = 0; zz < BZ; ++zz)
@@ -290,6 +291,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
   const float px = st.px, py = st.py, pz0 = st.pz0;
   const int iz0 = st.iz0;
   const bool col_in = st.col_in;
+  const uint64_t cols = __builtin_amdgcn_ballot_w64(col_in);
   const uint32_t j0 = brick_start[b], j1 = brick_start[b + 1];
 
   float res[BZ];
@@ -300,7 +302,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
     for (int zz = 0; zz < BZ; ++zz)
       if (col_in && zz < st.zrem) res[zz] = field[st.base + st.plane * (size_t)(iz0 + zz)];
   } else {
-    accumulate_brick<BZ>(rec, pair_gid, j0, j1, px, py, pz0, iz0, col_in, thr, res);
+    accumulate_brick<BZ>(rec, pair_gid, j0, j1, px, py, pz0, iz0, cols, thr, res);
     // residual and this brick's share of the loss
     float lsum = 0.0f;
 #pragma unroll
@@ -328,7 +330,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
     const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
-    const bool hit = column_hit(s, col_in, thr);
+    const bool hit = column_hit(s, cols, thr);
     if (kWaves == 1 && !hit) {
       // a pair whose support misses every column still owns a partials slot
       if (part && lane < 10)
@@ -483,11 +485,12 @@ __global__ __launch_bounds__(BXY* BXY) void k_count(const Record* __restrict__ r
                                                 unsigned long long* __restrict__ counts) {
   const uint32_t b = blockIdx.x;
   const Site st = site_of<BXY, BZ>(items, nitems, b);
+  const uint64_t cols = __builtin_amdgcn_ballot_w64(st.col_in);
   unsigned long long nin = 0, ncand = 0;
   for (uint32_t j = brick_start[b]; j < brick_start[b + 1]; ++j) {
     const Record r = load_record(rec, __builtin_amdgcn_readfirstlane(pair_gid[j]));
     const ColumnSetup s = column_setup<BZ>(r, st.px, st.py, st.pz0, st.iz0);
-    if (!column_hit(s, st.col_in, thr)) continue;
+    if (!column_hit(s, cols, thr)) continue;
     for (int zz = s.za; zz <= s.zb; ++zz) {
       const float q = quad_w(s, w_at(s, r.sz, zz));
       if (__builtin_amdgcn_ballot_w64(q > thr) == 0ull) continue;
