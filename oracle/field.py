@@ -309,6 +309,76 @@ def loss_grad(params, field, grid: Grid, k, return_parts=False):
     return L, grad
 
 
+def _pair_jacobian(c, G, d, P, R, ell, qn, qnorm, qok):
+    """d(c G(p))/dtheta for one primitive and one in-support voxel (11 values).
+
+    The single-voxel case of the sums in ``loss_grad`` with r = 1: e = G,
+    g = c G, D = g d d^T.
+    """
+    out = np.zeros(NPARAM)
+    g = c * G
+    out[0:3] = P @ (g * d)
+    D = g * np.outer(d, d)
+    si2 = np.exp(-2.0 * ell)
+    out[7:10] = si2 * np.diag(R.T @ D @ R)
+    if qok:
+        dR = -D @ R @ np.diag(si2)
+        dRq = rotation_partials(qn)
+        dqn = np.array([np.sum(dR * dRq[a]) for a in range(4)])
+        out[3:7] = (np.eye(4) - np.outer(qn, qn)) @ dqn / qnorm
+    out[10] = G
+    return out
+
+
+def boundary_slack(params, field, grid: Grid, k, band):
+    """How far dL/dtheta can move when pairs near the cut change sides.
+
+    A pair whose float64 m^2 lies within ``band`` of k^2 may be decided either
+    way by a float32 evaluator.  Flipping pair (i, p) (first order):
+      * adds or drops the direct term r(p) d(c_i G_i(p))/dtheta_i;
+      * moves Vhat(p) by c_i G_i(p), so r(p) by 2 c_i G_i(p), which changes
+        dL/dtheta_j by 2 c_i G_i(p) d(c_j G_j(p))/dtheta_j for every j whose
+        support holds p (i included).
+    Returns the (11, N) sum of the magnitudes of both over every such pair (a
+    bound for any set of flips) and the number of pairs.
+    """
+    mu, q, ell, c = split(params)
+    qn, qnorm, qok = normalize_quat(q)
+    R = rotation(qn)
+    P = precision(params)
+    S = covariance(params)
+    k2 = float(k) * float(k)
+    fld = np.asarray(field, dtype=np.float64).reshape(grid.shape)
+    V, _ = evaluate_windowed(params, grid, k)
+    r = 2.0 * (V - fld)
+    N = mu.shape[0]
+    slack = np.zeros((NPARAM, N))
+    amb = []
+    for i in range(N):
+        box = support_box(mu[i], S[i], math.sqrt(k2 + band), grid)  # pairs just outside too
+        if box is None:
+            continue
+        dx, dy, dz = _box_offsets(box, mu[i], grid)
+        m2 = _quad(P[i], dx, dy, dz)
+        hit = np.abs(m2 - k2) < band
+        for kk, jj, ii in zip(*np.nonzero(hit)):
+            amb.append((i, box[0][0] + ii, box[1][0] + jj, box[2][0] + kk))
+    for i, ix, iy, iz in amb:
+        p = np.array([grid.x0 + ix, grid.y0 + iy, grid.z0 + iz], dtype=np.float64)
+        d = p - mu[i]
+        Gi = math.exp(-0.5 * float(d @ P[i] @ d))
+        Ji = _pair_jacobian(c[i], Gi, d, P[i], R[i], ell[i], qn[i], qnorm[i], qok[i])
+        slack[:, i] += abs(r[iz, iy, ix]) * np.abs(Ji)
+        shift = 2.0 * abs(c[i]) * Gi
+        D = p[None, :] - mu
+        m2all = np.einsum("nj,njk,nk->n", D, P, D)
+        for j in np.nonzero(m2all < k2 + band)[0]:
+            Gj = math.exp(-0.5 * float(m2all[j]))
+            Jj = _pair_jacobian(c[j], Gj, D[j], P[j], R[j], ell[j], qn[j], qnorm[j], qok[j])
+            slack[:, j] += shift * np.abs(Jj)
+    return slack, len(amb)
+
+
 # ----------------------------------------------------------------------------
 # Adam and refinement
 # ----------------------------------------------------------------------------

@@ -297,3 +297,24 @@ def test_psnr_definition_and_sampled_estimate():
     # sampling std of the PSNR estimate for Gaussian residuals: 4.34 sqrt(2/n) dB
     sd_db = 10 / math.log(10) * math.sqrt(2.0 / 500_000)
     assert abs(F.psnr_from_mse(samp) - F.psnr_from_mse(full)) < 3 * sd_db
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_boundary_slack_bounds_the_effect_of_flipping_pairs(sign):
+    """Moving the cut from k^2 to k^2 +- 0.9 band flips exactly the pairs the
+    slack accounts for (those within band of the cut, on one side); the
+    gradient change must stay within the slack."""
+    grid = F.Grid(18, 16, 15)
+    params = S.random_params(25, (18, 16, 15), seed=5, scale_range=(0.8, 3.0), unit_quat=False)
+    field = np.random.default_rng(6).uniform(-1, 1, size=grid.shape)
+    k, band = 3.0, 0.05
+    slack, namb = F.boundary_slack(params, field, grid, k, band)
+    assert namb > 10
+    k2 = math.sqrt(k * k + sign * 0.9 * band)
+    _, g0 = F.loss_grad(params, field, grid, k)
+    _, g1 = F.loss_grad(params, field, grid, k2)
+    diff = np.abs(g1 - g0)
+    assert np.max(diff) > 0
+    assert np.all(diff <= 1.01 * slack + 1e-12)
+    # and the slack is not vacuous: same order as the change it bounds
+    assert np.sum(slack) < 50 * np.sum(diff)
