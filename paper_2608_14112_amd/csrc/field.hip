@@ -95,12 +95,14 @@ __device__ inline int reduce10_slot(int k, int row) {
 // ---- per (primitive, column) setup -------------------------------------------
 //
 // With t0 = (z0 - mu_z) - (gx dx + gy dy) the column coordinate at the
-// brick's first z and w0 = sz t0, Q at brick offset zz is qxy - w w with
-// w = w0 + zz sz.  Both terms are <= 0, so the sum never cancels (an
+// brick's first z and wm = sz (t0 + BZ / 2) the scaled coordinate at its
+// middle, Q at brick offset zz is qxy - w w with w = wm + (zz - BZ / 2) sz.
+// Anchoring at the middle halves the largest |wm|, whose rounding sets the
+// error of w.  Both terms of Q are <= 0, so the sum never cancels (an
 // expansion in powers of zz about the brick's first voxel would, when the
 // vertex is far from it).
 struct ColumnSetup {
-  float qxy, t0, w0;  // vertex height, t and w at the brick's first z
+  float qxy, t0, wm;  // vertex height, t at the brick's first z, w at its middle
   int za, zb;
   uint32_t zmask;  // bit zz set when brick offset zz lies in the z-range of the box
 };
@@ -116,7 +118,7 @@ __device__ inline ColumnSetup column_setup(const Record& r, float px, float py, 
   const float dy = py - r.mu[1];
   s.qxy = fmaf(r.s[0], dx, r.s[1] * dy) * dx + r.s[2] * dy * dy;
   s.t0 = (pz0 - r.mu[2]) - fmaf(r.gx, dx, r.gy * dy);
-  s.w0 = r.sz * s.t0;
+  s.wm = r.sz * (s.t0 + (float)(BZ / 2));
   return s;
 }
 
@@ -129,8 +131,9 @@ __device__ inline float vreg(float x) {
   return v;
 }
 
+template <int BZ>
 __device__ inline float w_at(const ColumnSetup& s, float szv, int zz) {
-  return fmaf((float)zz, szv, s.w0);
+  return fmaf((float)(zz - BZ / 2), szv, s.wm);
 }
 
 __device__ inline float quad_w(const ColumnSetup& s, float w) { return fmaf(-w, w, s.qxy); }
@@ -160,7 +163,7 @@ __device__ inline void accumulate_brick(const Record* __restrict__ rec,
 #pragma unroll
     for (int zz = 0; zz < BZ; ++zz) {
       if ((s.zmask >> zz) & 1u) {
-        const float q = quad_w(s, w_at(s, szv, zz));
+        const float q = quad_w(s, w_at<BZ>(s, szv, zz));
         if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
           const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
           acc[zz] = fmaf(r.c, G, acc[zz]);
@@ -345,7 +348,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
 #pragma unroll
         for (int zz = 0; zz < BZ; ++zz) {
           if ((s.zmask >> zz) & 1u) {
-            const float w = w_at(s, szv, zz);
+            const float w = w_at<BZ>(s, szv, zz);
             const float q = quad_w(s, w);
             if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
               const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
@@ -492,7 +495,7 @@ __global__ __launch_bounds__(BXY* BXY) void k_count(const Record* __restrict__ r
     const ColumnSetup s = column_setup<BZ>(r, st.px, st.py, st.pz0, st.iz0);
     if (!column_hit(s, cols, thr)) continue;
     for (int zz = s.za; zz <= s.zb; ++zz) {
-      const float q = quad_w(s, w_at(s, r.sz, zz));
+      const float q = quad_w(s, w_at<BZ>(s, r.sz, zz));
       if (__builtin_amdgcn_ballot_w64(q > thr) == 0ull) continue;
       ncand += 1;
       nin += (st.col_in && zz < st.zrem && q > thr) ? 1 : 0;
