@@ -339,6 +339,71 @@ gve_status gve_autotune(gve_ctx* ctx, const gve_params* p, const float* d_field,
                         int32_t table_len, int32_t* n_written);
 
 /*
+ * The paper's own training loop (Sec. III-C eq:field, Sec. III-F, Table
+ * tab:training-config), beside the sum-of-Gaussians path above.  Primitives
+ * carry 12 float32 rows [12][n]: mu (3), raw quaternion w x y z (4),
+ * log-scales (3), scalar attribute a, weight logit b (w = sigmoid(b)); the
+ * field is Vt(p) = sum w a G / max(sum w G, rho0) with G cut at m^2 >= k^2.
+ * Each iteration draws `samples` stratified points (frac_hi from voxels with
+ * V > v_hi, frac_mid from v_occ < V <= v_hi, the rest uniform; a class
+ * without voxels gives its share to the uniform class), jitters them by
+ * U[-1/2, 1/2]^3, gives each a partner jittered by another U[-1/2, 1/2]^3,
+ * and minimises
+ *   sum_{V>v_occ} (Vt - V)^2 + lam_rho sum_{V>v_occ} (rho - 1)^2
+ *   + lam_sm sum (rho(p) - rho(p'))^2 + lam_anc sum_i (a_i - V(mu_i))^2
+ *   + lam_aniso sum_i relu(max ell - min ell - ln aniso_max)^2
+ *   + lam_cap sum_ij relu(ell - ell_hi)^2 + relu(ell_lo - ell)^2
+ * (V at points by trilinear interpolation; V(mu_i) held fixed), lam_sm
+ * annealed linearly from lam_sm_start to lam_sm_end over the schedule, with
+ * Adam (lr, beta1, beta2, eps).  The paper does not print the lambda values;
+ * they are knobs.  `cell` is the edge (voxels) of the grid the sample points
+ * are bucketed into.  Random draws use the counter generator of
+ * gve_allocate (SplitMix64 of (seed, stream, index), streams 20-26, index
+ * iter * samples + s).
+ *   gve_paper_create / destroy / upload / download: the parameter set
+ *     (upload resets Adam).  gve_paper_from_params: a = c / kappa (the value
+ *     at the seed before the allocation's least-squares scale), weight w0.
+ *   gve_paper_sample: the points of iteration `iter`: d_pts [2S][3] (samples,
+ *     then partners), d_vals [S].
+ *   gve_paper_eval: Vt and the density at npts points d_pts [npts][3];
+ *     g is the volume the points lie in (for bucketing).
+ *   gve_paper_loss_grad: objective (total to *h_loss, the six terms to
+ *     h_parts[6]) and gradient [12][n] at the given points (test hook).
+ *   gve_paper_refine: `iters` iterations starting at schedule position
+ *     `first_iter` of a `schedule_len`-iteration schedule; h_loss[iters]
+ *     gets the objective before each update.
+ */
+typedef struct gve_paper_options {
+  float k, rho0;
+  int32_t samples;
+  float frac_hi, frac_mid, v_hi, v_occ;
+  float lam_rho, lam_sm_start, lam_sm_end, lam_anc, lam_aniso, lam_cap;
+  float aniso_max, ell_lo, ell_hi;
+  float lr, beta1, beta2, eps;
+  float cell;
+} gve_paper_options;
+typedef struct gve_paper gve_paper;
+gve_status gve_paper_default_options(gve_paper_options* o);
+gve_status gve_paper_create(gve_ctx* ctx, int64_t n, gve_paper** out);
+void gve_paper_destroy(gve_paper* p);
+gve_status gve_paper_upload(gve_ctx* ctx, gve_paper* p, const float* h_theta);
+gve_status gve_paper_download(gve_ctx* ctx, const gve_paper* p, float* h_theta);
+gve_status gve_paper_from_params(gve_ctx* ctx, gve_paper* p, const gve_params* src, double kappa,
+                                 float w0);
+gve_status gve_paper_sample(gve_ctx* ctx, const float* d_field, gve_grid g,
+                            const gve_paper_options* o, uint64_t seed, int64_t iter, float* d_pts,
+                            float* d_vals);
+gve_status gve_paper_eval(gve_ctx* ctx, const gve_paper* p, gve_grid g, const gve_paper_options* o,
+                          const float* d_pts, int64_t npts, float* d_vt, float* d_density);
+gve_status gve_paper_loss_grad(gve_ctx* ctx, gve_paper* p, const float* d_field, gve_grid g,
+                               const gve_paper_options* o, float lam_sm, const float* d_pts,
+                               const float* d_vals, int64_t samples, float* d_grad, double* h_parts,
+                               double* h_loss);
+gve_status gve_paper_refine(gve_ctx* ctx, gve_paper* p, const float* d_field, gve_grid g,
+                            const gve_paper_options* o, uint64_t seed, int32_t iters,
+                            int32_t first_iter, int32_t schedule_len, double* h_loss);
+
+/*
  * Learned warm start.  The paper has no learned component; this network and
  * its inputs are defined by this library (readings of the shapes it is given):
  * a multilayer perceptron 16 -> 128 -> 128 -> 11 with exact-erf GELU,

@@ -62,6 +62,14 @@ class OptionsC(ctypes.Structure):
                 ("schedule", ctypes.c_int32)]
 
 
+class PaperOptionsC(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_float) for f in ("k", "rho0")] + [("samples", ctypes.c_int32)] + \
+        [(f, ctypes.c_float) for f in ("frac_hi", "frac_mid", "v_hi", "v_occ", "lam_rho",
+                                       "lam_sm_start", "lam_sm_end", "lam_anc", "lam_aniso",
+                                       "lam_cap", "aniso_max", "ell_lo", "ell_hi", "lr", "beta1",
+                                       "beta2", "eps", "cell")]
+
+
 class TuneEntryC(ctypes.Structure):
     _fields_ = [("brick", ctypes.c_int32), ("brick_z", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("ms", ctypes.c_float)]
@@ -143,6 +151,18 @@ _SIGS = {
     "gve_batch_count_pairs": [_vp, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
     "gve_autotune": [_vp, _vp, _vp, GridC, _vp, ctypes.c_int32, _vp, ctypes.c_int32,
                      ctypes.POINTER(ctypes.c_int32)],
+    "gve_paper_default_options": [ctypes.POINTER(PaperOptionsC)],
+    "gve_paper_create": [_vp, _i64, ctypes.POINTER(_vp)],
+    "gve_paper_upload": [_vp, _vp, _vp],
+    "gve_paper_download": [_vp, _vp, _vp],
+    "gve_paper_from_params": [_vp, _vp, _vp, ctypes.c_double, ctypes.c_float],
+    "gve_paper_sample": [_vp, _vp, GridC, ctypes.POINTER(PaperOptionsC), ctypes.c_uint64, _i64,
+                         _vp, _vp],
+    "gve_paper_eval": [_vp, _vp, GridC, ctypes.POINTER(PaperOptionsC), _vp, _i64, _vp, _vp],
+    "gve_paper_loss_grad": [_vp, _vp, _vp, GridC, ctypes.POINTER(PaperOptionsC), ctypes.c_float,
+                            _vp, _vp, _i64, _vp, _vp, ctypes.POINTER(ctypes.c_double)],
+    "gve_paper_refine": [_vp, _vp, _vp, GridC, ctypes.POINTER(PaperOptionsC), ctypes.c_uint64,
+                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -158,9 +178,11 @@ for _name in ("gve_export_size", "gve_checkpoint_size"):
     getattr(_lib, _name).restype = ctypes.c_size_t
 _lib.gve_batch_destroy.argtypes = [_vp]
 _lib.gve_batch_destroy.restype = None
+_lib.gve_paper_destroy.argtypes = [_vp]
+_lib.gve_paper_destroy.restype = None
 
 EXPORTED = tuple(_SIGS) + ("gve_status_string", "gve_last_error", "gve_export_size",
-                           "gve_checkpoint_size", "gve_batch_destroy")
+                           "gve_checkpoint_size", "gve_batch_destroy", "gve_paper_destroy")
 EXPORT_HEADER = 7000
 
 
@@ -714,3 +736,117 @@ def autotune(ctx: Context, field, params: Params = None, grid: Grid = None, batc
                                ctypes.byref(nw))
     _check(st, ctx.handle)
     return [(e.brick, e.brick_z, e.schedule, e.ms) for e in table[:nw.value]]
+
+
+# ---- the paper's own training loop ------------------------------------------------------
+
+PAPER_NPARAM = 12
+
+
+def paper_options(**kw):
+    """gve_paper_default_options with fields overridden by keyword."""
+    o = PaperOptionsC()
+    _check(_lib.gve_paper_default_options(ctypes.byref(o)))
+    for key, val in kw.items():
+        if not hasattr(o, key):
+            raise AttributeError(key)
+        setattr(o, key, val)
+    return o
+
+
+class PaperParams:
+    """gve_paper: 12-row primitives (mu, q, ell, a, weight logit) plus Adam state."""
+
+    def __init__(self, ctx: Context, n: int):
+        self.ctx = ctx
+        self.n = int(n)
+        h = _vp()
+        _check(_lib.gve_paper_create(ctx.handle, _i64(self.n), ctypes.byref(h)), ctx.handle)
+        self.handle = h
+
+    def upload(self, theta):
+        a = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).reshape(PAPER_NPARAM, self.n))
+        _check(_lib.gve_paper_upload(self.ctx.handle, self.handle, a.ctypes.data_as(_vp)),
+               self.ctx.handle)
+        return self
+
+    def download(self):
+        a = np.empty((PAPER_NPARAM, self.n), dtype=np.float32)
+        _check(_lib.gve_paper_download(self.ctx.handle, self.handle, a.ctypes.data_as(_vp)),
+               self.ctx.handle)
+        return a
+
+    def from_params(self, params: Params, kappa, w0=0.1):
+        _check(_lib.gve_paper_from_params(self.ctx.handle, self.handle, params.handle,
+                                          ctypes.c_double(kappa), ctypes.c_float(w0)),
+               self.ctx.handle)
+        return self
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gve_paper_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def paper_sample(ctx: Context, field, grid: Grid, opts, seed, it):
+    """(points [2S, 3] float32 cuda: samples then partners, values [S])."""
+    import torch
+
+    S = opts.samples
+    pts = torch.empty((2 * S, 3), device="cuda", dtype=torch.float32)
+    vals = torch.empty(S, device="cuda", dtype=torch.float32)
+    _check(_lib.gve_paper_sample(ctx.handle, _ptr(field, torch.float32, grid.nx * grid.ny * grid.nz),
+                                 grid.c(), ctypes.byref(opts), ctypes.c_uint64(int(seed)),
+                                 _i64(int(it)), _ptr(pts), _ptr(vals)), ctx.handle)
+    return pts, vals
+
+
+def paper_eval(ctx: Context, params: PaperParams, grid: Grid, opts, pts):
+    """(Vt, density) at points [npts, 3] (float32 cuda)."""
+    import torch
+
+    npts = pts.shape[0]
+    vt = torch.empty(npts, device="cuda", dtype=torch.float32)
+    den = torch.empty(npts, device="cuda", dtype=torch.float32)
+    _check(_lib.gve_paper_eval(ctx.handle, params.handle, grid.c(), ctypes.byref(opts),
+                               _ptr(pts, torch.float32, 3 * npts), _i64(npts), _ptr(vt),
+                               _ptr(den)), ctx.handle)
+    return vt, den
+
+
+def paper_loss_grad(ctx: Context, params: PaperParams, field, grid: Grid, opts, lam_sm, pts, vals):
+    """(objective, six terms, gradient [12, n] float32 cuda) at the given points."""
+    import torch
+
+    S = vals.shape[0]
+    grad = torch.empty((PAPER_NPARAM, params.n), device="cuda", dtype=torch.float32)
+    parts = np.zeros(6, dtype=np.float64)
+    L = ctypes.c_double()
+    _check(_lib.gve_paper_loss_grad(ctx.handle, params.handle,
+                                    _ptr(field, torch.float32, grid.nx * grid.ny * grid.nz),
+                                    grid.c(), ctypes.byref(opts), ctypes.c_float(lam_sm),
+                                    _ptr(pts, torch.float32, 6 * S), _ptr(vals, torch.float32, S),
+                                    _i64(S), _ptr(grad), parts.ctypes.data_as(_vp),
+                                    ctypes.byref(L)), ctx.handle)
+    return L.value, parts, grad
+
+
+def paper_refine(ctx: Context, params: PaperParams, field, grid: Grid, opts, seed, iters,
+                 first_iter=0, schedule_len=None):
+    """Objective before each of ``iters`` iterations (numpy)."""
+    import torch
+
+    hist = np.zeros(max(int(iters), 1), dtype=np.float64)
+    sched = int(schedule_len) if schedule_len else int(first_iter) + int(iters)
+    _check(_lib.gve_paper_refine(ctx.handle, params.handle,
+                                 _ptr(field, torch.float32, grid.nx * grid.ny * grid.nz),
+                                 grid.c(), ctypes.byref(opts), ctypes.c_uint64(int(seed)),
+                                 ctypes.c_int32(int(iters)), ctypes.c_int32(int(first_iter)),
+                                 ctypes.c_int32(sched), hist.ctypes.data_as(_vp)), ctx.handle)
+    return hist[:iters]

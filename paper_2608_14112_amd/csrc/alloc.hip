@@ -31,22 +31,6 @@ constexpr int kVoxPerThread = 16;
 constexpr int kBlockVox = kThreads * kVoxPerThread;
 constexpr float kOcc = 0.02f;
 
-__device__ inline uint64_t splitmix64(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-__device__ inline uint64_t hash_bits(uint64_t seed, uint64_t stream, uint64_t idx) {
-  return splitmix64(splitmix64(seed ^ (stream * 0xD1B54A32D192ED03ull)) ^ idx);
-}
-
-// (top 53 bits + 1) * 2^-53: uniform in (0, 1], exact in double.
-__device__ inline double uniform01(uint64_t seed, uint64_t stream, uint64_t idx) {
-  return (double)((hash_bits(seed, stream, idx) >> 11) + 1ull) * 0x1.0p-53;
-}
-
 template <typename T>
 __device__ inline T wave_reduce_add(T v) {
 #pragma unroll

@@ -428,7 +428,9 @@ gve_status gve_destroy(gve_ctx* ctx) {
                     &ws.brick_loss, &ws.scan_tmp, &ws.sort_hist, &ws.dloss, &ws.clamp_count,
                     &ws.grad_tmp, &ws.alloc, &ws.voxf, &ws.partials, &ws.mlp,
                     &ws.sat, &ws.feat, &ws.theta_base, &ws.items, &ws.order_keys[0],
-                    &ws.order_keys[1], &ws.order_vals[0], &ws.order_vals[1], &ws.queue};
+                    &ws.order_keys[1], &ws.order_vals[0], &ws.order_vals[1], &ws.queue,
+                    &ws.p_cls, &ws.p_pts, &ws.p_acc, &ws.p_coef, &ws.p_keys[0], &ws.p_keys[1],
+                    &ws.p_idx[0], &ws.p_idx[1], &ws.p_start, &ws.p_loss};
   for (Scratch* s : all)
     if (s->ptr) hipFree(s->ptr);
   if (ws.h_pinned) hipHostFree(ws.h_pinned);
@@ -1742,5 +1744,359 @@ gve_status gve_autotune(gve_ctx* ctx, const gve_params* p, const float* d_field,
   ctx->opt = best;
   guard.keep = true;
   if (n_written) *n_written = written;
+  return GVE_OK;
+}
+
+// ---- the paper's own training loop --------------------------------------------------
+
+struct gve_paper {
+  int64_t n = 0;
+  int device = 0;
+  float* theta = nullptr;  // [12][n]
+  float* m = nullptr;
+  float* v = nullptr;
+  int64_t t = 0;
+};
+
+namespace {
+
+constexpr int kPRows = 12;
+
+gve_status paper_validate(const gve_ctx* ctx, const gve_paper_options* o) {
+  if (!o) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "options are NULL");
+  if (!(o->k > 0.f) || !(o->k <= 64.f) || !(o->rho0 > 0.f) || !std::isfinite(o->rho0))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "need 0 < k <= 64 and rho0 > 0");
+  if (o->samples < 1 || o->samples > (1 << 26))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "samples must be in [1, 2^26]");
+  if (!(o->frac_hi >= 0.f) || !(o->frac_mid >= 0.f) || o->frac_hi + o->frac_mid > 1.f)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "class fractions must be >= 0 and sum to <= 1");
+  if (!(o->cell >= 1.f) || !std::isfinite(o->cell))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "cell must be >= 1 voxel");
+  if (!(o->aniso_max > 1.f) || !(o->eps > 0.f) || !(o->lr >= 0.f))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "need aniso_max > 1, eps > 0, lr >= 0");
+  return GVE_OK;
+}
+
+gve_status check_paper(const gve_ctx* ctx, const gve_paper* p) {
+  if (!ctx) return GVE_ERR_INVALID_ARGUMENT;
+  const_cast<gve_ctx*>(ctx)->last_error.clear();
+  if (!p) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "paper parameter set is NULL");
+  if (p->device != ctx->device)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "parameter set and context on different devices");
+  return GVE_OK;
+}
+
+// Bucket np points into the cell grid: sorted point indices and cell ranges.
+gve_status paper_bucket(gve_ctx* ctx, const float* pts, int64_t np, const gve::CellGrid& cg,
+                        const uint32_t** sorted, const uint32_t** start) {
+  auto& ws = ctx->ws;
+  const int64_t ncells = (int64_t)cg.ncx * cg.ncy * cg.ncz;
+  if (ncells >= ((int64_t)1 << 31)) return fail(ctx, GVE_ERR_UNSUPPORTED, "too many cells");
+  const size_t pb = sizeof(uint32_t) * (size_t)std::max<int64_t>(np, 1);
+  for (int b = 0; b < 2; ++b) {
+    TRY(ensure(ctx, ws.p_keys[b], pb));
+    TRY(ensure(ctx, ws.p_idx[b], pb));
+  }
+  TRY(ensure(ctx, ws.p_start, sizeof(uint32_t) * (size_t)(ncells + 1)));
+  TRY(ensure(ctx, ws.sort_hist, gve::sort_hist_bytes(np)));
+  uint32_t* keys[2] = {static_cast<uint32_t*>(ws.p_keys[0].ptr), static_cast<uint32_t*>(ws.p_keys[1].ptr)};
+  uint32_t* idx[2] = {static_cast<uint32_t*>(ws.p_idx[0].ptr), static_cast<uint32_t*>(ws.p_idx[1].ptr)};
+  TRY_HIP(ctx, gve::paper_cell_keys(pts, np, cg, keys[0], idx[0], ctx->stream));
+  int which = 0;
+  TRY_HIP(ctx, gve::radix_sort_pairs(keys, idx, np, bits_for(ncells), ws.sort_hist.ptr, &which,
+                                     ctx->stream));
+  uint32_t* st = static_cast<uint32_t*>(ws.p_start.ptr);
+  TRY_HIP(ctx, gve::launch_ranges(keys[which], np, ncells, st, ctx->stream));
+  *sorted = idx[which];
+  *start = st;
+  return GVE_OK;
+}
+
+// Sums w a G and w G at np points (the first S get the numerator).
+gve_status paper_accumulate(gve_ctx* ctx, const gve_paper* p, const gve::CellGrid& cg, float k,
+                            const float* pts, int64_t np, int64_t S, const uint32_t** sorted,
+                            const uint32_t** start, double** num, double** den) {
+  TRY(paper_bucket(ctx, pts, np, cg, sorted, start));
+  TRY(ensure(ctx, ctx->ws.p_acc, sizeof(double) * 2 * (size_t)std::max<int64_t>(np, 1)));
+  double* acc = static_cast<double*>(ctx->ws.p_acc.ptr);
+  TRY_HIP(ctx, gve::paper_zero(acc, 2 * np, ctx->stream));
+  *num = acc;
+  *den = acc + np;
+  TRY_HIP(ctx, gve::paper_forward(p->theta, p->n, cg, k, S, pts, *sorted, *start, *num, *den,
+                                  ctx->stream));
+  return GVE_OK;
+}
+
+// One objective evaluation at 2S points (samples then partners): losses to
+// loss[0..5], gradient (mode 0) or Adam step (mode 1, step t).
+gve_status paper_pass(gve_ctx* ctx, gve_paper* p, const float* d_field, const gve_grid& g,
+                      const gve_paper_options& o, float lam_sm, const float* pts,
+                      const float* vals, int64_t S, int mode, float* d_grad, double* loss) {
+  const gve::CellGrid cg = gve::make_cells(g, o.cell);
+  const uint32_t *sorted = nullptr, *start = nullptr;
+  double *num = nullptr, *den = nullptr;
+  TRY_HIP(ctx, gve::paper_zero(loss, 6, ctx->stream));
+  TRY(paper_accumulate(ctx, p, cg, o.k, pts, 2 * S, S, &sorted, &start, &num, &den));
+  TRY(ensure(ctx, ctx->ws.p_coef, sizeof(float) * 4 * (size_t)S));
+  float* coefA = static_cast<float*>(ctx->ws.p_coef.ptr);
+  float* coefB = coefA + 2 * S;
+  TRY_HIP(ctx, gve::paper_coef(S, o, lam_sm, num, den, vals, coefA, coefB, loss, ctx->stream));
+  TRY_HIP(ctx, gve::paper_backward(p->theta, p->m, p->v, p->n, cg, o, mode, p->t, S, pts, sorted,
+                                   start, coefA, coefB, d_field, g, d_grad, loss + 3,
+                                   ctx->stream));
+  return GVE_OK;
+}
+
+double paper_total(const gve_paper_options& o, float lam_sm, const double* parts) {
+  return parts[0] + o.lam_rho * parts[1] + lam_sm * parts[2] + o.lam_anc * parts[3] +
+         o.lam_aniso * parts[4] + o.lam_cap * parts[5];
+}
+
+// Class block offsets of the field; returns the class sizes on the host.
+gve_status paper_classes(gve_ctx* ctx, const float* d_field, const gve_grid& g,
+                         const gve_paper_options& o, const uint32_t** off_hi,
+                         const uint32_t** off_mid, uint64_t* n_hi_vox, uint64_t* n_mid_vox) {
+  const int64_t M = g.nx * g.ny * g.nz;
+  const int64_t nb = gve::paper_class_blocks(M);
+  if (M >= ((int64_t)1 << 32)) return fail(ctx, GVE_ERR_UNSUPPORTED, "volume above 2^32 voxels");
+  TRY(ensure(ctx, ctx->ws.p_cls, sizeof(uint32_t) * 4 * (size_t)(nb + 1)));
+  TRY(ensure(ctx, ctx->ws.scan_tmp, gve::scan_tmp_bytes(nb + 1)));
+  uint32_t* base = static_cast<uint32_t*>(ctx->ws.p_cls.ptr);
+  uint32_t *c_hi = base, *c_mid = base + (nb + 1), *o_hi = base + 2 * (nb + 1),
+           *o_mid = base + 3 * (nb + 1);
+  TRY_HIP(ctx, gve::paper_class_counts(d_field, M, o.v_hi, o.v_occ, c_hi, c_mid, ctx->stream));
+  TRY_HIP(ctx, gve::scan_exclusive_u32(c_hi, o_hi, nb, ctx->ws.scan_tmp.ptr, ctx->stream));
+  TRY_HIP(ctx, gve::scan_exclusive_u32(c_mid, o_mid, nb, ctx->ws.scan_tmp.ptr, ctx->stream));
+  uint32_t* hp = static_cast<uint32_t*>(ctx->ws.h_pinned);
+  TRY_HIP(ctx, hipMemcpyAsync(hp, o_hi + nb, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipMemcpyAsync(hp + 1, o_mid + nb, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *n_hi_vox = hp[0];
+  *n_mid_vox = hp[1];
+  *off_hi = o_hi;
+  *off_mid = o_mid;
+  return GVE_OK;
+}
+
+void paper_class_split(const gve_paper_options& o, uint64_t n_hi_vox, uint64_t n_mid_vox,
+                       int* n_hi, int* n_mid) {
+  const int S = o.samples;
+  *n_hi = n_hi_vox ? (int)std::floor((double)o.frac_hi * S + 0.5) : 0;
+  *n_mid = n_mid_vox ? (int)std::floor((double)o.frac_mid * S + 0.5) : 0;
+}
+
+gve_status paper_points(gve_ctx* ctx, int64_t S, float** pts, float** vals) {
+  TRY(ensure(ctx, ctx->ws.p_pts, sizeof(float) * 7 * (size_t)S));
+  *pts = static_cast<float*>(ctx->ws.p_pts.ptr);
+  *vals = *pts + 6 * S;
+  return GVE_OK;
+}
+
+}  // namespace
+
+gve_status gve_paper_default_options(gve_paper_options* o) {
+  if (!o) return GVE_ERR_INVALID_ARGUMENT;
+  o->k = 5.0f;
+  o->rho0 = 0.05f;
+  o->samples = 3072;
+  o->frac_hi = 0.35f;
+  o->frac_mid = 0.40f;
+  o->v_hi = 0.4f;
+  o->v_occ = 0.02f;
+  o->lam_rho = 0.1f;
+  o->lam_sm_start = 0.1f;
+  o->lam_sm_end = 0.01f;
+  o->lam_anc = 0.01f;
+  o->lam_aniso = 1.0f;
+  o->lam_cap = 1.0f;
+  o->aniso_max = 3.0f;
+  o->ell_lo = std::log(0.25f);
+  o->ell_hi = std::log(64.0f);
+  o->lr = 8e-3f;
+  o->beta1 = 0.9f;
+  o->beta2 = 0.999f;
+  o->eps = 1e-8f;
+  o->cell = 32.0f;
+  return GVE_OK;
+}
+
+gve_status gve_paper_create(gve_ctx* ctx, int64_t n, gve_paper** out) {
+  if (!ctx || !out) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  if (n < 1 || n >= ((int64_t)1 << 31))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "primitive count must be in [1, 2^31)");
+  TRY(set_device(ctx));
+  gve_paper* p = new (std::nothrow) gve_paper();
+  if (!p) return GVE_ERR_OUT_OF_MEMORY;
+  p->n = n;
+  p->device = ctx->device;
+  const size_t b = sizeof(float) * kPRows * (size_t)n;
+  hipError_t e = hipMalloc(&p->theta, b);
+  if (e == hipSuccess) e = hipMalloc(&p->m, b);
+  if (e == hipSuccess) e = hipMalloc(&p->v, b);
+  if (e == hipSuccess) e = gve::fill_f32(p->theta, kPRows * n, 0.0f, ctx->stream);
+  if (e == hipSuccess) e = gve::fill_f32(p->m, kPRows * n, 0.0f, ctx->stream);
+  if (e == hipSuccess) e = gve::fill_f32(p->v, kPRows * n, 0.0f, ctx->stream);
+  if (e != hipSuccess) {
+    gve_paper_destroy(p);
+    return from_hip(ctx, e, "gve_paper_create");
+  }
+  *out = p;
+  return GVE_OK;
+}
+
+void gve_paper_destroy(gve_paper* p) {
+  if (!p) return;
+  hipSetDevice(p->device);
+  hipDeviceSynchronize();
+  if (p->theta) hipFree(p->theta);
+  if (p->m) hipFree(p->m);
+  if (p->v) hipFree(p->v);
+  delete p;
+}
+
+gve_status gve_paper_upload(gve_ctx* ctx, gve_paper* p, const float* h_theta) {
+  TRY(check_paper(ctx, p));
+  if (!h_theta) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "h_theta is NULL");
+  TRY(set_device(ctx));
+  TRY_HIP(ctx, hipMemcpyAsync(p->theta, h_theta, sizeof(float) * kPRows * (size_t)p->n,
+                              hipMemcpyHostToDevice, ctx->stream));
+  TRY_HIP(ctx, gve::fill_f32(p->m, kPRows * p->n, 0.0f, ctx->stream));
+  TRY_HIP(ctx, gve::fill_f32(p->v, kPRows * p->n, 0.0f, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  p->t = 0;
+  return GVE_OK;
+}
+
+gve_status gve_paper_download(gve_ctx* ctx, const gve_paper* p, float* h_theta) {
+  TRY(check_paper(ctx, p));
+  if (!h_theta) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "h_theta is NULL");
+  TRY(set_device(ctx));
+  TRY_HIP(ctx, hipMemcpyAsync(h_theta, p->theta, sizeof(float) * kPRows * (size_t)p->n,
+                              hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return GVE_OK;
+}
+
+gve_status gve_paper_from_params(gve_ctx* ctx, gve_paper* p, const gve_params* src, double kappa,
+                                 float w0) {
+  TRY(check_paper(ctx, p));
+  if (!src || src->n != p->n)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "source params missing or of another size");
+  if (!(kappa != 0.0) || !std::isfinite(kappa) || !(w0 > 0.f && w0 < 1.f))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "need kappa != 0 and 0 < w0 < 1");
+  TRY(set_device(ctx));
+  const int64_t n = p->n;
+  std::vector<float> h((size_t)11 * n), out((size_t)kPRows * n);
+  TRY_HIP(ctx, hipMemcpyAsync(h.data(), src->theta, sizeof(float) * h.size(), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  std::copy(h.begin(), h.begin() + 10 * n, out.begin());
+  const float logit = std::log(w0 / (1.0f - w0));
+  for (int64_t i = 0; i < n; ++i) {
+    out[10 * n + i] = (float)(h[10 * n + i] / kappa);
+    out[11 * n + i] = logit;
+  }
+  return gve_paper_upload(ctx, p, out.data());
+}
+
+gve_status gve_paper_sample(gve_ctx* ctx, const float* d_field, gve_grid g,
+                            const gve_paper_options* o, uint64_t seed, int64_t iter, float* d_pts,
+                            float* d_vals) {
+  if (!ctx) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  TRY(paper_validate(ctx, o));
+  if (!d_field || !d_pts || !d_vals || iter < 0)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "field, outputs and iter >= 0 are required");
+  TRY(validate_grid(ctx, g));
+  TRY(set_device(ctx));
+  const uint32_t *oh = nullptr, *om = nullptr;
+  uint64_t nh = 0, nm = 0;
+  TRY(paper_classes(ctx, d_field, g, *o, &oh, &om, &nh, &nm));
+  int n_hi, n_mid;
+  paper_class_split(*o, nh, nm, &n_hi, &n_mid);
+  TRY_HIP(ctx, gve::paper_sample(d_field, g, oh, om, o->samples, n_hi, n_mid, seed, (uint64_t)iter,
+                                 o->v_hi, o->v_occ, d_pts, d_vals, ctx->stream));
+  return GVE_OK;
+}
+
+gve_status gve_paper_eval(gve_ctx* ctx, const gve_paper* p, gve_grid g, const gve_paper_options* o,
+                          const float* d_pts, int64_t npts, float* d_vt, float* d_density) {
+  TRY(check_paper(ctx, p));
+  TRY(paper_validate(ctx, o));
+  if (!d_pts || npts < 1 || npts >= ((int64_t)1 << 31) || (!d_vt && !d_density))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "need points, 1 <= npts < 2^31 and an output");
+  TRY(validate_grid(ctx, g));
+  TRY(set_device(ctx));
+  const uint32_t *sorted = nullptr, *start = nullptr;
+  double *num = nullptr, *den = nullptr;
+  TRY(paper_accumulate(ctx, p, gve::make_cells(g, o->cell), o->k, d_pts, npts, npts, &sorted,
+                       &start, &num, &den));
+  TRY_HIP(ctx, gve::paper_density(num, den, npts, o->rho0, d_vt, d_density, ctx->stream));
+  return GVE_OK;
+}
+
+gve_status gve_paper_loss_grad(gve_ctx* ctx, gve_paper* p, const float* d_field, gve_grid g,
+                               const gve_paper_options* o, float lam_sm, const float* d_pts,
+                               const float* d_vals, int64_t samples, float* d_grad, double* h_parts,
+                               double* h_loss) {
+  TRY(check_paper(ctx, p));
+  TRY(paper_validate(ctx, o));
+  if (!d_field || !d_pts || !d_vals || !d_grad || samples < 1 || samples >= ((int64_t)1 << 30))
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "field, points, values, gradient and samples required");
+  TRY(validate_grid(ctx, g));
+  TRY(set_device(ctx));
+  TRY(ensure(ctx, ctx->ws.p_loss, sizeof(double) * 8));
+  double* loss = static_cast<double*>(ctx->ws.p_loss.ptr);
+  TRY(paper_pass(ctx, p, d_field, g, *o, lam_sm, d_pts, d_vals, samples, 0, d_grad, loss));
+  double* hp = static_cast<double*>(ctx->ws.h_pinned);
+  TRY_HIP(ctx, hipMemcpyAsync(hp, loss, sizeof(double) * 6, hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h_parts) std::copy(hp, hp + 6, h_parts);
+  if (h_loss) *h_loss = paper_total(*o, lam_sm, hp);
+  return GVE_OK;
+}
+
+gve_status gve_paper_refine(gve_ctx* ctx, gve_paper* p, const float* d_field, gve_grid g,
+                            const gve_paper_options* o, uint64_t seed, int32_t iters,
+                            int32_t first_iter, int32_t schedule_len, double* h_loss) {
+  TRY(check_paper(ctx, p));
+  TRY(paper_validate(ctx, o));
+  if (!d_field || iters < 0 || first_iter < 0 || schedule_len < 1)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "need a field, iters >= 0, schedule_len >= 1");
+  TRY(validate_grid(ctx, g));
+  TRY(set_device(ctx));
+  if (iters == 0) return GVE_OK;
+  const uint32_t *oh = nullptr, *om = nullptr;
+  uint64_t nh = 0, nm = 0;
+  TRY(paper_classes(ctx, d_field, g, *o, &oh, &om, &nh, &nm));
+  int n_hi, n_mid;
+  paper_class_split(*o, nh, nm, &n_hi, &n_mid);
+  const int64_t S = o->samples;
+  TRY(ensure(ctx, ctx->ws.p_loss, sizeof(double) * 6 * (size_t)iters));
+  double* loss = static_cast<double*>(ctx->ws.p_loss.ptr);
+  float *pts = nullptr, *vals = nullptr;
+  TRY(paper_points(ctx, S, &pts, &vals));
+  std::vector<float> lam((size_t)iters);
+  for (int32_t i = 0; i < iters; ++i) {
+    const int32_t it = first_iter + i;
+    const double f = schedule_len > 1 ? (double)std::min(it, schedule_len - 1) / (schedule_len - 1)
+                                      : 0.0;
+    lam[i] = (float)(o->lam_sm_start + (o->lam_sm_end - o->lam_sm_start) * f);
+    TRY_HIP(ctx, gve::paper_sample(d_field, g, oh, om, (int)S, n_hi, n_mid, seed, (uint64_t)it,
+                                   o->v_hi, o->v_occ, pts, vals, ctx->stream));
+    p->t += 1;
+    TRY(paper_pass(ctx, p, d_field, g, *o, lam[i], pts, vals, S, 1, nullptr, loss + 6 * i));
+  }
+  std::vector<double> h((size_t)6 * iters);
+  TRY_HIP(ctx, hipMemcpyAsync(h.data(), loss, sizeof(double) * h.size(), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int32_t i = 0; i < iters; ++i) {
+    const double L = paper_total(*o, lam[i], &h[6 * (size_t)i]);
+    if (h_loss) h_loss[i] = L;
+    if (!std::isfinite(L)) return fail(ctx, GVE_ERR_NUMERIC, "objective is not finite");
+  }
   return GVE_OK;
 }

@@ -75,6 +75,9 @@ struct Workspace {
   Scratch items;                 // ItemDesc [volumes] of the current binning
   Scratch order_keys[2], order_vals[2];  // heaviest-first brick order (queue schedule)
   Scratch queue;                 // uint32 work counter of the persistent launch
+  // the paper's training loop: class block counts / offsets, sample points,
+  // their float64 accumulators, gradient coefficients, cell sort, losses
+  Scratch p_cls, p_pts, p_acc, p_coef, p_keys[2], p_idx[2], p_start, p_loss;
   void* h_pinned = nullptr;      // pinned host staging (64 bytes)
 };
 
@@ -222,6 +225,38 @@ hipError_t alloc_weights(const float* U, const float* f, int64_t M, float* c_row
                          double* tmp, hipStream_t s);
 size_t normalize_tmp_floats();
 hipError_t normalize_field(float* f, int64_t M, float* tmp, hipStream_t s);
+
+// ---- the paper's own training loop (paper.hip) -----------------------------------
+// Uniform grid of cells (edge h voxels) over a volume, for bucketing sample
+// points; points outside are clamped into the border cells.
+struct CellGrid {
+  float x0, y0, z0, h;
+  int ncx, ncy, ncz;
+};
+CellGrid make_cells(const gve_grid& g, float h);
+int64_t paper_class_blocks(int64_t M);
+hipError_t paper_class_counts(const float* f, int64_t M, float v_hi, float v_occ, uint32_t* cnt_hi,
+                              uint32_t* cnt_mid, hipStream_t s);
+hipError_t paper_sample(const float* f, const gve_grid& g, const uint32_t* off_hi,
+                        const uint32_t* off_mid, int S, int n_hi, int n_mid, uint64_t seed,
+                        uint64_t it, float v_hi, float v_occ, float* pts, float* vals,
+                        hipStream_t s);
+hipError_t paper_cell_keys(const float* pts, int64_t np, const CellGrid& cg, uint32_t* keys,
+                           uint32_t* idx, hipStream_t s);
+hipError_t paper_zero(double* p, int64_t n, hipStream_t s);
+hipError_t paper_forward(const float* th, int64_t n, const CellGrid& cg, float k, int64_t S,
+                         const float* pts, const uint32_t* sorted, const uint32_t* start,
+                         double* num, double* den, hipStream_t s);
+hipError_t paper_density(const double* num, const double* den, int64_t np, float rho0, float* vt,
+                         float* dn, hipStream_t s);
+hipError_t paper_coef(int64_t S, const gve_paper_options& o, float lam_sm, const double* num,
+                      const double* den, const float* vals, float* coefA, float* coefB,
+                      double* loss, hipStream_t s);
+hipError_t paper_backward(float* th, float* m, float* v, int64_t n, const CellGrid& cg,
+                          const gve_paper_options& o, int mode, int64_t t, int64_t S,
+                          const float* pts, const uint32_t* sorted, const uint32_t* start,
+                          const float* coefA, const float* coefB, const float* field,
+                          const gve_grid& fg, float* grad_out, double* loss, hipStream_t s);
 
 // ---- warm-start network (mlp.hip) --------------------------------------------
 hipError_t mlp_gemm(bool ta, bool tb, int epi, int M, int N, int K, const float* A, int lda,

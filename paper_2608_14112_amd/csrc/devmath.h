@@ -1,6 +1,7 @@
-// Device helpers shared by the allocation and warm-start feature kernels:
-// float32 field gradients (central differences, one-sided at the faces) and
-// a cyclic Jacobi eigensolver for symmetric 3x3 matrices.
+// Device helpers shared by several kernel files: float32 field gradients
+// (central differences, one-sided at the faces), a cyclic Jacobi eigensolver
+// for symmetric 3x3 matrices, the counter-based random generator, and the
+// chain rule from per-primitive kernel moments to the geometric parameters.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,6 +9,90 @@
 #include <cstdint>
 
 namespace gve {
+
+// SplitMix64 finaliser (Steele, Lea and Flood, 2014) applied to a counter:
+// 64 random bits for (seed, stream, idx), and a double uniform in (0, 1].
+static __device__ inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+static __device__ inline uint64_t hash_bits(uint64_t seed, uint64_t stream, uint64_t idx) {
+  return splitmix64(splitmix64(seed ^ (stream * 0xD1B54A32D192ED03ull)) ^ idx);
+}
+
+// (top 53 bits + 1) * 2^-53: uniform in (0, 1], exact in double.
+static __device__ inline double uniform01(uint64_t seed, uint64_t stream, uint64_t idx) {
+  return (double)((hash_bits(seed, stream, idx) >> 11) + 1ull) * 0x1.0p-53;
+}
+
+// Chain rule for one primitive with raw quaternion q (4), log-scales ell (3):
+// from S_gd = sum g d (3) and D = sum g d d^T (xx, xy, xz, yy, yz, zz) of
+// d(sum g G)/dtheta written through G's moments, out[0..2] = dmu = P S_gd,
+// out[3..6] = dq = (I - q_n q_n^T) dq_n / |q| with dq_n = <-D R S^-2, dR/dq_n>
+// (zero if |q| < 1e-12), out[7..9] = dell_j = s_j^-2 (R^T D R)_jj.
+static __device__ inline void geometry_grad(const float q[4], const float ell[3],
+                                            const float sgd[3], const float Dv[6],
+                                            float out[10]) {
+  float qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+  const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  const bool qok = qn >= 1e-12f;
+  const float qinv = qok ? 1.0f / qn : 0.0f;
+  if (qok) {
+    qw *= qinv; qx *= qinv; qy *= qinv; qz *= qinv;
+  } else {
+    qw = 1.f; qx = qy = qz = 0.f;
+  }
+  float R[3][3];
+  R[0][0] = 1.f - 2.f * (qy * qy + qz * qz);
+  R[0][1] = 2.f * (qx * qy - qw * qz);
+  R[0][2] = 2.f * (qx * qz + qw * qy);
+  R[1][0] = 2.f * (qx * qy + qw * qz);
+  R[1][1] = 1.f - 2.f * (qx * qx + qz * qz);
+  R[1][2] = 2.f * (qy * qz - qw * qx);
+  R[2][0] = 2.f * (qx * qz - qw * qy);
+  R[2][1] = 2.f * (qy * qz + qw * qx);
+  R[2][2] = 1.f - 2.f * (qx * qx + qy * qy);
+  const float is2[3] = {expf(-2.f * ell[0]), expf(-2.f * ell[1]), expf(-2.f * ell[2])};
+  float P[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      P[a][b] = R[a][0] * R[b][0] * is2[0] + R[a][1] * R[b][1] * is2[1] + R[a][2] * R[b][2] * is2[2];
+  const float D[3][3] = {{Dv[0], Dv[1], Dv[2]}, {Dv[1], Dv[3], Dv[4]}, {Dv[2], Dv[4], Dv[5]}};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out[a] = P[a][0] * sgd[0] + P[a][1] * sgd[1] + P[a][2] * sgd[2];
+  float M[3][3];  // D R
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M[a][b] = D[a][0] * R[0][b] + D[a][1] * R[1][b] + D[a][2] * R[2][b];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    out[7 + j] = is2[j] * (R[0][j] * M[0][j] + R[1][j] * M[1][j] + R[2][j] * M[2][j]);
+  float G[3][3];  // -D R S^-2
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) G[a][b] = -M[a][b] * is2[b];
+  const float w = qw, x = qx, y = qy, z = qz;
+  const float dw = 2.f * (-z * G[0][1] + y * G[0][2] + z * G[1][0] - x * G[1][2] - y * G[2][0] +
+                          x * G[2][1]);
+  const float dxq = 2.f * (y * G[0][1] + z * G[0][2] + y * G[1][0] - 2.f * x * G[1][1] -
+                           w * G[1][2] + z * G[2][0] + w * G[2][1] - 2.f * x * G[2][2]);
+  const float dyq = 2.f * (-2.f * y * G[0][0] + x * G[0][1] + w * G[0][2] + x * G[1][0] +
+                           z * G[1][2] - w * G[2][0] + z * G[2][1] - 2.f * y * G[2][2]);
+  const float dzq = 2.f * (-2.f * z * G[0][0] - w * G[0][1] + x * G[0][2] + w * G[1][0] -
+                           2.f * z * G[1][1] + y * G[1][2] + x * G[2][0] + y * G[2][1]);
+  const float dot = w * dw + x * dxq + y * dyq + z * dzq;
+  out[3] = (dw - w * dot) * qinv;
+  out[4] = (dxq - x * dot) * qinv;
+  out[5] = (dyq - y * dot) * qinv;
+  out[6] = (dzq - z * dot) * qinv;
+}
 
 struct Dims {
   int64_t nx, ny, nz;

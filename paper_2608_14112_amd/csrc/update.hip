@@ -11,6 +11,7 @@
 //   dL/dR    = -D R S^-2, contracted with dR/dq_n (R is quadratic in q_n)
 //   dL/dq    = (I - q_n q_n^T) dL/dq_n / |q|   (zero if |q| < 1e-12)
 #include "common.h"
+#include "devmath.h"
 
 namespace gve {
 namespace {
@@ -56,64 +57,9 @@ __global__ __launch_bounds__(kThreads) void k_update(int mode, float* __restrict
           acc[a * n + i] = 0.0f;
         }
       }
-      float qw = th[3], qx = th[4], qy = th[5], qz = th[6];
-      const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-      const bool qok = qn >= 1e-12f;
-      const float qinv = qok ? 1.0f / qn : 0.0f;
-      if (qok) {
-        qw *= qinv; qx *= qinv; qy *= qinv; qz *= qinv;
-      } else {
-        qw = 1.f; qx = qy = qz = 0.f;
-      }
-      float R[3][3];
-      R[0][0] = 1.f - 2.f * (qy * qy + qz * qz);
-      R[0][1] = 2.f * (qx * qy - qw * qz);
-      R[0][2] = 2.f * (qx * qz + qw * qy);
-      R[1][0] = 2.f * (qx * qy + qw * qz);
-      R[1][1] = 1.f - 2.f * (qx * qx + qz * qz);
-      R[1][2] = 2.f * (qy * qz - qw * qx);
-      R[2][0] = 2.f * (qx * qz - qw * qy);
-      R[2][1] = 2.f * (qy * qz + qw * qx);
-      R[2][2] = 1.f - 2.f * (qx * qx + qy * qy);
-      const float is2[3] = {expf(-2.f * th[7]), expf(-2.f * th[8]), expf(-2.f * th[9])};
-      float P[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-          P[a][b] = R[a][0] * R[b][0] * is2[0] + R[a][1] * R[b][1] * is2[1] +
-                    R[a][2] * R[b][2] * is2[2];
       const float sgd[3] = {s[1], s[2], s[3]};
-      const float D[3][3] = {{s[4], s[5], s[6]}, {s[5], s[7], s[8]}, {s[6], s[8], s[9]}};
-#pragma unroll
-      for (int a = 0; a < 3; ++a) gr[a] = P[a][0] * sgd[0] + P[a][1] * sgd[1] + P[a][2] * sgd[2];
-      float M[3][3];  // D R
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) M[a][b] = D[a][0] * R[0][b] + D[a][1] * R[1][b] + D[a][2] * R[2][b];
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        gr[7 + j] = is2[j] * (R[0][j] * M[0][j] + R[1][j] * M[1][j] + R[2][j] * M[2][j]);
-      float G[3][3];  // dL/dR = -D R S^-2
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) G[a][b] = -M[a][b] * is2[b];
-      const float w = qw, x = qx, y = qy, z = qz;
-      float dw = 2.f * (-z * G[0][1] + y * G[0][2] + z * G[1][0] - x * G[1][2] - y * G[2][0] +
-                        x * G[2][1]);
-      float dxq = 2.f * (y * G[0][1] + z * G[0][2] + y * G[1][0] - 2.f * x * G[1][1] -
-                         w * G[1][2] + z * G[2][0] + w * G[2][1] - 2.f * x * G[2][2]);
-      float dyq = 2.f * (-2.f * y * G[0][0] + x * G[0][1] + w * G[0][2] + x * G[1][0] +
-                         z * G[1][2] - w * G[2][0] + z * G[2][1] - 2.f * y * G[2][2]);
-      float dzq = 2.f * (-2.f * z * G[0][0] - w * G[0][1] + x * G[0][2] + w * G[1][0] -
-                         2.f * z * G[1][1] + y * G[1][2] + x * G[2][0] + y * G[2][1]);
-      const float dot = w * dw + x * dxq + y * dyq + z * dzq;
-      gr[3] = (dw - w * dot) * qinv;
-      gr[4] = (dxq - x * dot) * qinv;
-      gr[5] = (dyq - y * dot) * qinv;
-      gr[6] = (dzq - z * dot) * qinv;
+      const float Dv[6] = {s[4], s[5], s[6], s[7], s[8], s[9]};
+      geometry_grad(&th[3], &th[7], sgd, Dv, gr);
       gr[10] = s[0];
     }
     if (mode == 0) {
