@@ -142,11 +142,18 @@ __device__ inline Record load_record(const Record* __restrict__ rec, uint32_t gi
   return rec[gid];
 }
 
-// True if any lane's column meets the support (the vertex of the parabola is
-// the column's largest Q); otherwise the whole (primitive, brick) is skipped.
-// cols = ballot of the lanes whose column lies inside the volume.
-__device__ inline bool column_hit(const ColumnSetup& s, uint64_t cols, float thr) {
-  return (__builtin_amdgcn_ballot_w64(s.qxy > thr) & cols) != 0ull;
+// True if some step of the pair (brick offsets za .. zb) has Q > thr in some
+// lane whose column lies inside the volume (cols = ballot of those lanes);
+// otherwise the whole (primitive, brick) pair is skipped.  Along the column Q
+// peaks at the vertex (w = 0): inside [za, zb] the largest Q is qxy, else Q at
+// the nearer end, computed exactly as the steps compute it.
+template <int BZ>
+__device__ inline bool column_hit(const ColumnSetup& s, float sz, uint64_t cols, float thr) {
+  if (s.zmask == 0u) return false;
+  const float wa = fmaf((float)(s.za - BZ / 2), sz, s.wm);
+  const float wb = fmaf((float)(s.zb - BZ / 2), sz, s.wm);
+  const float wn = wa > 0.f ? wa : (wb < 0.f ? wb : 0.f);
+  return (__builtin_amdgcn_ballot_w64(fmaf(-wn, wn, s.qxy) > thr) & cols) != 0ull;
 }
 
 template <int BZ>
@@ -159,7 +166,7 @@ __device__ inline void accumulate_brick(const Record* __restrict__ rec,
     const Record r = load_record(rec, gid);
     const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
     const float szv = vreg(r.sz);
-    if (!column_hit(s, cols, thr)) continue;
+    if (!column_hit<BZ>(s, szv, cols, thr)) continue;
 #pragma unroll
     for (int zz = 0; zz < BZ; ++zz) {
       if ((s.zmask >> zz) & 1u) {
@@ -333,7 +340,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
     const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
-    const bool hit = column_hit(s, cols, thr);
+    const bool hit = column_hit<BZ>(s, r.sz, cols, thr);
     if (kWaves == 1 && !hit) {
       // a pair whose support misses every column still owns a partials slot
       if (part && lane < 10)
@@ -493,7 +500,7 @@ __global__ __launch_bounds__(BXY* BXY) void k_count(const Record* __restrict__ r
   for (uint32_t j = brick_start[b]; j < brick_start[b + 1]; ++j) {
     const Record r = load_record(rec, __builtin_amdgcn_readfirstlane(pair_gid[j]));
     const ColumnSetup s = column_setup<BZ>(r, st.px, st.py, st.pz0, st.iz0);
-    if (!column_hit(s, cols, thr)) continue;
+    if (!column_hit<BZ>(s, r.sz, cols, thr)) continue;
     for (int zz = s.za; zz <= s.zb; ++zz) {
       const float q = quad_w(s, w_at<BZ>(s, r.sz, zz));
       if (__builtin_amdgcn_ballot_w64(q > thr) == 0ull) continue;
