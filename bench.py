@@ -201,7 +201,7 @@ def batched_bench(args):
     grids = [g.Grid(sh[2], sh[1], sh[0]) for sh in shapes]
     cap = max(max(sh) for sh in shapes) / 16.0
     ctx = g.Context(k=args.k, lr=args.lr, ell_min=math.log(0.25), ell_max=math.log(cap),
-                    deterministic=not args.atomics)
+                    deterministic=args.deterministic)
     B = g.Batch(ctx, grids, budgets)
     t0 = time.perf_counter()
     for i, (f, gr, n) in enumerate(zip(fields, grids, budgets)):
@@ -391,8 +391,9 @@ def main():
     ap.add_argument("--schedule", type=int, default=None,
                     help="brick schedule: 0 brick order, 1 XCD-grouped, 2 persistent queue "
                          "(default: the library's)")
-    ap.add_argument("--atomics", action="store_true",
-                    help="accumulate gradient sums with float atomics instead of per-pair slots")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="per-pair gradient slots summed in a fixed order (bitwise reproducible) "
+                         "instead of float atomics")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warm-start", action="store_true",
                     help="run the warm-start time-to-PSNR comparison instead")
@@ -432,7 +433,7 @@ def main():
     M = n ** 3
     ctx = g.Context(k=args.k, brick=args.brick, brick_z=args.brick_z, lr=args.lr,
                     ell_min=math.log(0.25), ell_max=math.log(max(n / 16.0, 0.25)),
-                    deterministic=not args.atomics, schedule=args.schedule)
+                    deterministic=args.deterministic, schedule=args.schedule)
     t0 = time.perf_counter()
     P, info = g.allocate(ctx, field, grid, args.budget, args.seed)
     torch.cuda.synchronize()
@@ -490,7 +491,7 @@ def main():
             "budget": args.budget,
             "k": args.k,
             "brick": [args.brick, args.brick, args.brick_z],
-            "gradient_sums": "float atomics" if args.atomics else "per-pair slots, fixed order",
+            "gradient_sums": "per-pair slots, fixed order" if args.deterministic else "float atomics",
             "schedule": ["brick order", "XCD-grouped", "persistent queue"][ctx.options.schedule],
             "seed": args.seed,
         },

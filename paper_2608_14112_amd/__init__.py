@@ -236,7 +236,7 @@ class Context:
     """Owns a gve_ctx bound to a HIP stream (default: torch's current stream)."""
 
     def __init__(self, k=3.0, brick=8, lr=8e-3, beta1=0.9, beta2=0.999, eps=1e-8,
-                 ell_min=-math.inf, ell_max=math.inf, brick_z=None, deterministic=True,
+                 ell_min=-math.inf, ell_max=math.inf, brick_z=None, deterministic=False,
                  schedule=None, stream=None):
         import torch
 

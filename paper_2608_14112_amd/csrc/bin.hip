@@ -132,31 +132,33 @@ __global__ __launch_bounds__(kThreads) void k_prep(const float* __restrict__ the
   if ((threadIdx.x & 63) == 0 && w) atomicAdd(total, w);
 }
 
+// One wave per primitive: lane j writes pairs j, j + 64, ... of the
+// primitive's brick range (z, y, x order), so consecutive lanes write
+// consecutive addresses.
 __global__ __launch_bounds__(kThreads) void k_emit(const Record* __restrict__ rec,
                                                    const uint32_t* __restrict__ offset, int64_t n,
                                                    const ItemDesc* __restrict__ items, int nitems,
                                                    BrickGeom bg, uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (i >= n) return;
-  uint32_t o = offset[i];
-  const uint32_t e = offset[i + 1];
-  if (o == e) return;
+  const uint32_t o = offset[i];
+  const uint32_t cnt = offset[i + 1] - o;
+  if (cnt == 0) return;
   const ItemDesc& it = items[item_of_prim(items, nitems, (uint32_t)i)];
   const Record& r = rec[i];
-  const int bx0 = r.lo[0] / bg.Bxy, bx1 = r.hi[0] / bg.Bxy;
-  const int by0 = r.lo[1] / bg.Bxy, by1 = r.hi[1] / bg.Bxy;
-  const int bz0 = r.lo[2] / bg.Bz, bz1 = r.hi[2] / bg.Bz;
-  for (int bz = bz0; bz <= bz1; ++bz)
-    for (int by = by0; by <= by1; ++by) {
-      const uint32_t row =
-          it.brick0 + (uint32_t)it.nbx * ((uint32_t)by + (uint32_t)it.nby * (uint32_t)bz);
-      for (int bx = bx0; bx <= bx1; ++bx) {
-        keys[o] = row + (uint32_t)bx;
-        vals[o] = (uint32_t)i;
-        ++o;
-      }
-    }
+  const uint32_t bx0 = (uint32_t)r.lo[0] / bg.Bxy, by0 = (uint32_t)r.lo[1] / bg.Bxy,
+                 bz0 = (uint32_t)r.lo[2] / bg.Bz;
+  const uint32_t nbx_g = (uint32_t)r.hi[0] / bg.Bxy - bx0 + 1;
+  const uint32_t nby_g = (uint32_t)r.hi[1] / bg.Bxy - by0 + 1;
+  for (uint32_t j = (uint32_t)lane; j < cnt; j += 64) {
+    const uint32_t rx = j % nbx_g, t = j / nbx_g;
+    const uint32_t ry = t % nby_g, rz = t / nby_g;
+    keys[o + j] = it.brick0 + (uint32_t)it.nbx * ((by0 + ry) + (uint32_t)it.nby * (bz0 + rz)) +
+                  (bx0 + rx);
+    vals[o + j] = (uint32_t)i;
+  }
 }
 
 // brick_start[b] = first index whose key >= b, for b in [0, nbricks].
@@ -220,7 +222,7 @@ hipError_t launch_prep(const float* theta, int64_t n, const ItemDesc* items, int
 
 hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, const ItemDesc* items,
                        int nitems, BrickGeom bg, uint32_t* keys, uint32_t* vals, hipStream_t s) {
-  const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
+  const unsigned blocks = (unsigned)((n * 64 + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, rec, offset, n, items, nitems, bg,
                      keys, vals);
   return hipGetLastError();

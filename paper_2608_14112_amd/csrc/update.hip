@@ -3,8 +3,8 @@
 //
 // Inputs per primitive (from the fused brick kernel, e = r G, g = c e,
 // d = p - mu):  S_e = sum e,  S_gd = sum g d,  D = sum g d d^T, either
-// accumulated by atomics or summed here over the primitive's per-brick
-// partials in emission order (deterministic).
+// accumulated by atomics or summed over the primitive's per-brick partials in
+// a fixed order (deterministic) by k_reduce_parts first.
 //   dL/dc    = S_e
 //   dL/dmu   = P S_gd                      (P = R S^-2 R^T)
 //   dL/dl_j  = s_j^-2 (R^T D R)_jj
@@ -90,6 +90,37 @@ __global__ __launch_bounds__(kThreads) void k_update(int mode, float* __restrict
   }
 }
 
+// Per-primitive sums of the per-pair partials in a fixed order, one wave per
+// primitive: the primitive's c slots are 10 c contiguous floats; lane l < 60
+// reads elements l, l + 60, l + 120, ... (always component l % 10, coalesced
+// 240-byte rows) into four interleaved partial sums, then lanes c, c + 10,
+// ..., c + 50 are combined in that order.  Writes acc[slot * n + i] (the update then reads and clears acc).
+__global__ __launch_bounds__(kThreads) void k_reduce_parts(const float* __restrict__ part,
+                                                           const uint32_t* __restrict__ offset,
+                                                           int64_t n, float* __restrict__ acc) {
+  const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const size_t a = (size_t)offset[i] * 10, e = (size_t)offset[i + 1] * 10;
+  // four independent loads in flight per lane; the sum order stays fixed
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+  if (lane < 60) {
+    size_t k = a + (size_t)lane;
+    for (; k + 180 < e; k += 240) {
+      s0 += part[k];
+      s1 += part[k + 60];
+      s2 += part[k + 120];
+      s3 += part[k + 180];
+    }
+    for (; k < e; k += 60) s0 += part[k];
+  }
+  const float s = (s0 + s1) + (s2 + s3);
+  float t = s;
+#pragma unroll
+  for (int r = 1; r < 6; ++r) t += __shfl(s, lane + 10 * r, 64);
+  if (lane < 10) acc[(int64_t)lane * n + i] = t;
+}
+
 }  // namespace
 
 hipError_t launch_update(int mode, float* theta, float* m, float* v, float* acc,
@@ -106,6 +137,13 @@ hipError_t launch_update(int mode, float* theta, float* m, float* v, float* acc,
   ac.inv_bc2 = (float)(1.0 / (1.0 - pow((double)opt.beta2, tt)));
   ac.lmin = opt.ell_min;
   ac.lmax = opt.ell_max;
+  if (part && mode != 2) {
+    const unsigned wblocks = (unsigned)((n * 64 + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(wblocks), dim3(kThreads), 0, s, part, offset, n, acc);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    part = nullptr;
+  }
   const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_update, dim3(blocks), dim3(kThreads), 0, s, mode, theta, m, v, acc, part,
                      offset, grad_in, grad_out, n, ac, clamp_count);

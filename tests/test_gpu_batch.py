@@ -55,6 +55,7 @@ def _ggrid(g, grid):
 
 
 def _setup(g, torch, vols=VOLUMES, **ctx_kw):
+    ctx_kw.setdefault("deterministic", True)      # bitwise comparisons below
     ctx = g.Context(k=3.0, lr=5e-3, **ctx_kw)
     B = g.Batch(ctx, [_ggrid(g, v[0]) for v in vols], [v[1] for v in vols])
     thetas = [_params(*v) for v in vols]
