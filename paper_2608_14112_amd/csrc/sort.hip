@@ -6,9 +6,10 @@
 // handles `w` <= 8 key bits:
 //   1. per-tile digit histogram, stored digit-major: hist[d * ntiles + tile];
 //   2. exclusive scan of the flattened histogram -> global write offsets;
-//   3. stable scatter: a tile is consumed in rounds of 256 items in index
-//      order; an item's rank among equal digits in its wave comes from eight
-//      ballots, across waves from per-wave counts in LDS.
+//   3. stable scatter: a tile is ordered by digit in LDS, consumed in rounds
+//      of 256 items in index order (an item's rank among equal digits in its
+//      wave comes from up to eight ballots, across waves from per-wave counts
+//      in LDS), then written out run by run.
 #include "common.h"
 
 namespace gve {
@@ -36,15 +37,42 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ 
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kThreads) void k_scatter(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int64_t n, int shift,
-    uint32_t mask, int wbits, int64_t ntiles, const uint32_t* __restrict__ offs,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
-  __shared__ uint32_t run[kRadix];            // items of each digit already placed
-  __shared__ uint32_t wcnt[kWaves][kRadix];   // this round's count per wave and digit
+// Exclusive prefix sum of one value per thread over the block.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* __restrict__ wsum) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  run[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+  uint32_t incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+  return before + incl - v;
+}
+
+// Stable scatter of one tile: the tile is first ordered by digit in LDS
+// (rounds of 256 items in index order; an item's rank among equal digits in
+// its wave from the ballots, across waves from per-wave counts), then written
+// out in that order, so each digit's run of the tile lands as one contiguous
+// stretch of the output.
+__global__ __launch_bounds__(kThreads) void k_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int64_t n, int shift,
+    uint32_t mask, int wbits, int64_t ntiles, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ offs, uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+  __shared__ uint32_t skey[kTile], sval[kTile];
+  __shared__ uint32_t bstart[kRadix];         // tile-local start of each digit
+  __shared__ uint32_t run[kRadix];            // items of each digit already staged
+  __shared__ uint32_t wcnt[kWaves][kRadix];   // this round's count per wave and digit
+  __shared__ uint32_t wsum[kWaves];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const uint32_t mine = hist[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+  bstart[threadIdx.x] = block_exclusive_scan(mine, wsum);
+  run[threadIdx.x] = 0;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t base = (int64_t)blockIdx.x * kTile;
   for (int r = 0; r < kRounds; ++r) {
@@ -69,10 +97,10 @@ __global__ __launch_bounds__(kThreads) void k_scatter(
     if (valid && rank_in_wave == 0) wcnt[wave][d] = (uint32_t)__popcll(same);
     __syncthreads();
     if (valid) {
-      uint32_t pos = run[d] + rank_in_wave;
+      uint32_t pos = bstart[d] + run[d] + rank_in_wave;
       for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-      kout[pos] = key;
-      vout[pos] = val;
+      skey[pos] = key;
+      sval[pos] = val;
     }
     __syncthreads();
     uint32_t add = 0;
@@ -80,6 +108,14 @@ __global__ __launch_bounds__(kThreads) void k_scatter(
     for (int w = 0; w < kWaves; ++w) add += wcnt[w][threadIdx.x];
     run[threadIdx.x] += add;
     __syncthreads();
+  }
+  const int64_t cnt = (n - base) < kTile ? (n - base) : kTile;
+  for (int j = threadIdx.x; j < cnt; j += kThreads) {
+    const uint32_t key = skey[j];
+    const uint32_t d = (key >> shift) & mask;
+    const uint32_t pos = offs[(int64_t)d * ntiles + blockIdx.x] + ((uint32_t)j - bstart[d]);
+    kout[pos] = key;
+    vout[pos] = sval[j];
   }
 }
 
@@ -116,7 +152,7 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int
     e = scan_exclusive_u32(hist, offs, h, stmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)t), dim3(kThreads), 0, s, keys[cur], vals[cur], n,
-                       shift, mask, wb, t, offs, keys[cur ^ 1], vals[cur ^ 1]);
+                       shift, mask, wb, t, hist, offs, keys[cur ^ 1], vals[cur ^ 1]);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur ^= 1;
