@@ -1,0 +1,92 @@
+"""Parity at the benchmark's full size: 1024^3 fronts field, 1.4M primitives
+from the device allocation, k = 3, the benchmark's launch configuration
+(default options: 8x8x32 bricks, brick-order schedule, atomic sums).
+
+The oracle cannot evaluate a billion voxels, so it checks samples it can
+compute one by one: the field at 200 random voxels (from every primitive whose
+support box holds the voxel), and the loss gradient of 24 random primitives
+(on a sub-grid covering each one's support box, with every primitive whose
+box meets that sub-grid, which is exactly the data its gradient depends on).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import field as F
+from synth import fields as S
+from tests.parity import BAND, check_field, check_grad
+
+pytestmark = pytest.mark.gpu
+
+N_SIDE = 1024
+BUDGET = 1_400_000
+SEED = 2026
+
+
+@pytest.fixture(scope="module")
+def workload():
+    import torch
+
+    import paper_2608_14112_amd as g
+    assert torch.cuda.is_available()
+    print("[fullsize] fronts 1024^3 + allocation of 1.4M", flush=True)
+    field = S.fronts_field(N_SIDE, SEED, device="cuda")
+    grid = g.Grid(N_SIDE, N_SIDE, N_SIDE)
+    ctx = g.Context(k=3.0)
+    P, info = g.allocate(ctx, field, grid, BUDGET, SEED)
+    theta = P.download().astype(np.float64)
+    return g, torch, ctx, field, grid, P, theta
+
+
+def _boxes(theta, k):
+    """Support boxes (inclusive voxel ranges, unclipped) of every primitive."""
+    S_ = F.covariance(theta)
+    half = k * np.sqrt(np.stack([S_[:, 0, 0], S_[:, 1, 1], S_[:, 2, 2]], axis=1))
+    mu = theta[0:3].T
+    return np.ceil(mu - half).astype(np.int64), np.floor(mu + half).astype(np.int64)
+
+
+def _meets(lo, hi, a, b):
+    """Primitives whose box meets the voxel box [a, b] (inclusive, per axis)."""
+    return np.nonzero(np.all(lo <= b, axis=1) & np.all(hi >= a, axis=1))[0]
+
+
+def test_field_at_sampled_voxels(workload):
+    g, torch, ctx, field, grid, P, theta = workload
+    out = g.evaluate(ctx, P, grid)
+    lo, hi = _boxes(theta, 3.0)
+    rng = np.random.default_rng(11)
+    vox = rng.integers(0, N_SIDE, size=(200, 3))
+    flat = out.reshape(-1)
+    for x, y, z in vox:
+        cand = _meets(lo, hi, np.array([x, y, z]), np.array([x, y, z]))
+        sub = theta[:, cand]
+        g1 = F.Grid(1, 1, 1, int(x), int(y), int(z))
+        V, A, bracket = F.evaluate_windowed(sub, g1, 3.0, band=BAND)
+        got = float(flat[int(x) + N_SIDE * (int(y) + N_SIDE * int(z))])
+        check_field(np.array([[[got]]]), V, A, bracket)
+
+
+def test_gradient_of_sampled_primitives(workload):
+    g, torch, ctx, field, grid, P, theta = workload
+    grad = torch.empty((11, BUDGET), device="cuda")
+    g.loss_grad(ctx, P, field, grid, grad)
+    grad = grad.cpu().numpy().astype(np.float64)
+    lo, hi = _boxes(theta, 3.0)
+    rng = np.random.default_rng(12)
+    picks = rng.choice(BUDGET, size=24, replace=False)
+    fld = field  # torch, on the device
+    for i in picks:
+        a = np.maximum(lo[i], 0)
+        b = np.minimum(hi[i], N_SIDE - 1)
+        sub_grid = F.Grid(int(b[0] - a[0] + 1), int(b[1] - a[1] + 1), int(b[2] - a[2] + 1),
+                          int(a[0]), int(a[1]), int(a[2]))
+        cand = _meets(lo, hi, a, b)
+        j = int(np.nonzero(cand == i)[0][0])
+        block = fld[a[2]:b[2] + 1, a[1]:b[1] + 1, a[0]:b[0] + 1].cpu().numpy().astype(np.float64)
+        # coordinates relative to the sub-grid are the same world coordinates
+        _, gr = F.loss_grad(theta[:, cand], block, sub_grid, 3.0)
+        slack, _ = F.boundary_slack(theta[:, cand], block, sub_grid, 3.0, BAND)
+        print(f"[fullsize] primitive {i}: {cand.size} neighbours, box {sub_grid.shape}", flush=True)
+        check_grad(grad[:, i:i + 1], gr[:, j:j + 1], slack=slack[:, j:j + 1])
