@@ -309,6 +309,56 @@ def loss_grad(params, field, grid: Grid, k, return_parts=False):
     return L, grad
 
 
+def loss_grad_absolute(params, field, grid: Grid, k):
+    """Sum over in-support pairs of |per-pair contribution| to dL/dtheta, (11, N).
+
+    The same per-pair terms as ``loss_grad`` (r = 2 (V_k - V), g = c r G,
+    d = p - mu), each taken in absolute value before summing: the scale
+    against which float32 accumulation error in a gradient entry is measured
+    (a gradient that is a small difference of large terms cannot be matched
+    to 1e-3 of itself, only to 1e-3 of this).
+    """
+    mu, q, ell, c = split(params)
+    qn, qnorm, qok = normalize_quat(q)
+    R = rotation(qn)
+    P = precision(params)
+    S = covariance(params)
+    k2 = float(k) * float(k)
+    fld = np.asarray(field, dtype=np.float64).reshape(grid.shape)
+    V, _ = evaluate_windowed(params, grid, k)
+    r = 2.0 * (V - fld)
+    N = mu.shape[0]
+    out = np.zeros((NPARAM, N))
+    for i in range(N):
+        box = support_box(mu[i], S[i], k, grid)
+        if box is None:
+            continue
+        dx, dy, dz = _box_offsets(box, mu[i], grid)
+        m2 = _quad(P[i], dx, dy, dz)
+        inside = m2 < k2
+        if not np.any(inside):
+            continue
+        sl = (slice(box[2][0], box[2][1] + 1), slice(box[1][0], box[1][1] + 1),
+              slice(box[0][0], box[0][1] + 1))
+        G = np.exp(-0.5 * m2[inside])
+        e = r[sl][inside] * G
+        g = c[i] * e
+        d = np.stack([dx[inside], dy[inside], dz[inside]], axis=1)      # [v, 3]
+        out[10, i] = np.sum(np.abs(e))
+        out[0:3, i] = np.sum(np.abs((g[:, None] * d) @ P[i].T), axis=0)
+        si2 = np.exp(-2.0 * ell[i])
+        proj = d @ R[i]                                                  # r_j^T d
+        out[7:10, i] = si2 * np.sum(np.abs(g)[:, None] * proj * proj, axis=0)
+        if qok[i]:
+            Dp = g[:, None, None] * d[:, :, None] * d[:, None, :]        # [v, 3, 3]
+            dR = -np.einsum("vij,jk->vik", Dp, R[i] @ np.diag(si2))
+            dRq = rotation_partials(qn[i])
+            dqn = np.einsum("vij,aij->va", dR, dRq)
+            qg = dqn @ (np.eye(4) - np.outer(qn[i], qn[i])).T / qnorm[i]
+            out[3:7, i] = np.sum(np.abs(qg), axis=0)
+    return out
+
+
 def _pair_jacobian(c, G, d, P, R, ell, qn, qnorm, qok):
     """d(c G(p))/dtheta for one primitive and one in-support voxel (11 values).
 

@@ -48,22 +48,28 @@ def check_field(gpu, ref, A, bracket=None, rtol=VAL_RTOL):
     return worst
 
 
-def check_grad(gpu, ref, rtol=GRAD_RTOL, slack=None):
+def check_grad(gpu, ref, rtol=GRAD_RTOL, slack=None, absolute=None):
     """``slack`` (from ``oracle.field.boundary_slack``): per entry, how far the
     gradient may move because pairs near the cut are decided either way; it is
-    added to the elementwise tolerance and its norm to the norm-wise one."""
+    added to the elementwise tolerance and its norm to the norm-wise one.
+    ``absolute`` (from ``oracle.field.loss_grad_absolute``): the sum of the
+    absolute per-pair contributions; when given, the relative tolerance also
+    applies to it (for entries that are small differences of large terms,
+    e.g. a single primitive's quaternion gradient)."""
     gpu = np.asarray(gpu, dtype=np.float64)
     if slack is None:
         slack = np.zeros_like(ref)
+    if absolute is None:
+        absolute = np.zeros_like(ref)
     out = {}
     for name, sl in GROUPS.items():
-        g, r, s = gpu[sl], ref[sl], slack[sl]
+        g, r, s, a = gpu[sl], ref[sl], slack[sl], absolute[sl]
         nr = float(np.linalg.norm(r))
         err = float(np.linalg.norm(g - r))
-        assert err <= rtol * nr + float(np.linalg.norm(s)), \
+        assert err <= rtol * (nr + float(np.linalg.norm(a))) + float(np.linalg.norm(s)), \
             f"{name}: norm-wise relative error {err / max(nr, 1e-300):.3e}"
         floor = 0.1 * rtol * float(np.max(np.abs(r))) if r.size else 0.0
-        bad = np.abs(g - r) > rtol * np.abs(r) + floor + s
+        bad = np.abs(g - r) > rtol * (np.abs(r) + a) + floor + s
         assert not np.any(bad), f"{name}: {int(bad.sum())} entries outside tolerance"
         out[name] = err / nr if nr > 0 else err
     return out

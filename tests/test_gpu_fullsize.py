@@ -88,5 +88,8 @@ def test_gradient_of_sampled_primitives(workload):
         # coordinates relative to the sub-grid are the same world coordinates
         _, gr = F.loss_grad(theta[:, cand], block, sub_grid, 3.0)
         slack, _ = F.boundary_slack(theta[:, cand], block, sub_grid, 3.0, BAND)
+        # one primitive's gradient sums thousands of float32 terms with heavy
+        # cancellation (q . dL/dq = 0): its error scale is the absolute sum
+        absg = F.loss_grad_absolute(theta[:, cand], block, sub_grid, 3.0)[:, j:j + 1]
         print(f"[fullsize] primitive {i}: {cand.size} neighbours, box {sub_grid.shape}", flush=True)
-        check_grad(grad[:, i:i + 1], gr[:, j:j + 1], slack=slack[:, j:j + 1])
+        check_grad(grad[:, i:i + 1], gr[:, j:j + 1], slack=slack[:, j:j + 1], absolute=absg)

@@ -318,3 +318,27 @@ def test_boundary_slack_bounds_the_effect_of_flipping_pairs(sign):
     assert np.all(diff <= 1.01 * slack + 1e-12)
     # and the slack is not vacuous: same order as the change it bounds
     assert np.sum(slack) < 50 * np.sum(diff)
+
+
+def test_absolute_gradient_bounds_the_gradient_and_matches_single_pair():
+    """|dL/dtheta| <= sum of |per-pair terms| entrywise, with equality for c
+    when every residual has one sign; on a one-voxel grid (a single pair per
+    primitive) the absolute sum is |gradient| exactly."""
+    grid = F.Grid(15, 13, 12)
+    params = S.random_params(6, (15, 13, 12), seed=3, scale_range=(1.0, 3.0), unit_quat=False)
+    field = np.random.default_rng(4).uniform(-1, 1, size=grid.shape)
+    _, gr = F.loss_grad(params, field, grid, 3.0)
+    ab = F.loss_grad_absolute(params, field, grid, 3.0)
+    assert np.all(np.abs(gr) <= ab * (1 + 1e-12) + 1e-15)
+    V, _ = F.evaluate_windowed(params, grid, 3.0)
+    below = V - 5.0                        # target far above: every residual negative
+    _, g2 = F.loss_grad(params, below, grid, 3.0)
+    a2 = F.loss_grad_absolute(params, below, grid, 3.0)
+    assert np.allclose(np.abs(g2[10]), a2[10], rtol=1e-12)
+    one = F.Grid(1, 1, 1, 7, 6, 6)
+    p1 = params.copy()
+    p1[0:3] = np.array([[7.3], [6.2], [5.9]]) + np.random.default_rng(5).uniform(-0.5, 0.5, (3, 6))
+    f1 = np.array([[[0.37]]])
+    _, g1 = F.loss_grad(p1, f1, one, 3.0)
+    a1 = F.loss_grad_absolute(p1, f1, one, 3.0)
+    assert np.allclose(np.abs(g1), a1, rtol=1e-10, atol=1e-15)
