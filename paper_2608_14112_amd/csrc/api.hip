@@ -182,9 +182,10 @@ int resident_groups(gve_ctx* ctx, int bxy, int bz) {
   return r;
 }
 
-// prep -> scan -> emit -> radix sort -> brick ranges (-> heaviest-first
-// order for the queue schedule).  Reads the pair count back to the host (one
-// small synchronising copy) to size the pair buffers.
+// prep -> (scan -> cull ->) scan -> emit -> radix sort -> brick ranges (->
+// heaviest-first order for the queue schedule).  Reads the box pair total (and
+// with culling the kept total) back to the host, small synchronising copies
+// that size the pair buffers.
 gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* out) {
   hipStream_t s = ctx->stream;
   auto& ws = ctx->ws;
@@ -202,17 +203,43 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   TRY_HIP(ctx, gve::fill_u64(total, 1, s));
   TRY_HIP(ctx, gve::launch_prep(p->theta, n, items, vol.n, ctx->opt.k, bg, p->rec, p->count,
                                 total, s));
-  TRY_HIP(ctx, gve::scan_exclusive_u32(p->count, p->offset, n, ws.scan_tmp.ptr, s));
-  TRY_HIP(ctx, hipMemcpyAsync(ws.h_pinned, total, sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, s));
+  // Culling drops bricks a separating plane parts from the support.  The
+  // deterministic partials address a pair by its brick's rank in the whole
+  // box, so they keep every box brick.  The box total bounds the kept total,
+  // so below the limit every 32-bit scan is exact.
+  const bool cull = ctx->opt.deterministic == 0;
+  unsigned char* hp = static_cast<unsigned char*>(ws.h_pinned);
+  const uint32_t* box_off = nullptr;
+  uint32_t* kept = nullptr;
+  if (cull) {
+    TRY(ensure(ctx, ws.box_off, sizeof(uint32_t) * (size_t)(n + 1)));
+    uint32_t* bo = static_cast<uint32_t*>(ws.box_off.ptr);
+    TRY_HIP(ctx, gve::scan_exclusive_u32(p->count, bo, n, ws.scan_tmp.ptr, s));
+    box_off = bo;
+  }
+  TRY_HIP(ctx, hipMemcpyAsync(hp, total, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   TRY_HIP(ctx, hipStreamSynchronize(s));
-  const unsigned long long T = *reinterpret_cast<unsigned long long*>(ws.h_pinned);
-  if (T >= 0xFFFFFFF0ull)
+  const unsigned long long box_total = *reinterpret_cast<unsigned long long*>(hp);
+  if (box_total >= 0xFFFFFFF0ull)
     return fail(ctx, GVE_ERR_UNSUPPORTED,
                 "more than 2^32 (primitive, brick) pairs; use larger bricks or a smaller k");
+  if (cull) {
+    // the kept keys wait in the sort's second key buffer until emission
+    TRY(ensure(ctx, ws.keys[1], sizeof(uint32_t) * (size_t)(box_total > 0 ? box_total : 1)));
+    kept = static_cast<uint32_t*>(ws.keys[1].ptr);
+    TRY_HIP(ctx, gve::launch_cull(p->rec, n, box_off, items, vol.n, bg, ctx->opt.k, kept,
+                                  p->count, s));
+  }
+  TRY_HIP(ctx, gve::scan_exclusive_u32(p->count, p->offset, n, ws.scan_tmp.ptr, s));
+  unsigned long long T = box_total;
+  if (cull) {
+    TRY_HIP(ctx, hipMemcpyAsync(hp + 8, p->offset + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    TRY_HIP(ctx, hipStreamSynchronize(s));
+    T = *reinterpret_cast<uint32_t*>(hp + 8);
+  }
   const size_t pair_bytes = sizeof(uint32_t) * (size_t)(T > 0 ? T : 1);
   for (int b = 0; b < 2; ++b) {
-    TRY(ensure(ctx, ws.keys[b], pair_bytes));
+    TRY(ensure(ctx, ws.keys[b], pair_bytes));  // keys[1] already holds >= T: kept
     TRY(ensure(ctx, ws.vals[b], pair_bytes));
   }
   const bool queue = ctx->opt.schedule == GVE_SCHED_QUEUE;
@@ -221,7 +248,8 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   TRY(ensure(ctx, ws.brick_start, sizeof(uint32_t) * (size_t)(bg.nbricks + 1)));
   uint32_t* keys[2] = {static_cast<uint32_t*>(ws.keys[0].ptr), static_cast<uint32_t*>(ws.keys[1].ptr)};
   uint32_t* vals[2] = {static_cast<uint32_t*>(ws.vals[0].ptr), static_cast<uint32_t*>(ws.vals[1].ptr)};
-  TRY_HIP(ctx, gve::launch_emit(p->rec, p->offset, n, items, vol.n, bg, keys[0], vals[0], s));
+  TRY_HIP(ctx, gve::launch_emit(p->rec, p->offset, n, items, vol.n, bg, box_off, kept, keys[0],
+                                vals[0], s));
   int which = 0;
   TRY_HIP(ctx, gve::radix_sort_pairs(keys, vals, (int64_t)T, bits_for(bg.nbricks), ws.sort_hist.ptr,
                                      &which, s));

@@ -7,6 +7,9 @@
 //            bounding box
 //            (|d_j| < k sqrt(Sigma_jj) bounds the ellipsoid m^2 < k^2) clipped
 //            to the grid, and the number of bricks that box touches;
+//   cull   : (atomic gradient sums only) per primitive, the bricks of its box
+//            that a separating plane does not part from its support, their
+//            keys and their count (which replaces the box's brick count);
 //   emit   : the (brick, primitive) pairs at the scanned offsets;
 //   ranges : first pair of every brick in the brick-sorted list (binary search).
 #include "common.h"
@@ -132,13 +135,120 @@ __global__ __launch_bounds__(kThreads) void k_prep(const float* __restrict__ the
   if ((threadIdx.x & 63) == 0 && w) atomicAdd(total, w);
 }
 
-// One wave per primitive: lane j writes pairs j, j + 64, ... of the
-// primitive's brick range (z, y, x order), so consecutive lanes write
-// consecutive addresses.
+// ---- culling of bricks that miss the support -----------------------------
+//
+// A brick that meets a primitive's k-sigma box can still miss its ellipsoid
+// m^2 < k^2 (the corners of a rotated ellipsoid's box).  Let C be the brick's
+// part of the box (voxel centres), c its centre, h its half extents,
+// d = c - mu and n = P d, the ellipsoid's normal direction at c.  Along n the
+// ellipsoid m <= K reaches at most n.mu + K sqrt(n^T Sigma n) = n.mu + K sqrt(d^T P d),
+// and C reaches down to n.c - sum_j |n_j| h_j, so the plane normal to n parts
+// them when
+//     d^T P d - sum_j |n_j| h_j > K sqrt(d^T P d).
+// With K = k (1 + 1e-3) every voxel of C then has m^2 > 1.002 k^2, well
+// clear of where float32 rounding could decide the cut either way, and a
+// relative allowance of 1e-5 covers the rounding of the test itself.  In the
+// record's scaled units (Q = -(log2 e / 2) m^2, the xy part qxy = s0 dx^2 +
+// s1 dx dy + s2 dy^2, the z part -(sz t)^2 with t = dz - gx dx - gy dy) the
+// scaled normal (log2 e / 2) P d is
+//     (-(s0 dx + s1 dy / 2) - sz^2 t gx, -(s1 dx / 2 + s2 dy) - sz^2 t gy, sz^2 t)
+// and (log2 e / 2) d^T P d = sz^2 t^2 - qxy.  The test is conservative: a brick
+// it keeps may still miss (the brick kernels test every column anyway).
+__device__ inline bool brick_meets_support(const Record& r, const ItemDesc& it, BrickGeom bg,
+                                           uint32_t bx, uint32_t by, uint32_t bz, float k) {
+  const int bxy = bg.Bxy, bzz = bg.Bz;
+  const int xa = max((int)bx * bxy, r.lo[0]), xb = min((int)bx * bxy + bxy - 1, r.hi[0]);
+  const int ya = max((int)by * bxy, r.lo[1]), yb = min((int)by * bxy + bxy - 1, r.hi[1]);
+  const int za = max((int)bz * bzz, r.lo[2]), zb = min((int)bz * bzz + bzz - 1, r.hi[2]);
+  const float dx = 0.5f * (float)(xa + xb) + (float)it.x0 - r.mu[0];
+  const float dy = 0.5f * (float)(ya + yb) + (float)it.y0 - r.mu[1];
+  const float dz = 0.5f * (float)(za + zb) + (float)it.z0 - r.mu[2];
+  const float hx = 0.5f * (float)(xb - xa), hy = 0.5f * (float)(yb - ya),
+              hz = 0.5f * (float)(zb - za);
+  const float t = dz - (r.gx * dx + r.gy * dy);
+  const float sz2 = r.sz * r.sz;
+  const float qxy = (r.s[0] * dx + r.s[1] * dy) * dx + r.s[2] * dy * dy;
+  const float nx = -(r.s[0] * dx + 0.5f * r.s[1] * dy) - sz2 * t * r.gx;
+  const float ny = -(0.5f * r.s[1] * dx + r.s[2] * dy) - sz2 * t * r.gy;
+  const float nz = sz2 * t;
+  const float mm = sz2 * t * t - qxy;
+  const float side = fabsf(nx) * hx + fabsf(ny) * hy + fabsf(nz) * hz;
+  const float reach = (1.0f + 1e-3f) * k * sqrtf(kHalfLog2e) * sqrtf(mm);
+  // NaN anywhere keeps the brick
+  return !(mm - side > reach + 1e-5f * (mm + side));
+}
+
+// Bricks of primitive i's box, in (z, y, x) order.
+struct BoxBricks {
+  uint32_t bx0, by0, bz0, nbx, nby;
+  __device__ void at(uint32_t j, uint32_t& bx, uint32_t& by, uint32_t& bz) const {
+    const uint32_t t = j / nbx;
+    bx = bx0 + j % nbx;
+    by = by0 + t % nby;
+    bz = bz0 + t / nby;
+  }
+};
+
+__device__ inline BoxBricks box_bricks(const Record& r, BrickGeom bg) {
+  BoxBricks b;
+  b.bx0 = (uint32_t)r.lo[0] / bg.Bxy;
+  b.by0 = (uint32_t)r.lo[1] / bg.Bxy;
+  b.bz0 = (uint32_t)r.lo[2] / bg.Bz;
+  b.nbx = (uint32_t)r.hi[0] / bg.Bxy - b.bx0 + 1;
+  b.nby = (uint32_t)r.hi[1] / bg.Bxy - b.by0 + 1;
+  return b;
+}
+
+__device__ inline uint32_t brick_key(const ItemDesc& it, uint32_t bx, uint32_t by, uint32_t bz) {
+  return it.brick0 + (uint32_t)it.nbx * (by + (uint32_t)it.nby * bz) + bx;
+}
+
+// One wave per primitive over the bricks of its box (box_off: scan of prep's
+// box brick counts).  Keeps the bricks brick_meets_support does not reject,
+// in box order, compacted by ballot: their keys go to kept[box_off[i] ..] and
+// their number to count[i].
+__global__ __launch_bounds__(kThreads) void k_cull(const Record* __restrict__ rec, int64_t n,
+                                                   const uint32_t* __restrict__ box_off,
+                                                   const ItemDesc* __restrict__ items, int nitems,
+                                                   BrickGeom bg, float k,
+                                                   uint32_t* __restrict__ kept,
+                                                   uint32_t* __restrict__ count) {
+  const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const uint32_t o = box_off[i];
+  const uint32_t total = box_off[i + 1] - o;
+  if (total == 0) return;  // count[i] is already 0
+  const ItemDesc& it = items[item_of_prim(items, nitems, (uint32_t)i)];
+  const Record r = rec[i];
+  const BoxBricks bb = box_bricks(r, bg);
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t nkept = 0;
+  for (uint32_t base = 0; base < total; base += 64) {
+    const uint32_t j = base + (uint32_t)lane;
+    bool keep = false;
+    uint32_t bx = 0, by = 0, bz = 0;
+    if (j < total) {
+      bb.at(j, bx, by, bz);
+      keep = brick_meets_support(r, it, bg, bx, by, bz, k);
+    }
+    const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+    if (keep) kept[o + nkept + (uint32_t)__popcll(m & below)] = brick_key(it, bx, by, bz);
+    nkept += (uint32_t)__popcll(m);
+  }
+  if (lane == 0) count[i] = nkept;
+}
+
+// One wave per primitive: the pairs at the scanned offsets.  Without culling
+// every brick of the box in (z, y, x) order (lane j writes pairs j, j + 64,
+// ..., consecutive lanes at consecutive addresses); with culling the kept
+// keys k_cull stored.
 __global__ __launch_bounds__(kThreads) void k_emit(const Record* __restrict__ rec,
                                                    const uint32_t* __restrict__ offset, int64_t n,
                                                    const ItemDesc* __restrict__ items, int nitems,
-                                                   BrickGeom bg, uint32_t* __restrict__ keys,
+                                                   BrickGeom bg, const uint32_t* __restrict__ box_off,
+                                                   const uint32_t* __restrict__ kept,
+                                                   uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals) {
   const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -146,17 +256,20 @@ __global__ __launch_bounds__(kThreads) void k_emit(const Record* __restrict__ re
   const uint32_t o = offset[i];
   const uint32_t cnt = offset[i + 1] - o;
   if (cnt == 0) return;
+  if (kept) {
+    const uint32_t src = box_off[i];
+    for (uint32_t j = (uint32_t)lane; j < cnt; j += 64) {
+      keys[o + j] = kept[src + j];
+      vals[o + j] = (uint32_t)i;
+    }
+    return;
+  }
   const ItemDesc& it = items[item_of_prim(items, nitems, (uint32_t)i)];
-  const Record& r = rec[i];
-  const uint32_t bx0 = (uint32_t)r.lo[0] / bg.Bxy, by0 = (uint32_t)r.lo[1] / bg.Bxy,
-                 bz0 = (uint32_t)r.lo[2] / bg.Bz;
-  const uint32_t nbx_g = (uint32_t)r.hi[0] / bg.Bxy - bx0 + 1;
-  const uint32_t nby_g = (uint32_t)r.hi[1] / bg.Bxy - by0 + 1;
+  const BoxBricks bb = box_bricks(rec[i], bg);
   for (uint32_t j = (uint32_t)lane; j < cnt; j += 64) {
-    const uint32_t rx = j % nbx_g, t = j / nbx_g;
-    const uint32_t ry = t % nby_g, rz = t / nby_g;
-    keys[o + j] = it.brick0 + (uint32_t)it.nbx * ((by0 + ry) + (uint32_t)it.nby * (bz0 + rz)) +
-                  (bx0 + rx);
+    uint32_t bx, by, bz;
+    bb.at(j, bx, by, bz);
+    keys[o + j] = brick_key(it, bx, by, bz);
     vals[o + j] = (uint32_t)i;
   }
 }
@@ -220,11 +333,21 @@ hipError_t launch_prep(const float* theta, int64_t n, const ItemDesc* items, int
   return hipGetLastError();
 }
 
+hipError_t launch_cull(const Record* rec, int64_t n, const uint32_t* box_off, const ItemDesc* items,
+                       int nitems, BrickGeom bg, float k, uint32_t* kept, uint32_t* count,
+                       hipStream_t s) {
+  const unsigned blocks = (unsigned)((n * 64 + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_cull, dim3(blocks), dim3(kThreads), 0, s, rec, n, box_off, items, nitems,
+                     bg, k, kept, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, const ItemDesc* items,
-                       int nitems, BrickGeom bg, uint32_t* keys, uint32_t* vals, hipStream_t s) {
+                       int nitems, BrickGeom bg, const uint32_t* box_off, const uint32_t* kept,
+                       uint32_t* keys, uint32_t* vals, hipStream_t s) {
   const unsigned blocks = (unsigned)((n * 64 + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, rec, offset, n, items, nitems, bg,
-                     keys, vals);
+                     box_off, kept, keys, vals);
   return hipGetLastError();
 }
 

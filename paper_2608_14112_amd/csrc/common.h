@@ -61,6 +61,7 @@ struct Workspace {
   Scratch brick_start;           // uint32 [n_bricks + 1]
   Scratch brick_loss;            // float  [n_bricks]
   Scratch scan_tmp;              // scan partials
+  Scratch box_off;               // uint32 [n + 1] scan of box brick counts (culling)
   Scratch sort_hist;             // radix sort histograms
   Scratch dloss;                 // double [4]
   Scratch clamp_count;           // unsigned long long
@@ -161,8 +162,17 @@ struct Schedule {
 hipError_t launch_prep(const float* theta, int64_t n, const ItemDesc* items, int nitems, float k,
                        BrickGeom bg, Record* rec, uint32_t* count, unsigned long long* total,
                        hipStream_t s);
+// Culling: box_off = exclusive scan of prep's box brick counts; the keys of
+// the box bricks a separating plane does not part from the support m^2 < k^2
+// go to kept[box_off[i] ..] and their number to count[i].
+hipError_t launch_cull(const Record* rec, int64_t n, const uint32_t* box_off, const ItemDesc* items,
+                       int nitems, BrickGeom bg, float k, uint32_t* kept, uint32_t* count,
+                       hipStream_t s);
+// Pairs at the scanned offsets: every box brick (kept == nullptr) or the
+// kept keys of launch_cull.
 hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, const ItemDesc* items,
-                       int nitems, BrickGeom bg, uint32_t* keys, uint32_t* vals, hipStream_t s);
+                       int nitems, BrickGeom bg, const uint32_t* box_off, const uint32_t* kept,
+                       uint32_t* keys, uint32_t* vals, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t npairs, int64_t nbricks,
                          uint32_t* brick_start, hipStream_t s);
 // Heaviest-first brick order for kSchedQueue: keys = leading zeros of the

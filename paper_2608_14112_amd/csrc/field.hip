@@ -349,7 +349,8 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
     }
     float v[10];
     {
-      float se = 0.0f, sW = 0.0f, sWW = 0.0f;
+      // moments of e over the brick offset zz (a literal operand per step)
+      float se = 0.0f, sK = 0.0f, sKK = 0.0f;
       if (hit) {
         const float szv = vreg(r.sz);
 #pragma unroll
@@ -361,23 +362,19 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
               const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
               const float e = res[zz] * G;
               se += e;
-              const float ew = e * w;
-              sW += ew;
-              sWW = fmaf(ew, w, sWW);
+              sK = fmaf((float)zz, e, sK);
+              sKK = fmaf((float)(zz * zz), e, sKK);
             }
           }
         }
       }
-      // sum e t = sW / sz, sum e t^2 = sWW / sz^2; back to d = p - mu:
-      // sum e dz = sT + ofs se, sum e dz^2 = sTT + 2 ofs sT + ofs^2 se
-      const float isz = __builtin_amdgcn_rcpf(r.sz);  // 1 ulp; gradients need 1e-3
-      const float sT = sW * isz;
-      const float sTT = sWW * isz * isz;
+      // dz = p_z - mu_z = ofs + zz with ofs = z0 - mu_z, so
+      // sum e dz = sK + ofs se and sum e dz^2 = sKK + 2 ofs sK + ofs^2 se
       const float dx = px - r.mu[0];
       const float dy = py - r.mu[1];
-      const float ofs = (pz0 - r.mu[2]) - s.t0;
-      const float s1 = fmaf(ofs, se, sT);
-      const float s2 = fmaf(ofs, fmaf(ofs, se, 2.0f * sT), sTT);
+      const float ofs = pz0 - r.mu[2];
+      const float s1 = fmaf(ofs, se, sK);
+      const float s2 = fmaf(ofs, fmaf(ofs, se, 2.0f * sK), sKK);
       const float cse = r.c * se, cs1 = r.c * s1;
       v[0] = se;
       v[1] = dx * cse;

@@ -93,6 +93,61 @@ def test_forward_is_bitwise_reproducible_and_brick_invariant():
         assert np.max(np.abs(a.astype(np.float64) - c) / (A + 1e-30)) < 1e-5
 
 
+def _support_bricks(params, grid, k, bxy, bz):
+    """(primitive, brick) pairs whose brick holds a voxel with m^2 < k^2 (1 + 1e-4),
+    and pairs whose brick meets the primitive's k-sigma box (float64 definitions)."""
+    cov = F.covariance(params)
+    P = F.precision(params)
+    mu = params[0:3].T
+    nsup = nbox = 0
+    for i in range(params.shape[1]):
+        box = F.support_box(mu[i], cov[i], k, grid)
+        if box is None:
+            continue
+        (ia, ib), (ja, jb), (ka, kb) = box
+        nbox += (ib // bxy - ia // bxy + 1) * (jb // bxy - ja // bxy + 1) * (kb // bz - ka // bz + 1)
+        dx, dy, dz = F._box_offsets(box, mu[i], grid)
+        inside = F._quad(P[i], dx, dy, dz) < k * k * (1 + 1e-4)
+        zz, yy, xx = np.nonzero(inside)
+        keys = {((x + ia) // bxy, (y + ja) // bxy, (z + ka) // bz) for x, y, z in zip(xx, yy, zz)}
+        nsup += len(keys)
+    return nsup, nbox
+
+
+@pytest.mark.parametrize("brick", [(8, 32), (16, 16)])
+def test_brick_culling_keeps_every_brick_with_support(brick):
+    """Atomic-sum binning drops bricks a separating plane parts from the
+    support; the deterministic binning keeps the whole box.  The field is
+    bitwise the same, and the kept pairs lie between the bricks that hold
+    support and the bricks of the box."""
+    g, torch = _lib()
+    grid = F.Grid(48, 44, 70, 2, -1, 3)
+    rng = np.random.default_rng(21)
+    p = S.random_params(120, (48, 44, 70), seed=21, scale_range=(0.7, 2.0), unit_quat=False)
+    p[7] += rng.uniform(0.5, 1.6, p.shape[1])          # elongated: log-scale spread up to ~5x
+    p[0] += grid.x0
+    p[1] += grid.y0
+    p[2] += grid.z0
+    p = p.astype(np.float32).astype(np.float64)
+    bxy, bz = brick
+    outs, pairs = [], []
+    for det in (False, True):
+        ctx = g.Context(k=3.0, brick=bxy, brick_z=bz, deterministic=det)
+        P = g.Params(ctx, p.shape[1]).upload(p.astype(np.float32))
+        out = torch.empty(grid.shape, device="cuda", dtype=torch.float32)
+        g.evaluate(ctx, P, g.Grid(grid.nx, grid.ny, grid.nz, grid.x0, grid.y0, grid.z0), out)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+        pairs.append(ctx.stats()["n_overlaps"])
+    assert np.array_equal(outs[0], outs[1])
+    nsup, nbox = _support_bricks(p, grid, 3.0, bxy, bz)
+    print(f"support {nsup}, culled {pairs[0]}, box {pairs[1]} (oracle box {nbox})", flush=True)
+    assert nsup <= pairs[0] < pairs[1]
+    assert abs(pairs[1] - nbox) <= 0.01 * nbox
+    V, A, br = F.evaluate_windowed(p, grid, 3.0, band=BAND)
+    check_field(outs[0], V, A, br)
+
+
 def test_large_k_equals_untruncated_field():
     g, torch = _lib()
     grid = F.Grid(30, 30, 30)
