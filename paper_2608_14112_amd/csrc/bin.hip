@@ -178,14 +178,30 @@ __device__ inline bool brick_meets_support(const Record& r, const ItemDesc& it, 
   return !(mm - side > reach + 1e-5f * (mm + side));
 }
 
+// j / d for j < 2^21 through a float reciprocal: (j + 1/2) / d lies at least
+// 1/(2d) from every integer, and a reciprocal within 1 ulp times a rounded
+// product moves it by less than (j + 1/2) / d * 1.5 * 2^-23 < 1/(2d), so the
+// truncation is exact.
+__device__ inline uint32_t div_small(uint32_t j, float inv_d) {
+  return (uint32_t)(((float)j + 0.5f) * inv_d);
+}
+
 // Bricks of primitive i's box, in (z, y, x) order.
 struct BoxBricks {
   uint32_t bx0, by0, bz0, nbx, nby;
+  float inv_nbx, inv_nby;
   __device__ void at(uint32_t j, uint32_t& bx, uint32_t& by, uint32_t& bz) const {
-    const uint32_t t = j / nbx;
-    bx = bx0 + j % nbx;
-    by = by0 + t % nby;
-    bz = bz0 + t / nby;
+    uint32_t t, u;
+    if (j < (1u << 21)) {
+      t = div_small(j, inv_nbx);
+      u = div_small(t, inv_nby);
+    } else {
+      t = j / nbx;
+      u = t / nby;
+    }
+    bx = bx0 + (j - t * nbx);
+    by = by0 + (t - u * nby);
+    bz = bz0 + u;
   }
 };
 
@@ -196,6 +212,8 @@ __device__ inline BoxBricks box_bricks(const Record& r, BrickGeom bg) {
   b.bz0 = (uint32_t)r.lo[2] / bg.Bz;
   b.nbx = (uint32_t)r.hi[0] / bg.Bxy - b.bx0 + 1;
   b.nby = (uint32_t)r.hi[1] / bg.Bxy - b.by0 + 1;
+  b.inv_nbx = 1.0f / (float)b.nbx;
+  b.inv_nby = 1.0f / (float)b.nby;
   return b;
 }
 
@@ -203,52 +221,63 @@ __device__ inline uint32_t brick_key(const ItemDesc& it, uint32_t bx, uint32_t b
   return it.brick0 + (uint32_t)it.nbx * (by + (uint32_t)it.nby * bz) + bx;
 }
 
-// One wave per primitive over the bricks of its box (box_off: scan of prep's
-// box brick counts).  Keeps the bricks brick_meets_support does not reject,
-// in box order, compacted by ballot: their keys go to kept[box_off[i] ..] and
-// their number to count[i].
+// Sixteen lanes per primitive (four primitives per wave, so that launching
+// and loading cost less than the work) over the bricks of its box (box_off:
+// scan of prep's box brick counts).  Keeps the bricks brick_meets_support
+// does not reject, in box order, compacted by ballot within the lane group:
+// their keys go to kept[box_off[i] ..] and their number to count[i].
+constexpr int kGroup = 16;
+
 __global__ __launch_bounds__(kThreads) void k_cull(const Record* __restrict__ rec, int64_t n,
                                                    const uint32_t* __restrict__ box_off,
                                                    const ItemDesc* __restrict__ items, int nitems,
                                                    BrickGeom bg, float k,
                                                    uint32_t* __restrict__ kept,
                                                    uint32_t* __restrict__ count) {
-  const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kGroup;
   const int lane = threadIdx.x & 63;
-  if (i >= n) return;
-  const uint32_t o = box_off[i];
-  const uint32_t total = box_off[i + 1] - o;
-  if (total == 0) return;  // count[i] is already 0
-  const ItemDesc& it = items[item_of_prim(items, nitems, (uint32_t)i)];
-  const Record r = rec[i];
-  const BoxBricks bb = box_bricks(r, bg);
-  const uint64_t below = (1ull << lane) - 1ull;
+  const int sub = lane & (kGroup - 1);
+  const int shift = lane & ~(kGroup - 1);  // first lane of the group
+  const bool live = i < n;
+  uint32_t o = 0, total = 0;
+  if (live) {
+    o = box_off[i];
+    total = box_off[i + 1] - o;
+  }
+  Record r{};
+  BoxBricks bb{};
+  const ItemDesc* it = items;
+  if (total > 0) {
+    r = rec[i];
+    bb = box_bricks(r, bg);
+    it = &items[item_of_prim(items, nitems, (uint32_t)i)];
+  }
+  const uint64_t below = ((1ull << lane) - 1ull) & ~((1ull << shift) - 1ull);
   uint32_t nkept = 0;
-  for (uint32_t base = 0; base < total; base += 64) {
-    const uint32_t j = base + (uint32_t)lane;
+  // every lane of the wave takes part in each ballot; a group idles once its
+  // box is done
+  for (uint32_t base = 0; __builtin_amdgcn_ballot_w64(base < total) != 0ull; base += kGroup) {
+    const uint32_t j = base + (uint32_t)sub;
     bool keep = false;
     uint32_t bx = 0, by = 0, bz = 0;
     if (j < total) {
       bb.at(j, bx, by, bz);
-      keep = brick_meets_support(r, it, bg, bx, by, bz, k);
+      keep = brick_meets_support(r, *it, bg, bx, by, bz, k);
     }
     const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
-    if (keep) kept[o + nkept + (uint32_t)__popcll(m & below)] = brick_key(it, bx, by, bz);
-    nkept += (uint32_t)__popcll(m);
+    if (keep) kept[o + nkept + (uint32_t)__popcll(m & below)] = brick_key(*it, bx, by, bz);
+    nkept += (uint32_t)__popcll((m >> shift) & ((1ull << kGroup) - 1ull));
   }
-  if (lane == 0) count[i] = nkept;
+  if (live && total > 0 && sub == 0) count[i] = nkept;
 }
 
-// One wave per primitive: the pairs at the scanned offsets.  Without culling
-// every brick of the box in (z, y, x) order (lane j writes pairs j, j + 64,
-// ..., consecutive lanes at consecutive addresses); with culling the kept
-// keys k_cull stored.
+// Pairs at the scanned offsets, every brick of the box in (z, y, x) order:
+// one wave per primitive, lane j writes pairs j, j + 64, ... (consecutive
+// lanes at consecutive addresses).
 __global__ __launch_bounds__(kThreads) void k_emit(const Record* __restrict__ rec,
                                                    const uint32_t* __restrict__ offset, int64_t n,
                                                    const ItemDesc* __restrict__ items, int nitems,
-                                                   BrickGeom bg, const uint32_t* __restrict__ box_off,
-                                                   const uint32_t* __restrict__ kept,
-                                                   uint32_t* __restrict__ keys,
+                                                   BrickGeom bg, uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals) {
   const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -256,20 +285,32 @@ __global__ __launch_bounds__(kThreads) void k_emit(const Record* __restrict__ re
   const uint32_t o = offset[i];
   const uint32_t cnt = offset[i + 1] - o;
   if (cnt == 0) return;
-  if (kept) {
-    const uint32_t src = box_off[i];
-    for (uint32_t j = (uint32_t)lane; j < cnt; j += 64) {
-      keys[o + j] = kept[src + j];
-      vals[o + j] = (uint32_t)i;
-    }
-    return;
-  }
   const ItemDesc& it = items[item_of_prim(items, nitems, (uint32_t)i)];
   const BoxBricks bb = box_bricks(rec[i], bg);
   for (uint32_t j = (uint32_t)lane; j < cnt; j += 64) {
     uint32_t bx, by, bz;
     bb.at(j, bx, by, bz);
     keys[o + j] = brick_key(it, bx, by, bz);
+    vals[o + j] = (uint32_t)i;
+  }
+}
+
+// Pairs at the scanned offsets from the keys k_cull kept: sixteen lanes per
+// primitive.
+__global__ __launch_bounds__(kThreads) void k_emit_kept(const uint32_t* __restrict__ offset,
+                                                        int64_t n,
+                                                        const uint32_t* __restrict__ box_off,
+                                                        const uint32_t* __restrict__ kept,
+                                                        uint32_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ vals) {
+  const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kGroup;
+  const uint32_t sub = threadIdx.x & (kGroup - 1);
+  if (i >= n) return;
+  const uint32_t o = offset[i];
+  const uint32_t cnt = offset[i + 1] - o;
+  const uint32_t src = box_off[i];
+  for (uint32_t j = sub; j < cnt; j += kGroup) {
+    keys[o + j] = kept[src + j];
     vals[o + j] = (uint32_t)i;
   }
 }
@@ -336,7 +377,7 @@ hipError_t launch_prep(const float* theta, int64_t n, const ItemDesc* items, int
 hipError_t launch_cull(const Record* rec, int64_t n, const uint32_t* box_off, const ItemDesc* items,
                        int nitems, BrickGeom bg, float k, uint32_t* kept, uint32_t* count,
                        hipStream_t s) {
-  const unsigned blocks = (unsigned)((n * 64 + kThreads - 1) / kThreads);
+  const unsigned blocks = (unsigned)((n * kGroup + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_cull, dim3(blocks), dim3(kThreads), 0, s, rec, n, box_off, items, nitems,
                      bg, k, kept, count);
   return hipGetLastError();
@@ -345,9 +386,15 @@ hipError_t launch_cull(const Record* rec, int64_t n, const uint32_t* box_off, co
 hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, const ItemDesc* items,
                        int nitems, BrickGeom bg, const uint32_t* box_off, const uint32_t* kept,
                        uint32_t* keys, uint32_t* vals, hipStream_t s) {
-  const unsigned blocks = (unsigned)((n * 64 + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, rec, offset, n, items, nitems, bg,
-                     box_off, kept, keys, vals);
+  if (kept) {
+    const unsigned blocks = (unsigned)((n * kGroup + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_emit_kept, dim3(blocks), dim3(kThreads), 0, s, offset, n, box_off, kept,
+                       keys, vals);
+  } else {
+    const unsigned blocks = (unsigned)((n * 64 + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, rec, offset, n, items, nitems,
+                       bg, keys, vals);
+  }
   return hipGetLastError();
 }
 

@@ -16,15 +16,17 @@
 //   k_forward : Vhat on the brick (Sec. III-C eq:field, truncated).
 //   k_fused   : Vhat, residual r = 2 (Vhat - V), the brick's share of
 //               L = sum (Vhat - V)^2, then for every primitive of the brick the
-//               ten sums of the analytic gradient (e = r G, g = c e,
-//               d = p - mu): sum e, sum g d (3), sum g d d^T (6 unique),
-//               reduced over the workgroup with cross-lane permutes and LDS,
+//               ten sums of the analytic gradient (e = r G, d = p - mu):
+//               sum e, sum e d (3), sum e d d^T (6 unique; the weight c,
+//               common to all bricks of a primitive, is applied once per
+//               primitive by the update), reduced over the workgroup with
+//               cross-lane permutes and LDS,
 //               then either added to the primitive's accumulators with float
 //               atomics, or (deterministic mode) stored to the pair's own slot
 //               of a partials array that the update kernel sums per primitive
-//               in a fixed order.  Per column only sum e, sum e w, sum e w^2 are
-//               needed because dx, dy and dz - t are constant along it (and
-//               t = w / sz).
+//               in a fixed order.  Per column only sum e, sum e zz and
+//               sum e zz^2 over the brick offset zz are needed, because dx and
+//               dy are constant along it and dz = (z0 - mu_z) + zz.
 #include <algorithm>
 
 #include "common.h"
@@ -375,17 +377,17 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
       const float ofs = pz0 - r.mu[2];
       const float s1 = fmaf(ofs, se, sK);
       const float s2 = fmaf(ofs, fmaf(ofs, se, 2.0f * sK), sKK);
-      const float cse = r.c * se, cs1 = r.c * s1;
+      const float xe = dx * se, ye = dy * se;
       v[0] = se;
-      v[1] = dx * cse;
-      v[2] = dy * cse;
-      v[3] = cs1;
-      v[4] = dx * dx * cse;
-      v[5] = dx * dy * cse;
-      v[6] = dx * cs1;
-      v[7] = dy * dy * cse;
-      v[8] = dy * cs1;
-      v[9] = r.c * s2;
+      v[1] = xe;
+      v[2] = ye;
+      v[3] = s1;
+      v[4] = dx * xe;
+      v[5] = dy * xe;
+      v[6] = dx * s1;
+      v[7] = dy * ye;
+      v[8] = dy * s1;
+      v[9] = s2;
     }
     float o[3];
     wave_reduce10(v, o);

@@ -1,10 +1,12 @@
 // Chain rule from the brick kernels' per-primitive sums to the 11 parameters,
 // fused with the bias-corrected Adam step (Sec. III-F cites Kingma and Ba).
 //
-// Inputs per primitive (from the fused brick kernel, e = r G, g = c e,
-// d = p - mu):  S_e = sum e,  S_gd = sum g d,  D = sum g d d^T, either
-// accumulated by atomics or summed over the primitive's per-brick partials in
-// a fixed order (deterministic) by k_reduce_parts first.
+// Inputs per primitive (from the fused brick kernel, e = r G, d = p - mu):
+// S_e = sum e,  S_ed = sum e d,  D_e = sum e d d^T, either accumulated by
+// atomics or summed over the primitive's per-brick partials in a fixed order
+// (deterministic) by k_reduce_parts first.  With g = c e the weighted sums are
+// S_gd = c S_ed and D = c D_e (c is the same in every brick, so it is applied
+// here once).
 //   dL/dc    = S_e
 //   dL/dmu   = P S_gd                      (P = R S^-2 R^T)
 //   dL/dl_j  = s_j^-2 (R^T D R)_jj
@@ -57,8 +59,9 @@ __global__ __launch_bounds__(kThreads) void k_update(int mode, float* __restrict
           acc[a * n + i] = 0.0f;
         }
       }
-      const float sgd[3] = {s[1], s[2], s[3]};
-      const float Dv[6] = {s[4], s[5], s[6], s[7], s[8], s[9]};
+      const float c = th[10];
+      const float sgd[3] = {c * s[1], c * s[2], c * s[3]};
+      const float Dv[6] = {c * s[4], c * s[5], c * s[6], c * s[7], c * s[8], c * s[9]};
       geometry_grad(&th[3], &th[7], sgd, Dv, gr);
       gr[10] = s[0];
     }
