@@ -494,14 +494,14 @@ gve_status gve_params_create(gve_ctx* ctx, int64_t n, gve_params** out) {
   if (e == hipSuccess) e = hipMalloc(&p->theta, f11);
   if (e == hipSuccess) e = hipMalloc(&p->m, f11);
   if (e == hipSuccess) e = hipMalloc(&p->v, f11);
-  if (e == hipSuccess) e = hipMalloc(&p->acc, sizeof(float) * 10 * (size_t)n);
+  if (e == hipSuccess) e = hipMalloc(&p->acc, sizeof(float) * gve::kAccStride * (size_t)n);
   if (e == hipSuccess) e = hipMalloc(&p->rec, sizeof(gve::Record) * (size_t)n);
   if (e == hipSuccess) e = hipMalloc(&p->count, sizeof(uint32_t) * (size_t)n);
   if (e == hipSuccess) e = hipMalloc(&p->offset, sizeof(uint32_t) * (size_t)(n + 1));
   if (e == hipSuccess) e = gve::fill_f32(p->theta, 11 * n, 0.0f, ctx->stream);
   if (e == hipSuccess) e = gve::fill_f32(p->m, 11 * n, 0.0f, ctx->stream);
   if (e == hipSuccess) e = gve::fill_f32(p->v, 11 * n, 0.0f, ctx->stream);
-  if (e == hipSuccess) e = gve::fill_f32(p->acc, 10 * n, 0.0f, ctx->stream);
+  if (e == hipSuccess) e = gve::fill_f32(p->acc, gve::kAccStride * n, 0.0f, ctx->stream);
   if (e != hipSuccess) {
     gve_params_destroy(p);
     return from_hip(ctx, e, "gve_params_create");
@@ -605,7 +605,7 @@ gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field
   TRY(set_device(ctx));
   gve_params* pm = const_cast<gve_params*>(p);
   TRY(ensure_dloss(ctx));
-  TRY_HIP(ctx, gve::fill_f32(pm->acc, 10 * p->n, 0.0f, ctx->stream));
+  TRY_HIP(ctx, gve::fill_f32(pm->acc, gve::kAccStride * p->n, 0.0f, ctx->stream));
   double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
   float* part = nullptr;
   TRY(loss_and_sums(ctx, p, d_field, g, dl, &part));
@@ -613,7 +613,7 @@ gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field
     TRY_HIP(ctx, gve::launch_update(0, pm->theta, pm->m, pm->v, pm->acc, part, p->offset, nullptr,
                                     d_grad, p->n, p->t, ctx->opt, nullptr, ctx->stream));
   } else {
-    TRY_HIP(ctx, gve::fill_f32(pm->acc, 10 * p->n, 0.0f, ctx->stream));
+    TRY_HIP(ctx, gve::fill_f32(pm->acc, gve::kAccStride * p->n, 0.0f, ctx->stream));
   }
   if (h_loss) {
     TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, dl, sizeof(double), hipMemcpyDeviceToHost,
@@ -640,7 +640,7 @@ gve_status gve_vjp(gve_ctx* ctx, const gve_params* p, const float* d_upstream, g
   TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)std::max<int64_t>(bn.bg.nbricks, 1)));
   float* part = nullptr;
   TRY(partials_for(ctx, bn.npairs, &part));
-  if (!part) TRY_HIP(ctx, gve::fill_f32(pm->acc, 10 * p->n, 0.0f, ctx->stream));
+  if (!part) TRY_HIP(ctx, gve::fill_f32(pm->acc, gve::kAccStride * p->n, 0.0f, ctx->stream));
   TRY(fused(ctx, p, bn, d_upstream, part, static_cast<float*>(ctx->ws.brick_loss.ptr), true));
   TRY_HIP(ctx, gve::launch_update(0, pm->theta, pm->m, pm->v, pm->acc, part, p->offset, nullptr,
                                   d_grad, p->n, p->t, ctx->opt, nullptr, ctx->stream));
@@ -861,7 +861,7 @@ gve_status refine_vol(gve_ctx* ctx, gve_params* p, const float* d_field, const V
   const size_t nl = (size_t)vol.n * (size_t)(iters > 0 ? iters : 1);
   TRY(ensure(ctx, ctx->ws.grad_tmp, sizeof(double) * nl));
   double* hist = static_cast<double*>(ctx->ws.grad_tmp.ptr);
-  TRY_HIP(ctx, gve::fill_f32(p->acc, 10 * p->n, 0.0f, ctx->stream));
+  TRY_HIP(ctx, gve::fill_f32(p->acc, gve::kAccStride * p->n, 0.0f, ctx->stream));
   const bool timing = ctx->timing && iters > 0;
   if (timing) {
     while ((int64_t)ctx->events.size() < 4 * (int64_t)iters) {
@@ -1185,7 +1185,7 @@ gve_status eval_loss(gve_ctx* ctx, const gve_params* p, const float* d_field, co
   double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
   float* part = nullptr;
   TRY(loss_and_sums(ctx, p, d_field, g, dl, &part));
-  if (!part) TRY_HIP(ctx, gve::fill_f32(const_cast<gve_params*>(p)->acc, 10 * p->n, 0.0f, ctx->stream));
+  if (!part) TRY_HIP(ctx, gve::fill_f32(const_cast<gve_params*>(p)->acc, gve::kAccStride * p->n, 0.0f, ctx->stream));
   TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, dl, sizeof(double), hipMemcpyDeviceToHost,
                               ctx->stream));
   TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));

@@ -36,6 +36,11 @@ static_assert(sizeof(Record) == 64, "record must be 64 bytes");
 
 constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
 
+// Gradient accumulators: acc[i * kAccStride + a] holds sum a (0..9) of
+// primitive i, so the ten float atomics of one (primitive, brick) pair all
+// fall in one 64-byte line (entries 10..15 are padding and stay zero).
+constexpr int kAccStride = 16;
+
 // One volume of a set that is binned and evaluated together (a single-volume
 // call is a set of one).  Primitives [prim0, next prim0) belong to it and
 // reach only its bricks [brick0, next brick0); its voxels start at `vox` in
@@ -104,7 +109,7 @@ struct gve_params {
   float* theta = nullptr;   // [11][n]
   float* m = nullptr;       // [11][n]
   float* v = nullptr;       // [11][n]
-  float* acc = nullptr;     // [10][n] gradient partial sums (see field kernels)
+  float* acc = nullptr;     // [n][kAccStride] gradient partial sums (see field kernels)
   gve::Record* rec = nullptr;  // [n]
   uint32_t* count = nullptr;   // [n]   bricks overlapped per primitive
   uint32_t* offset = nullptr;  // [n+1] exclusive scan of count
@@ -187,7 +192,7 @@ int fused_resident_groups(int bxy, int bz, int device);
 hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid,
                           const uint32_t* brick_start, const ItemDesc* items, int nitems,
                           BrickGeom bg, float k, float* out, const Schedule& sc, hipStream_t s);
-// part == nullptr: float atomics into acc [10][n].  Otherwise each (primitive,
+// part == nullptr: float atomics into acc [n][kAccStride].  Otherwise each (primitive,
 // brick) pair stores its ten sums to part[(offset[gid] + rank) * 10 + slot],
 // rank = the brick's position in the primitive's emitted brick range.
 hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid,

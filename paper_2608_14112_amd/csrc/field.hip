@@ -405,7 +405,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const int slot = reduce10_slot(k, row);
-          if (slot >= 0) unsafeAtomicAdd(&gacc[(int64_t)slot * n + gid], o[k]);
+          if (slot >= 0) unsafeAtomicAdd(&gacc[(int64_t)gid * kAccStride + slot], o[k]);
         }
       }
     } else {
@@ -424,7 +424,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
           part[(size_t)pair_slot<BXY, BZ>(r, offset, gid, st.bx, st.by, st.bz) * 10 +
                threadIdx.x] = t;
         } else if (t != 0.0f) {
-          unsafeAtomicAdd(&gacc[(int64_t)threadIdx.x * n + gid], t);
+          unsafeAtomicAdd(&gacc[(int64_t)gid * kAccStride + threadIdx.x], t);
         }
       }
       __syncthreads();

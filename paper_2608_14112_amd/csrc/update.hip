@@ -55,8 +55,8 @@ __global__ __launch_bounds__(kThreads) void k_update(int mode, float* __restrict
       } else {
 #pragma unroll
         for (int a = 0; a < 10; ++a) {
-          s[a] = acc[a * n + i];
-          acc[a * n + i] = 0.0f;
+          s[a] = acc[i * kAccStride + a];
+          acc[i * kAccStride + a] = 0.0f;
         }
       }
       const float c = th[10];
@@ -97,7 +97,8 @@ __global__ __launch_bounds__(kThreads) void k_update(int mode, float* __restrict
 // primitive: the primitive's c slots are 10 c contiguous floats; lane l < 60
 // reads elements l, l + 60, l + 120, ... (always component l % 10, coalesced
 // 240-byte rows) into four interleaved partial sums, then lanes c, c + 10,
-// ..., c + 50 are combined in that order.  Writes acc[slot * n + i] (the update then reads and clears acc).
+// ..., c + 50 are combined in that order.  Writes acc[i * kAccStride + slot]
+// (the update then reads and clears acc).
 __global__ __launch_bounds__(kThreads) void k_reduce_parts(const float* __restrict__ part,
                                                            const uint32_t* __restrict__ offset,
                                                            int64_t n, float* __restrict__ acc) {
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_parts(const float* __restri
   float t = s;
 #pragma unroll
   for (int r = 1; r < 6; ++r) t += __shfl(s, lane + 10 * r, 64);
-  if (lane < 10) acc[(int64_t)lane * n + i] = t;
+  if (lane < 10) acc[i * kAccStride + lane] = t;
 }
 
 }  // namespace
