@@ -158,27 +158,37 @@ __device__ inline bool column_hit(const ColumnSetup& s, float sz, uint64_t cols,
   return (__builtin_amdgcn_ballot_w64(fmaf(-wn, wn, s.qxy) > thr) & cols) != 0ull;
 }
 
+// With `steps` (one-wave bricks), the brick offsets at which some lane of
+// pair j - j0 < kStepCap was inside the support are stored as a bit mask
+// (0: the pair misses the brick), so the backward pass visits only those.
+constexpr uint32_t kStepCap = 1024;
+
 template <int BZ>
 __device__ inline void accumulate_brick(const Record* __restrict__ rec,
                                         const uint32_t* __restrict__ pair_gid, uint32_t j0,
                                         uint32_t j1, float px, float py, float pz0, int iz0,
-                                        uint64_t cols, float thr, float (&acc)[BZ]) {
+                                        uint64_t cols, float thr, float (&acc)[BZ],
+                                        uint32_t* __restrict__ steps) {
   for (uint32_t j = j0; j < j1; ++j) {
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
     const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
     const float szv = vreg(r.sz);
-    if (!column_hit<BZ>(s, szv, cols, thr)) continue;
+    uint32_t active = 0u;
+    if (column_hit<BZ>(s, szv, cols, thr)) {
 #pragma unroll
-    for (int zz = 0; zz < BZ; ++zz) {
-      if ((s.zmask >> zz) & 1u) {
-        const float q = quad_w(s, w_at<BZ>(s, szv, zz));
-        if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
-          const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
-          acc[zz] = fmaf(r.c, G, acc[zz]);
+      for (int zz = 0; zz < BZ; ++zz) {
+        if ((s.zmask >> zz) & 1u) {
+          const float q = quad_w(s, w_at<BZ>(s, szv, zz));
+          if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
+            active |= 1u << zz;
+            const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
+            acc[zz] = fmaf(r.c, G, acc[zz]);
+          }
         }
       }
     }
+    if (steps && j - j0 < kStepCap && (threadIdx.x & 63) == 0) steps[j - j0] = active;
   }
 }
 
@@ -247,7 +257,7 @@ __device__ __attribute__((always_inline)) inline void forward_brick(const Record
 #pragma unroll
   for (int zz = 0; zz < BZ; ++zz) acc[zz] = 0.0f;
   accumulate_brick<BZ>(rec, pair_gid, brick_start[b], brick_start[b + 1], st.px, st.py, st.pz0,
-                       st.iz0, __builtin_amdgcn_ballot_w64(st.col_in), thr, acc);
+                       st.iz0, __builtin_amdgcn_ballot_w64(st.col_in), thr, acc, nullptr);
   if (st.col_in) {
 #pragma unroll
     for (int zz = 0; zz < BZ; ++zz)
@@ -280,6 +290,31 @@ __device__ inline uint32_t pair_slot(const Record& r, const uint32_t* __restrict
          ((uint32_t)bx - lx);
 }
 
+// The backward steps of one pair over the brick offsets in `run`: moments
+// of e = r G over zz.  CHECK skips offsets where no lane is inside the
+// support; without it every offset in `run` must hold some lane inside (the
+// offsets the forward pass recorded), and the steps carry no branch that
+// waits on a compare.
+template <int BZ, bool CHECK>
+__device__ inline void backward_steps(const ColumnSetup& s, float szv, uint32_t run,
+                                      const float (&res)[BZ], float thr, float& se, float& sK,
+                                      float& sKK) {
+#pragma unroll
+  for (int zz = 0; zz < BZ; ++zz) {
+    if ((run >> zz) & 1u) {
+      const float w = w_at<BZ>(s, szv, zz);
+      const float q = quad_w(s, w);
+      if (!CHECK || __builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
+        const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
+        const float e = res[zz] * G;
+        se += e;
+        sK = fmaf((float)zz, e, sK);
+        sKK = fmaf((float)(zz * zz), e, sKK);
+      }
+    }
+  }
+}
+
 // One brick of the fused pass.  VJP = false: residual r = 2 (Vhat - V) from
 // the forward pass and the target `field`, loss share to brick_loss.
 // VJP = true: no forward pass; r is read from `field` (an upstream gradient
@@ -294,7 +329,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
                                    float* __restrict__ gacc, int64_t n, float* __restrict__ part,
                                    const uint32_t* __restrict__ offset,
                                    float* __restrict__ brick_loss,
-                                   float (*red)[10]) {
+                                   float (*red)[10], uint32_t* __restrict__ steps) {
   constexpr int kWaves = (BXY * BXY + 63) / 64;
   const Site st = site_of<BXY, BZ>(items, nitems, b);
   const int lane = threadIdx.x & 63;
@@ -314,7 +349,8 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
     for (int zz = 0; zz < BZ; ++zz)
       if (col_in && zz < st.zrem) res[zz] = field[st.base + st.plane * (size_t)(iz0 + zz)];
   } else {
-    accumulate_brick<BZ>(rec, pair_gid, j0, j1, px, py, pz0, iz0, cols, thr, res);
+    accumulate_brick<BZ>(rec, pair_gid, j0, j1, px, py, pz0, iz0, cols, thr, res,
+                         kWaves == 1 ? steps : nullptr);
     // residual and this brick's share of the loss
     float lsum = 0.0f;
 #pragma unroll
@@ -342,7 +378,10 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
     const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
-    const bool hit = column_hit<BZ>(s, r.sz, cols, thr);
+    // the steps the forward pass found active, else the box's z-range
+    const bool recorded = kWaves == 1 && !VJP && j - j0 < kStepCap;
+    const uint32_t run = recorded ? __builtin_amdgcn_readfirstlane(steps[j - j0]) : s.zmask;
+    const bool hit = recorded ? run != 0u : column_hit<BZ>(s, r.sz, cols, thr);
     if (kWaves == 1 && !hit) {
       // a pair whose support misses every column still owns a partials slot
       if (part && lane < 10)
@@ -355,20 +394,10 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
       float se = 0.0f, sK = 0.0f, sKK = 0.0f;
       if (hit) {
         const float szv = vreg(r.sz);
-#pragma unroll
-        for (int zz = 0; zz < BZ; ++zz) {
-          if ((s.zmask >> zz) & 1u) {
-            const float w = w_at<BZ>(s, szv, zz);
-            const float q = quad_w(s, w);
-            if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
-              const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
-              const float e = res[zz] * G;
-              se += e;
-              sK = fmaf((float)zz, e, sK);
-              sKK = fmaf((float)(zz * zz), e, sKK);
-            }
-          }
-        }
+        if (recorded)
+          backward_steps<BZ, false>(s, szv, run, res, thr, se, sK, sKK);
+        else
+          backward_steps<BZ, true>(s, szv, run, res, thr, se, sK, sKK);
       }
       // dz = p_z - mu_z = ofs + zz with ofs = z0 - mu_z, so
       // sum e dz = sK + ofs se and sum e dz^2 = sKK + 2 ofs sK + ofs^2 se
@@ -446,9 +475,10 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
                                                 float* __restrict__ brick_loss) {
   constexpr int kWaves = (BXY * BXY + 63) / 64;
   __shared__ float red[kWaves][10];
+  __shared__ uint32_t steps[kWaves == 1 && !VJP ? kStepCap : 1];
   const uint32_t b = xcd ? xcd_brick(blockIdx.x, nbricks) : blockIdx.x;
   fused_brick<BXY, BZ, VJP>(rec, pair_gid, brick_start, items, nitems, b, thr, field, gacc, n,
-                            part, offset, brick_loss, red);
+                            part, offset, brick_loss, red, steps);
 }
 
 // Persistent: each workgroup takes queue positions from *counter until they
@@ -469,6 +499,7 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused_queue(const Record* __restri
                                                       float* __restrict__ brick_loss) {
   constexpr int kWaves = (BXY * BXY + 63) / 64;
   __shared__ float red[kWaves][10];
+  __shared__ uint32_t steps[kWaves == 1 && !VJP ? kStepCap : 1];
   __shared__ uint32_t next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
@@ -477,7 +508,7 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused_queue(const Record* __restri
     __syncthreads();
     if (w >= nbricks) break;
     fused_brick<BXY, BZ, VJP>(rec, pair_gid, brick_start, items, nitems, order[w], thr, field,
-                              gacc, n, part, offset, brick_loss, red);
+                              gacc, n, part, offset, brick_loss, red, steps);
   }
 }
 
