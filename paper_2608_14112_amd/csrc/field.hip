@@ -315,6 +315,49 @@ __device__ inline void backward_steps(const ColumnSetup& s, float szv, uint32_t 
   }
 }
 
+// Backward steps of a recorded pair by recurrence.  Along a column Q is a
+// parabola in zz: with R(zz) = exp2(Q(zz + 1) - Q(zz)) = exp2(-(2 w + sz) sz)
+// and C = exp2(-2 sz^2), G(zz + 1) = G(zz) R(zz) and R(zz + 1) = R(zz) C, two
+// products per step in place of w, Q and an exp2.  The chain starts exactly
+// one offset before the first recorded offset z0 (w, Q, and exp2 of Q and of
+// the first difference there) and advances once per offset up to the last,
+// z1; offsets between them that no lane reached add zero.  A lane whose
+// starting Q is <= -100 starts at G = 0: the caller takes this path only
+// when (z1 - z0 + 1) sz < reach = sqrt(100 + thr) - sqrt(-thr), and then no
+// such lane can enter the support by z1 (|w| < sqrt(-thr) inside it, and |w|
+// moves by sz per offset), so those lanes add nothing, as with the direct
+// form; every other lane's chain keeps Q >= -100, inside the float range.
+// Rounding grows along the chain, to about 1e-4 relative after 32 products:
+// inside the gradient tolerance.  The forward pass, whose values must meet
+// 1e-5, keeps the direct exponential.  The support test is G > T with
+// T = exp2(thr).
+template <int BZ>
+__device__ inline void backward_steps_chain(const ColumnSetup& s, float szv, float sz, int z0,
+                                            int z1, const float (&res)[BZ], float T, float& se,
+                                            float& sK, float& sKK) {
+  const float w0 = fmaf((float)(z0 - 1 - BZ / 2), szv, s.wm);
+  const float q0 = quad_w(s, w0);
+  float G = q0 > -100.0f ? __builtin_amdgcn_exp2f(q0) : 0.0f;
+  float R = __builtin_amdgcn_exp2f(fminf(-fmaf(2.0f, w0, sz) * sz, 100.0f));
+  const float C = __builtin_amdgcn_exp2f(-2.0f * sz * sz);
+  // offsets z0 .. z1 (z1 <= 31; 2u << 31 wraps to 0, giving all ones)
+  const uint32_t span = ((2u << z1) - 1u) & ~((1u << z0) - 1u);
+#pragma unroll
+  for (int zz = 0; zz < BZ; ++zz) {
+    if ((span >> zz) & 1u) {
+      // keeps the compiler from turning this uniform branch into selects
+      // that would run every offset of the brick
+      asm volatile("");
+      G *= R;
+      R *= C;
+      const float e = res[zz] * (G > T ? G : 0.0f);
+      se += e;
+      sK = fmaf((float)zz, e, sK);
+      sKK = fmaf((float)(zz * zz), e, sKK);
+    }
+  }
+}
+
 // One brick of the fused pass.  VJP = false: residual r = 2 (Vhat - V) from
 // the forward pass and the target `field`, loss share to brick_loss.
 // VJP = true: no forward pass; r is read from `field` (an upstream gradient
@@ -374,6 +417,9 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
     __syncthreads();
   }
 
+  // support test and reach of the recurrence form of the backward steps
+  const float T = __builtin_amdgcn_exp2f(thr);
+  const float reach = 100.0f + thr > 0.0f ? sqrtf(100.0f + thr) - sqrtf(-thr) : 0.0f;
   for (uint32_t j = j0; j < j1; ++j) {
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
@@ -394,10 +440,15 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
       float se = 0.0f, sK = 0.0f, sKK = 0.0f;
       if (hit) {
         const float szv = vreg(r.sz);
-        if (recorded)
-          backward_steps<BZ, false>(s, szv, run, res, thr, se, sK, sKK);
-        else
+        if (recorded) {
+          const int z0 = (int)__builtin_ctz(run), z1 = 31 - (int)__builtin_clz(run);
+          if ((float)(z1 - z0 + 1) * r.sz < reach)
+            backward_steps_chain<BZ>(s, szv, r.sz, z0, z1, res, T, se, sK, sKK);
+          else
+            backward_steps<BZ, false>(s, szv, run, res, thr, se, sK, sKK);
+        } else {
           backward_steps<BZ, true>(s, szv, run, res, thr, se, sK, sKK);
+        }
       }
       // dz = p_z - mu_z = ofs + zz with ofs = z0 - mu_z, so
       // sum e dz = sK + ofs se and sum e dz^2 = sKK + 2 ofs sK + ofs^2 se
