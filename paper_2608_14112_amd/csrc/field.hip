@@ -154,7 +154,9 @@ __device__ inline bool column_hit(const ColumnSetup& s, float sz, uint64_t cols,
   if (s.zmask == 0u) return false;
   const float wa = fmaf((float)(s.za - BZ / 2), sz, s.wm);
   const float wb = fmaf((float)(s.zb - BZ / 2), sz, s.wm);
-  const float wn = wa > 0.f ? wa : (wb < 0.f ? wb : 0.f);
+  // za <= zb and sz > 0 give wa <= wb, so the median of (wa, wb, 0) is 0
+  // clamped to [wa, wb]: the w of the segment point nearest the vertex
+  const float wn = __builtin_amdgcn_fmed3f(wa, wb, 0.0f);
   return (__builtin_amdgcn_ballot_w64(fmaf(-wn, wn, s.qxy) > thr) & cols) != 0ull;
 }
 
