@@ -512,6 +512,9 @@ def main():
         "work": {"pairs_in_support": pairs, "candidate_evals": cand,
                  "lane_efficiency": pairs / cand if cand else None,
                  "overlaps": st["n_overlaps"], "bricks": st["n_bricks"]},
+        "memory_gb": {"workspace": st["workspace_bytes"] / 1e9,
+                      "params": P.n * (4 * 11 * 4 + 64 + 16 * 4 + 2 * 4) / 1e9,
+                      "field": float(field.numel()) * 4 / 1e9},
         "quality": {"mse_last": mse, "psnr_last_db": 10 * math.log10(1.0 / mse),
                     "loss_first": float(losses[0]), "loss_last": float(losses[-1])},
         "allocation": {"seconds": t_alloc, **{k: v for k, v in info.items()}},

@@ -108,6 +108,12 @@ typedef struct gve_stats {
   double ms_bin;          /* prep + scan + emit + sort + ranges */
   double ms_fused;        /* fused forward + squared error + backward kernel */
   double ms_update;       /* loss reduction + chain rule + Adam */
+  /* Device scratch the context holds (pair lists, sort buffers, partials,
+   * allocation and warm-start work arrays); it grows on demand and is freed
+   * by gve_destroy.  Parameter sets are counted separately by the caller
+   * (gve_params: 4 [11][n] arrays + a 64-byte record, 16 accumulators and
+   * two counts per primitive). */
+  int64_t workspace_bytes;
 } gve_stats;
 
 typedef struct gve_ctx gve_ctx;

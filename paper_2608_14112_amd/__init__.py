@@ -83,7 +83,8 @@ class StatsC(ctypes.Structure):
                 ("n_overlaps", ctypes.c_int64), ("n_clamped", ctypes.c_int64),
                 ("iterations", ctypes.c_int64), ("last_loss", ctypes.c_double),
                 ("timed_iterations", ctypes.c_int64), ("ms_bin", ctypes.c_double),
-                ("ms_fused", ctypes.c_double), ("ms_update", ctypes.c_double)]
+                ("ms_fused", ctypes.c_double), ("ms_update", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_int64)]
 
 
 class AllocInfoC(ctypes.Structure):

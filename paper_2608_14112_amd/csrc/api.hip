@@ -1077,6 +1077,21 @@ gve_status gve_allocate(gve_ctx* ctx, const float* d_field, gve_grid g, int64_t 
 gve_status gve_get_stats(const gve_ctx* ctx, gve_stats* out) {
   if (!ctx || !out) return GVE_ERR_INVALID_ARGUMENT;
   *out = ctx->stats;
+  const gve::Workspace& w = ctx->ws;
+  const gve::Scratch* all[] = {&w.keys[0], &w.keys[1], &w.vals[0], &w.vals[1], &w.brick_start,
+                               &w.brick_loss, &w.scan_tmp, &w.box_off, &w.sort_hist, &w.dloss,
+                               &w.clamp_count, &w.grad_tmp, &w.alloc, &w.voxf, &w.partials,
+                               &w.mlp, &w.sat, &w.feat, &w.theta_base, &w.items,
+                               &w.order_keys[0], &w.order_keys[1], &w.order_vals[0],
+                               &w.order_vals[1], &w.queue, &w.p_cls, &w.p_pts, &w.p_acc,
+                               &w.p_coef, &w.p_keys[0], &w.p_keys[1], &w.p_idx[0], &w.p_idx[1],
+                               &w.p_start, &w.p_loss};
+  static_assert(sizeof(all) / sizeof(all[0]) * sizeof(gve::Scratch) + sizeof(void*) ==
+                    sizeof(gve::Workspace),
+                "every scratch buffer of the workspace is counted");
+  int64_t bytes = 0;
+  for (const gve::Scratch* s : all) bytes += s->ptr ? (int64_t)s->bytes : 0;
+  out->workspace_bytes = bytes;
   return GVE_OK;
 }
 

@@ -165,6 +165,30 @@ __device__ inline bool column_hit(const ColumnSetup& s, float sz, uint64_t cols,
 // (0: the pair misses the brick), so the backward pass visits only those.
 constexpr uint32_t kStepCap = 1024;
 
+// Forward steps of one pair: w, Q and exp2 at every offset of the box's
+// z-range (after the compare, offsets where no lane is inside the support are
+// skipped).  Returns the mask of active offsets.  (The product form the
+// backward pass uses, restarted exactly every eight offsets to hold the
+// values' 1e-5, measured slower here: the extra uniform branches cost more
+// than the exponentials they save.)
+template <int BZ>
+__device__ inline uint32_t forward_steps(const ColumnSetup& s, float szv, float c, float thr,
+                                         float (&acc)[BZ]) {
+  uint32_t active = 0u;
+#pragma unroll
+  for (int zz = 0; zz < BZ; ++zz) {
+    if ((s.zmask >> zz) & 1u) {
+      const float q = quad_w(s, w_at<BZ>(s, szv, zz));
+      if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
+        active |= 1u << zz;
+        const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
+        acc[zz] = fmaf(c, G, acc[zz]);
+      }
+    }
+  }
+  return active;
+}
+
 template <int BZ>
 __device__ inline void accumulate_brick(const Record* __restrict__ rec,
                                         const uint32_t* __restrict__ pair_gid, uint32_t j0,
@@ -178,17 +202,7 @@ __device__ inline void accumulate_brick(const Record* __restrict__ rec,
     const float szv = vreg(r.sz);
     uint32_t active = 0u;
     if (column_hit<BZ>(s, szv, cols, thr)) {
-#pragma unroll
-      for (int zz = 0; zz < BZ; ++zz) {
-        if ((s.zmask >> zz) & 1u) {
-          const float q = quad_w(s, w_at<BZ>(s, szv, zz));
-          if (__builtin_amdgcn_ballot_w64(q > thr) != 0ull) {
-            active |= 1u << zz;
-            const float G = (q > thr) ? __builtin_amdgcn_exp2f(q) : 0.0f;
-            acc[zz] = fmaf(r.c, G, acc[zz]);
-          }
-        }
-      }
+      active = forward_steps<BZ>(s, szv, r.c, thr, acc);
     }
     if (steps && j - j0 < kStepCap && (threadIdx.x & 63) == 0) steps[j - j0] = active;
   }

@@ -64,6 +64,8 @@ def test_evaluate_matches_oracle(k, brick, case):
     V, A, br = F.evaluate_windowed(params, grid, k, band=BAND)
     check_field(got, V, A, br)
     assert st["n_primitives"] == n and st["n_overlaps"] > 0
+    # pair lists and sort buffers at least
+    assert st["workspace_bytes"] >= 4 * 4 * st["n_overlaps"]
 
 
 def test_evaluate_tiny_workload_size():
@@ -206,6 +208,32 @@ def test_loss_grad_matches_oracle(brick, k, deterministic):
     Lr, gr = F.loss_grad(params, field.astype(np.float64), grid, k)
     assert abs(L - Lr) <= 1e-5 * Lr
     slack, _ = F.boundary_slack(params, field, grid, k, BAND)
+    check_grad(grad, gr, slack=slack)
+
+
+@pytest.mark.parametrize("kind", ["wide", "thin"])
+def test_loss_grad_both_backward_forms(kind):
+    """The backward pass evaluates G along each column by a product recurrence
+    when a pair's recorded span times s_z is short enough, else directly.
+    Wide primitives (sigma 2.5-5, s_z about 0.2) take the recurrence; primitives
+    thin in one axis (0.35-0.6, rotated, s_z up to about 2.4) take the direct form
+    for most pairs.  Both against the oracle, atomic sums, 8x8x32 bricks."""
+    g, torch = _lib()
+    grid = F.Grid(40, 36, 70, 2, 0, -5)
+    rng = np.random.default_rng(31 if kind == "wide" else 32)
+    n = 50
+    p = S.random_params(n, (40, 36, 70), seed=33, scale_range=(2.5, 5.0), unit_quat=False)
+    if kind == "thin":
+        p[9] = np.log(rng.uniform(0.35, 0.6, n))
+    p[0] += grid.x0
+    p[1] += grid.y0
+    p[2] += grid.z0
+    p = p.astype(np.float32).astype(np.float64)
+    field = rng.uniform(-0.2, 1.0, size=grid.shape).astype(np.float32)
+    L, grad = _loss_grad_gpu(g, torch, p, field, grid, 3.0, (8, 32), deterministic=False)
+    Lr, gr = F.loss_grad(p, field.astype(np.float64), grid, 3.0)
+    assert abs(L - Lr) <= 1e-5 * Lr
+    slack, _ = F.boundary_slack(p, field, grid, 3.0, BAND)
     check_grad(grad, gr, slack=slack)
 
 
