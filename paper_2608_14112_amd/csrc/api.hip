@@ -148,7 +148,8 @@ struct Binned {
   const gve::ItemDesc* items = nullptr;  // device
   int nitems = 0;
   gve::Schedule sched;
-  const uint32_t* gid = nullptr;
+  const uint32_t* gid = nullptr;   // primitive of each sorted pair
+  const uint32_t* slot = nullptr;  // its emission index (deterministic sums), else null
   const uint32_t* start = nullptr;
   int64_t npairs = 0;
 };
@@ -203,11 +204,12 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   TRY_HIP(ctx, gve::fill_u64(total, 1, s));
   TRY_HIP(ctx, gve::launch_prep(p->theta, n, items, vol.n, ctx->opt.k, bg, p->rec, p->count,
                                 total, s));
-  // Culling drops bricks a separating plane parts from the support.  The
-  // deterministic partials address a pair by its brick's rank in the whole
-  // box, so they keep every box brick.  The box total bounds the kept total,
-  // so below the limit every 32-bit scan is exact.
-  const bool cull = ctx->opt.deterministic == 0;
+  // Culling drops bricks a separating plane parts from the support.  The box
+  // total bounds the kept total, so below the limit every 32-bit scan is
+  // exact.  Deterministic sums address a pair's partials by its emission
+  // index, which the sort carries as the value.
+  const bool cull = true;
+  const bool slots = ctx->opt.deterministic != 0;
   unsigned char* hp = static_cast<unsigned char*>(ws.h_pinned);
   const uint32_t* box_off = nullptr;
   uint32_t* kept = nullptr;
@@ -248,8 +250,13 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   TRY(ensure(ctx, ws.brick_start, sizeof(uint32_t) * (size_t)(bg.nbricks + 1)));
   uint32_t* keys[2] = {static_cast<uint32_t*>(ws.keys[0].ptr), static_cast<uint32_t*>(ws.keys[1].ptr)};
   uint32_t* vals[2] = {static_cast<uint32_t*>(ws.vals[0].ptr), static_cast<uint32_t*>(ws.vals[1].ptr)};
-  TRY_HIP(ctx, gve::launch_emit(p->rec, p->offset, n, items, vol.n, bg, box_off, kept, keys[0],
-                                vals[0], s));
+  uint32_t* owner = nullptr;
+  if (slots) {
+    TRY(ensure(ctx, ws.owner, pair_bytes));
+    TRY(ensure(ctx, ws.slot_gid, pair_bytes));
+    owner = static_cast<uint32_t*>(ws.owner.ptr);
+  }
+  TRY_HIP(ctx, gve::launch_emit(p->offset, n, box_off, kept, keys[0], vals[0], owner, s));
   int which = 0;
   TRY_HIP(ctx, gve::radix_sort_pairs(keys, vals, (int64_t)T, bits_for(bg.nbricks), ws.sort_hist.ptr,
                                      &which, s));
@@ -281,6 +288,13 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   out->items = items;
   out->nitems = vol.n;
   out->gid = vals[which];
+  out->slot = nullptr;
+  if (slots) {
+    uint32_t* g = static_cast<uint32_t*>(ws.slot_gid.ptr);
+    TRY_HIP(ctx, gve::launch_gather_owner(owner, vals[which], (int64_t)T, g, s));
+    out->slot = vals[which];
+    out->gid = g;
+  }
   out->start = start;
   out->npairs = (int64_t)T;
   ctx->stats.n_primitives = n;
@@ -300,7 +314,7 @@ gve_status fused(gve_ctx* ctx, const gve_params* p, const Binned& bn, const floa
   if (bn.sched.kind == gve::kSchedQueue)
     TRY_HIP(ctx, gve::fill_u32(bn.sched.counter, 1, ctx->stream));
   TRY_HIP(ctx, gve::launch_fused(p->rec, bn.gid, bn.start, bn.items, bn.nitems, bn.bg,
-                                 ctx->opt.k, d_field, p->acc, p->n, part, p->offset, brick_loss,
+                                 ctx->opt.k, d_field, p->acc, p->n, part, bn.slot, brick_loss,
                                  bn.sched, ctx->stream, vjp));
   return GVE_OK;
 }
@@ -1079,7 +1093,8 @@ gve_status gve_get_stats(const gve_ctx* ctx, gve_stats* out) {
   *out = ctx->stats;
   const gve::Workspace& w = ctx->ws;
   const gve::Scratch* all[] = {&w.keys[0], &w.keys[1], &w.vals[0], &w.vals[1], &w.brick_start,
-                               &w.brick_loss, &w.scan_tmp, &w.box_off, &w.sort_hist, &w.dloss,
+                               &w.brick_loss, &w.scan_tmp, &w.box_off, &w.owner, &w.slot_gid,
+                               &w.sort_hist, &w.dloss,
                                &w.clamp_count, &w.grad_tmp, &w.alloc, &w.voxf, &w.partials,
                                &w.mlp, &w.sat, &w.feat, &w.theta_base, &w.items,
                                &w.order_keys[0], &w.order_keys[1], &w.order_vals[0],

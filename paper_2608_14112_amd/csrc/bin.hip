@@ -7,9 +7,9 @@
 //            bounding box
 //            (|d_j| < k sqrt(Sigma_jj) bounds the ellipsoid m^2 < k^2) clipped
 //            to the grid, and the number of bricks that box touches;
-//   cull   : (atomic gradient sums only) per primitive, the bricks of its box
-//            that a separating plane does not part from its support, their
-//            keys and their count (which replaces the box's brick count);
+//   cull   : per primitive, the bricks of its box that a separating plane
+//            does not part from its support, their keys and their count
+//            (which replaces the box's brick count);
 //   emit   : the (brick, primitive) pairs at the scanned offsets;
 //   ranges : first pair of every brick in the brick-sorted list (binary search).
 #include "common.h"
@@ -271,38 +271,18 @@ __global__ __launch_bounds__(kThreads) void k_cull(const Record* __restrict__ re
   if (live && total > 0 && sub == 0) count[i] = nkept;
 }
 
-// Pairs at the scanned offsets, every brick of the box in (z, y, x) order:
-// one wave per primitive, lane j writes pairs j, j + 64, ... (consecutive
-// lanes at consecutive addresses).
-__global__ __launch_bounds__(kThreads) void k_emit(const Record* __restrict__ rec,
-                                                   const uint32_t* __restrict__ offset, int64_t n,
-                                                   const ItemDesc* __restrict__ items, int nitems,
-                                                   BrickGeom bg, uint32_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals) {
-  const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (i >= n) return;
-  const uint32_t o = offset[i];
-  const uint32_t cnt = offset[i + 1] - o;
-  if (cnt == 0) return;
-  const ItemDesc& it = items[item_of_prim(items, nitems, (uint32_t)i)];
-  const BoxBricks bb = box_bricks(rec[i], bg);
-  for (uint32_t j = (uint32_t)lane; j < cnt; j += 64) {
-    uint32_t bx, by, bz;
-    bb.at(j, bx, by, bz);
-    keys[o + j] = brick_key(it, bx, by, bz);
-    vals[o + j] = (uint32_t)i;
-  }
-}
-
 // Pairs at the scanned offsets from the keys k_cull kept: sixteen lanes per
-// primitive.
+// primitive.  The value of a pair is its primitive id, or, with `owner`
+// (deterministic gradient sums), its emission index p, with owner[p] = the
+// primitive id: the sorted emission indices then name each pair's own
+// partials slot (a primitive's slots are its contiguous emission range).
 __global__ __launch_bounds__(kThreads) void k_emit_kept(const uint32_t* __restrict__ offset,
                                                         int64_t n,
                                                         const uint32_t* __restrict__ box_off,
                                                         const uint32_t* __restrict__ kept,
                                                         uint32_t* __restrict__ keys,
-                                                        uint32_t* __restrict__ vals) {
+                                                        uint32_t* __restrict__ vals,
+                                                        uint32_t* __restrict__ owner) {
   const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kGroup;
   const uint32_t sub = threadIdx.x & (kGroup - 1);
   if (i >= n) return;
@@ -311,8 +291,22 @@ __global__ __launch_bounds__(kThreads) void k_emit_kept(const uint32_t* __restri
   const uint32_t src = box_off[i];
   for (uint32_t j = sub; j < cnt; j += kGroup) {
     keys[o + j] = kept[src + j];
-    vals[o + j] = (uint32_t)i;
+    if (owner) {
+      vals[o + j] = o + j;
+      owner[o + j] = (uint32_t)i;
+    } else {
+      vals[o + j] = (uint32_t)i;
+    }
   }
+}
+
+// gid[j] = owner[slot[j]]: the primitive of each sorted pair, from its
+// emission index.
+__global__ __launch_bounds__(kThreads) void k_gather_owner(const uint32_t* __restrict__ owner,
+                                                           const uint32_t* __restrict__ slot,
+                                                           int64_t n, uint32_t* __restrict__ gid) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j < n) gid[j] = owner[slot[j]];
 }
 
 // brick_start[b] = first index whose key >= b, for b in [0, nbricks].
@@ -383,18 +377,19 @@ hipError_t launch_cull(const Record* rec, int64_t n, const uint32_t* box_off, co
   return hipGetLastError();
 }
 
-hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, const ItemDesc* items,
-                       int nitems, BrickGeom bg, const uint32_t* box_off, const uint32_t* kept,
-                       uint32_t* keys, uint32_t* vals, hipStream_t s) {
-  if (kept) {
-    const unsigned blocks = (unsigned)((n * kGroup + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_emit_kept, dim3(blocks), dim3(kThreads), 0, s, offset, n, box_off, kept,
-                       keys, vals);
-  } else {
-    const unsigned blocks = (unsigned)((n * 64 + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, rec, offset, n, items, nitems,
-                       bg, keys, vals);
-  }
+hipError_t launch_emit(const uint32_t* offset, int64_t n, const uint32_t* box_off,
+                       const uint32_t* kept, uint32_t* keys, uint32_t* vals, uint32_t* owner,
+                       hipStream_t s) {
+  const unsigned blocks = (unsigned)((n * kGroup + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_emit_kept, dim3(blocks), dim3(kThreads), 0, s, offset, n, box_off, kept,
+                     keys, vals, owner);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_owner(const uint32_t* owner, const uint32_t* slot, int64_t n,
+                               uint32_t* gid, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_gather_owner, dim3(blocks), dim3(kThreads), 0, s, owner, slot, n, gid);
   return hipGetLastError();
 }
 

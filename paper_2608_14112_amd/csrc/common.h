@@ -67,6 +67,8 @@ struct Workspace {
   Scratch brick_loss;            // float  [n_bricks]
   Scratch scan_tmp;              // scan partials
   Scratch box_off;               // uint32 [n + 1] scan of box brick counts (culling)
+  Scratch owner, slot_gid;       // uint32 [T] primitive of each emission index / sorted pair
+                                 // (deterministic sums)
   Scratch sort_hist;             // radix sort histograms
   Scratch dloss;                 // double [4]
   Scratch clamp_count;           // unsigned long long
@@ -173,11 +175,14 @@ hipError_t launch_prep(const float* theta, int64_t n, const ItemDesc* items, int
 hipError_t launch_cull(const Record* rec, int64_t n, const uint32_t* box_off, const ItemDesc* items,
                        int nitems, BrickGeom bg, float k, uint32_t* kept, uint32_t* count,
                        hipStream_t s);
-// Pairs at the scanned offsets: every box brick (kept == nullptr) or the
-// kept keys of launch_cull.
-hipError_t launch_emit(const Record* rec, const uint32_t* offset, int64_t n, const ItemDesc* items,
-                       int nitems, BrickGeom bg, const uint32_t* box_off, const uint32_t* kept,
-                       uint32_t* keys, uint32_t* vals, hipStream_t s);
+// Pairs at the scanned offsets from the kept keys of launch_cull; values are
+// primitive ids, or with `owner` emission indices p (owner[p] = primitive).
+hipError_t launch_emit(const uint32_t* offset, int64_t n, const uint32_t* box_off,
+                       const uint32_t* kept, uint32_t* keys, uint32_t* vals, uint32_t* owner,
+                       hipStream_t s);
+// gid[j] = owner[slot[j]] for j < n.
+hipError_t launch_gather_owner(const uint32_t* owner, const uint32_t* slot, int64_t n,
+                               uint32_t* gid, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t npairs, int64_t nbricks,
                          uint32_t* brick_start, hipStream_t s);
 // Heaviest-first brick order for kSchedQueue: keys = leading zeros of the
@@ -193,12 +198,13 @@ hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid,
                           const uint32_t* brick_start, const ItemDesc* items, int nitems,
                           BrickGeom bg, float k, float* out, const Schedule& sc, hipStream_t s);
 // part == nullptr: float atomics into acc [n][kAccStride].  Otherwise each (primitive,
-// brick) pair stores its ten sums to part[(offset[gid] + rank) * 10 + slot],
-// rank = the brick's position in the primitive's emitted brick range.
+// brick) pair stores its ten sums to part[pslot[j] * 10 + a], pslot[j] = the
+// emission index of sorted pair j (a primitive's emission range is
+// [offset[i], offset[i + 1])), which the update sums per primitive in order.
 hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid,
                         const uint32_t* brick_start, const ItemDesc* items, int nitems,
                         BrickGeom bg, float k, const float* field, float* acc, int64_t n,
-                        float* part, const uint32_t* offset, float* brick_loss,
+                        float* part, const uint32_t* pslot, float* brick_loss,
                         const Schedule& sc, hipStream_t s, bool vjp = false);
 hipError_t launch_count(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
                         const ItemDesc* items, int nitems, BrickGeom bg, float k,

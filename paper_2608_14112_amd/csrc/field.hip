@@ -292,20 +292,6 @@ __global__ __launch_bounds__(BXY* BXY) void k_forward(const Record* __restrict__
   forward_brick<BXY, BZ>(rec, pair_gid, brick_start, items, nitems, b, thr, out);
 }
 
-// Slot of the (primitive, brick) pair in the partials array: the primitive's
-// first pair plus the brick's rank in its emitted brick range (z, y, x order).
-template <int BXY, int BZ>
-__device__ inline uint32_t pair_slot(const Record& r, const uint32_t* __restrict__ offset,
-                                     uint32_t gid, int bx, int by, int bz) {
-  // box bounds are clamped to the volume, so non-negative: unsigned division
-  const uint32_t lx = (uint32_t)r.lo[0] / BXY, ly = (uint32_t)r.lo[1] / BXY,
-                 lz = (uint32_t)r.lo[2] / BZ;
-  const uint32_t nbx_g = (uint32_t)r.hi[0] / BXY - lx + 1;
-  const uint32_t nby_g = (uint32_t)r.hi[1] / BXY - ly + 1;
-  return offset[gid] + (((uint32_t)bz - lz) * nby_g + ((uint32_t)by - ly)) * nbx_g +
-         ((uint32_t)bx - lx);
-}
-
 // The backward steps of one pair over the brick offsets in `run`: moments
 // of e = r G over zz.  CHECK skips offsets where no lane is inside the
 // support; without it every offset in `run` must hold some lane inside (the
@@ -386,7 +372,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
                                    const ItemDesc* __restrict__ items, int nitems, uint32_t b,
                                    float thr, const float* __restrict__ field,
                                    float* __restrict__ gacc, int64_t n, float* __restrict__ part,
-                                   const uint32_t* __restrict__ offset,
+                                   const uint32_t* __restrict__ pslot,
                                    float* __restrict__ brick_loss,
                                    float (*red)[10], uint32_t* __restrict__ steps) {
   constexpr int kWaves = (BXY * BXY + 63) / 64;
@@ -447,7 +433,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
     if (kWaves == 1 && !hit) {
       // a pair whose support misses every column still owns a partials slot
       if (part && lane < 10)
-        part[(size_t)pair_slot<BXY, BZ>(r, offset, gid, st.bx, st.by, st.bz) * 10 + lane] = 0.0f;
+        part[(size_t)pslot[j] * 10 + lane] = 0.0f;
       continue;
     }
     float v[10];
@@ -489,7 +475,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
     wave_reduce10(v, o);
     if (kWaves == 1) {
       if (part) {
-        const uint32_t slot_base = pair_slot<BXY, BZ>(r, offset, gid, st.bx, st.by, st.bz);
+        const uint32_t slot_base = pslot[j];
         if ((lane & 15) == 0) {
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
@@ -517,8 +503,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
         float t = 0.0f;
         for (int w = 0; w < kWaves; ++w) t += red[w][threadIdx.x];
         if (part) {
-          part[(size_t)pair_slot<BXY, BZ>(r, offset, gid, st.bx, st.by, st.bz) * 10 +
-               threadIdx.x] = t;
+          part[(size_t)pslot[j] * 10 + threadIdx.x] = t;
         } else if (t != 0.0f) {
           unsafeAtomicAdd(&gacc[(int64_t)gid * kAccStride + threadIdx.x], t);
         }
@@ -538,14 +523,14 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
                                                 const float* __restrict__ field,
                                                 float* __restrict__ gacc, int64_t n,
                                                 float* __restrict__ part,
-                                                const uint32_t* __restrict__ offset,
+                                                const uint32_t* __restrict__ pslot,
                                                 float* __restrict__ brick_loss) {
   constexpr int kWaves = (BXY * BXY + 63) / 64;
   __shared__ float red[kWaves][10];
   __shared__ uint32_t steps[kWaves == 1 && !VJP ? kStepCap : 1];
   const uint32_t b = xcd ? xcd_brick(blockIdx.x, nbricks) : blockIdx.x;
   fused_brick<BXY, BZ, VJP>(rec, pair_gid, brick_start, items, nitems, b, thr, field, gacc, n,
-                            part, offset, brick_loss, red, steps);
+                            part, pslot, brick_loss, red, steps);
 }
 
 // Persistent: each workgroup takes queue positions from *counter until they
@@ -562,7 +547,7 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused_queue(const Record* __restri
                                                       const float* __restrict__ field,
                                                       float* __restrict__ gacc, int64_t n,
                                                       float* __restrict__ part,
-                                                      const uint32_t* __restrict__ offset,
+                                                      const uint32_t* __restrict__ pslot,
                                                       float* __restrict__ brick_loss) {
   constexpr int kWaves = (BXY * BXY + 63) / 64;
   __shared__ float red[kWaves][10];
@@ -575,7 +560,7 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused_queue(const Record* __restri
     __syncthreads();
     if (w >= nbricks) break;
     fused_brick<BXY, BZ, VJP>(rec, pair_gid, brick_start, items, nitems, order[w], thr, field,
-                              gacc, n, part, offset, brick_loss, red, steps);
+                              gacc, n, part, pslot, brick_loss, red, steps);
   }
 }
 
@@ -718,7 +703,7 @@ hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid, const uin
 hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid, const uint32_t* brick_start,
                         const ItemDesc* items, int nitems, BrickGeom bg, float k,
                         const float* field, float* acc, int64_t n, float* part,
-                        const uint32_t* offset, float* brick_loss, const Schedule& sc,
+                        const uint32_t* pslot, float* brick_loss, const Schedule& sc,
                         hipStream_t s, bool vjp) {
   const float thr = -kHalfLog2e * k * k;
   if (bg.nbricks <= 0) return hipSuccess;
@@ -735,18 +720,18 @@ hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid, const uint3
     if (queue && vjp)                                                                         \
       hipLaunchKernelGGL((k_fused_queue<XY, Z, true>), grid, dim3(XY * XY), 0, s, rec,          \
                          pair_gid, brick_start, items, nitems, nb, order, counter, thr, field,  \
-                         acc, n, part, offset, brick_loss);                                     \
+                         acc, n, part, pslot, brick_loss);                                     \
     else if (queue)                                                                           \
       hipLaunchKernelGGL((k_fused_queue<XY, Z, false>), grid, dim3(XY * XY), 0, s, rec,         \
                          pair_gid, brick_start, items, nitems, nb, order, counter, thr, field,  \
-                         acc, n, part, offset, brick_loss);                                     \
+                         acc, n, part, pslot, brick_loss);                                     \
     else if (vjp)                                                                             \
       hipLaunchKernelGGL((k_fused<XY, Z, true>), grid, dim3(XY * XY), 0, s, rec, pair_gid,      \
-                         brick_start, items, nitems, nb, xcd, thr, field, acc, n, part, offset, \
+                         brick_start, items, nitems, nb, xcd, thr, field, acc, n, part, pslot,  \
                          brick_loss);                                                           \
     else                                                                                      \
       hipLaunchKernelGGL((k_fused<XY, Z, false>), grid, dim3(XY * XY), 0, s, rec, pair_gid,     \
-                         brick_start, items, nitems, nb, xcd, thr, field, acc, n, part, offset, \
+                         brick_start, items, nitems, nb, xcd, thr, field, acc, n, part, pslot,  \
                          brick_loss);                                                           \
     return hipGetLastError();                                                                 \
   }

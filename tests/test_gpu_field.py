@@ -118,10 +118,9 @@ def _support_bricks(params, grid, k, bxy, bz):
 
 @pytest.mark.parametrize("brick", [(8, 32), (16, 16)])
 def test_brick_culling_keeps_every_brick_with_support(brick):
-    """Atomic-sum binning drops bricks a separating plane parts from the
-    support; the deterministic binning keeps the whole box.  The field is
-    bitwise the same, and the kept pairs lie between the bricks that hold
-    support and the bricks of the box."""
+    """Binning drops bricks a separating plane parts from the support, in
+    both gradient modes.  The field is bitwise the same in both, and the kept
+    pairs lie between the bricks that hold support and the bricks of the box."""
     g, torch = _lib()
     grid = F.Grid(48, 44, 70, 2, -1, 3)
     rng = np.random.default_rng(21)
@@ -142,10 +141,10 @@ def test_brick_culling_keeps_every_brick_with_support(brick):
         outs.append(out.cpu().numpy())
         pairs.append(ctx.stats()["n_overlaps"])
     assert np.array_equal(outs[0], outs[1])
+    assert pairs[0] == pairs[1]
     nsup, nbox = _support_bricks(p, grid, 3.0, bxy, bz)
-    print(f"support {nsup}, culled {pairs[0]}, box {pairs[1]} (oracle box {nbox})", flush=True)
-    assert nsup <= pairs[0] < pairs[1]
-    assert abs(pairs[1] - nbox) <= 0.01 * nbox
+    print(f"support {nsup}, kept {pairs[0]}, box {nbox}", flush=True)
+    assert nsup <= pairs[0] < 0.95 * nbox
     V, A, br = F.evaluate_windowed(p, grid, 3.0, band=BAND)
     check_field(outs[0], V, A, br)
 
