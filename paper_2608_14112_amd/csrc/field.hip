@@ -228,7 +228,17 @@ struct Site {
   int zrem;            // voxels of the volume from iz0 on (may exceed the brick)
   float px, py, pz0;   // lane column position (world), first z
   bool col_in;         // the column lies inside the volume
-  size_t base, plane;  // column's voxel at z = 0 in the concatenated buffers, z stride
+  size_t org;          // brick's corner voxel (x, y, iz0) in the concatenated buffers (uniform)
+  size_t plane;        // z stride
+  uint32_t lbytes;     // byte offset of the lane's column from the corner (lx + nx ly) * 4
+
+  // Address of the lane's voxel at brick offset zz: a uniform base plus a
+  // 32-bit lane offset, the form global loads and stores take directly.
+  template <typename T>
+  __device__ T* at(T* buf, int zz) const {
+    T* zb = buf + org + plane * (size_t)zz;
+    return (T*)((char*)zb + lbytes);
+  }
 };
 
 template <int BXY, int BZ>
@@ -249,7 +259,9 @@ __device__ inline Site site_of(const ItemDesc* __restrict__ items, int nitems, u
   s.pz0 = (float)(it.z0 + s.iz0);
   s.col_in = ix < it.nx && iy < it.ny;
   s.plane = (size_t)it.nx * (size_t)it.ny;
-  s.base = (size_t)it.vox + (size_t)ix + (size_t)it.nx * (size_t)iy;
+  s.org = (size_t)it.vox + (size_t)(s.bx * BXY) + (size_t)it.nx * (size_t)(s.by * BXY) +
+          s.plane * (size_t)s.iz0;
+  s.lbytes = 4u * ((threadIdx.x % BXY) + (uint32_t)it.nx * (threadIdx.x / BXY));
   return s;
 }
 
@@ -277,7 +289,7 @@ __device__ __attribute__((always_inline)) inline void forward_brick(const Record
   if (st.col_in) {
 #pragma unroll
     for (int zz = 0; zz < BZ; ++zz)
-      if (zz < st.zrem) out[st.base + st.plane * (size_t)(st.iz0 + zz)] = acc[zz];
+      if (zz < st.zrem) *st.at(out, zz) = acc[zz];
   }
 }
 
@@ -360,6 +372,37 @@ __device__ inline void backward_steps_chain(const ColumnSetup& s, float szv, flo
   }
 }
 
+// Target values of the lane's column at brick offsets z0 .. z0 + NZ - 1
+// (0 outside the volume), read as raw buffer loads: each z-plane's brick corner
+// is a uniform resource base and the lane's byte offset the one per-lane
+// operand, so the NZ loads share one offset register and are issued together
+// (one wait per chunk rather than per voxel).  A lane whose column lies outside
+// the volume passes an offset past the record count and reads 0.
+constexpr int kLoadZ = 8;
+// Fourth word of a gfx9-family buffer resource: 32-bit data format, no
+// swizzle, no index stride (the offset is a plain byte offset).
+constexpr int kBufferWord3 = 0x00020000;
+
+__device__ inline float plane_load(const float* __restrict__ buf, const Site& st, int zz,
+                                   uint32_t voff, int nrec) {
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(buf + st.org + st.plane * (size_t)zz), (short)0, nrec, kBufferWord3);
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0));
+}
+
+template <int NZ>
+__device__ inline void load_column_chunk(const float* __restrict__ field, const Site& st,
+                                         uint32_t voff, int nrec, int z0, float (&t)[NZ]) {
+  if (z0 + NZ <= st.zrem) {
+#pragma unroll
+    for (int u = 0; u < NZ; ++u) t[u] = plane_load(field, st, z0 + u, voff, nrec);
+  } else {
+#pragma unroll
+    for (int u = 0; u < NZ; ++u)
+      t[u] = z0 + u < st.zrem ? plane_load(field, st, z0 + u, voff, nrec) : 0.0f;
+  }
+}
+
 // One brick of the fused pass.  VJP = false: residual r = 2 (Vhat - V) from
 // the forward pass and the target `field`, loss share to brick_loss.
 // VJP = true: no forward pass; r is read from `field` (an upstream gradient
@@ -385,28 +428,50 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
   const bool col_in = st.col_in;
   const uint64_t cols = __builtin_amdgcn_ballot_w64(col_in);
   const uint32_t j0 = brick_start[b], j1 = brick_start[b + 1];
+  // target reads: lanes outside the volume read past the record count (0);
+  // an inside lane's offset is below one plane and below 2^29 bytes
+  static_assert(BZ % kLoadZ == 0, "brick depth must be a multiple of the load chunk");
+  const uint32_t voff = col_in ? st.lbytes : 0x80000000u;
+  const int nrec = (int)std::min(st.plane * 4, (size_t)0x7FFFFFFF);
 
   float res[BZ];
 #pragma unroll
   for (int zz = 0; zz < BZ; ++zz) res[zz] = 0.0f;
   if (VJP) {
 #pragma unroll
-    for (int zz = 0; zz < BZ; ++zz)
-      if (col_in && zz < st.zrem) res[zz] = field[st.base + st.plane * (size_t)(iz0 + zz)];
+    for (int z0 = 0; z0 < BZ; z0 += kLoadZ) {
+      float t[kLoadZ];
+      load_column_chunk<kLoadZ>(field, st, voff, nrec, z0, t);
+#pragma unroll
+      for (int u = 0; u < kLoadZ; ++u) res[z0 + u] = t[u];
+      asm volatile("" ::: "memory");
+    }
   } else {
     accumulate_brick<BZ>(rec, pair_gid, j0, j1, px, py, pz0, iz0, cols, thr, res,
                          kWaves == 1 ? steps : nullptr);
     // residual and this brick's share of the loss
     float lsum = 0.0f;
 #pragma unroll
-    for (int zz = 0; zz < BZ; ++zz) {
-      float r = 0.0f;
-      if (col_in && zz < st.zrem) {
-        const float d = res[zz] - field[st.base + st.plane * (size_t)(iz0 + zz)];
-        lsum = fmaf(d, d, lsum);
-        r = 2.0f * d;
+    for (int z0 = 0; z0 < BZ; z0 += kLoadZ) {
+      float t[kLoadZ];
+      load_column_chunk<kLoadZ>(field, st, voff, nrec, z0, t);
+#pragma unroll
+      for (int u = 0; u < kLoadZ; ++u) {
+        const int zz = z0 + u;
+        float r = 0.0f;
+        if (col_in && zz < st.zrem) {
+          const float d = res[zz] - t[u];
+          lsum = fmaf(d, d, lsum);
+          r = 2.0f * d;
+        }
+        res[zz] = r;
       }
-      res[zz] = r;
+      // one chunk of loads in flight at a time, each consumed before the
+      // next is issued (the compiler would otherwise issue all of them first
+      // and hold BZ more registers)
+#pragma unroll
+      for (int u = 0; u < kLoadZ; ++u) asm volatile("" ::"v"(res[z0 + u]));
+      asm volatile("" : "+v"(lsum)::"memory");
     }
     lsum = wave_sum(lsum);
     if (lane == 0) red[wave][0] = lsum;
