@@ -177,6 +177,31 @@ gve_status gve_evaluate(gve_ctx* ctx, const gve_params* p, gve_grid g, float* d_
 gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field, gve_grid g,
                          float* d_grad, double* h_loss);
 
+/*
+ * Dense reference evaluation (Sec. III-G: the cost of testing every
+ * primitive-sample pair is what binning removes).  Same result as
+ * gve_evaluate, Vhat on every voxel of g into d_out [nz][ny][nx] (caller-owned
+ * device float32), but every (primitive, voxel) pair is evaluated and tested
+ * against m^2 < k^2, with no bricks; the time grows as voxels x primitives, so
+ * it is meant for small grids (a baseline for the binned path).  Per voxel the
+ * sum runs in increasing primitive index.  Errors: INVALID_ARGUMENT for null
+ * pointers or bad grids; UNSUPPORTED beyond 65535 * 64 primitives; DEVICE for
+ * HIP failures.  Asynchronous.
+ */
+gve_status gve_dense_evaluate(gve_ctx* ctx, const gve_params* p, gve_grid g, float* d_out);
+
+/*
+ * Dense reference loss and gradient: gve_loss_grad's L and dL/dtheta
+ * ([11][n] float32 into d_grad, caller-owned device memory, may be NULL) with
+ * every (primitive, voxel) pair evaluated.  The gradient sums use float
+ * atomics (last bits depend on execution order, whatever
+ * options.deterministic says).  The context keeps an [nz][ny][nx] float32
+ * residual buffer.  L into *h_loss if not NULL (synchronises).  Errors as
+ * gve_dense_evaluate, NUMERIC for a non-finite loss.
+ */
+gve_status gve_dense_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field,
+                               gve_grid g, float* d_grad, double* h_loss);
+
 /* Vector-Jacobian product of the truncated field: d_grad [11][n] (device,
  * caller-owned) = sum_p u(p) dVhat(p)/dtheta for an upstream gradient
  * u = d_upstream [nz][ny][nx] (device float32), the truncation indicator held

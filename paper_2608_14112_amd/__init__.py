@@ -115,6 +115,8 @@ _SIGS = {
     "gve_params_set_step": [_vp, _i64],
     "gve_evaluate": [_vp, _vp, GridC, _vp],
     "gve_loss_grad": [_vp, _vp, _vp, GridC, _vp, ctypes.POINTER(ctypes.c_double)],
+    "gve_dense_evaluate": [_vp, _vp, GridC, _vp],
+    "gve_dense_loss_grad": [_vp, _vp, _vp, GridC, _vp, ctypes.POINTER(ctypes.c_double)],
     "gve_adam_step": [_vp, _vp, _vp],
     "gve_vjp": [_vp, _vp, _vp, GridC, _vp],
     "gve_export": [_vp, _vp, GridC, ctypes.c_float, ctypes.c_float, _vp, ctypes.c_size_t],
@@ -379,6 +381,33 @@ def loss_grad(ctx: Context, params: Params, field, grid: Grid, grad=None, want_l
     L = ctypes.c_double(0.0)
     _check(_lib.gve_loss_grad(ctx.handle, params.handle, _ptr(field, torch.float32, n), grid.c(),
                               gp, ctypes.byref(L) if want_loss else None), ctx.handle)
+    return L.value if want_loss else None
+
+
+def dense_evaluate(ctx: Context, params: Params, grid: Grid, out=None):
+    """gve_dense_evaluate: the same truncated field with every (primitive, voxel) pair
+    evaluated (no binning), into ``out`` (float32 cuda [nz, ny, nx]; allocated when not
+    given)."""
+    import torch
+
+    if out is None:
+        out = torch.empty(grid.shape, device="cuda", dtype=torch.float32)
+    _check(_lib.gve_dense_evaluate(ctx.handle, params.handle, grid.c(),
+                                   _ptr(out, torch.float32, grid.nx * grid.ny * grid.nz)),
+           ctx.handle)
+    return out
+
+
+def dense_loss_grad(ctx: Context, params: Params, field, grid: Grid, grad=None, want_loss=True):
+    """gve_dense_loss_grad: loss_grad with every (primitive, voxel) pair evaluated."""
+    import torch
+
+    n = grid.nx * grid.ny * grid.nz
+    gp = _ptr(grad, torch.float32, NPARAM * params.n) if grad is not None else None
+    L = ctypes.c_double(0.0)
+    _check(_lib.gve_dense_loss_grad(ctx.handle, params.handle, _ptr(field, torch.float32, n),
+                                    grid.c(), gp, ctypes.byref(L) if want_loss else None),
+           ctx.handle)
     return L.value if want_loss else None
 
 

@@ -303,6 +303,30 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   return GVE_OK;
 }
 
+// Records of every primitive (the prep kernel alone, no pair list): what the
+// dense reference path reads.
+gve_status prep_only(gve_ctx* ctx, const gve_params* p, const gve_grid& g) {
+  const int64_t off[2] = {0, p->n};
+  int64_t nbricks = 0;
+  TRY(upload_items(ctx, Vol{&g, off, 1}, brick_xy(ctx), brick_z(ctx), &nbricks));
+  TRY(ensure_dloss(ctx));
+  unsigned long long* total = reinterpret_cast<unsigned long long*>(ctx->ws.dloss.ptr) + 1;
+  gve::BrickGeom bg;
+  bg.Bxy = brick_xy(ctx);
+  bg.Bz = brick_z(ctx);
+  bg.nbricks = nbricks;
+  TRY_HIP(ctx, gve::launch_prep(p->theta, p->n, static_cast<const gve::ItemDesc*>(ctx->ws.items.ptr),
+                                1, ctx->opt.k, bg, p->rec, p->count, total, ctx->stream));
+  return GVE_OK;
+}
+
+// The dense path launches one workgroup row per 64 primitives.
+gve_status check_dense(const gve_ctx* ctx, const gve_params* p) {
+  if ((p->n + 63) / 64 > 65535)
+    return fail(ctx, GVE_ERR_UNSUPPORTED, "dense path: at most 65535 * 64 primitives");
+  return GVE_OK;
+}
+
 gve_status bin(gve_ctx* ctx, const gve_params* p, const gve_grid& g, Binned* out) {
   const int64_t off[2] = {0, p->n};
   return bin_vol(ctx, p, Vol{&g, off, 1}, out);
@@ -635,6 +659,54 @@ gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field
     TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
     *h_loss = *static_cast<double*>(ctx->ws.h_pinned);
     ctx->stats.last_loss = *h_loss;
+    if (!std::isfinite(*h_loss)) return fail(ctx, GVE_ERR_NUMERIC, "loss is not finite");
+  }
+  return GVE_OK;
+}
+
+gve_status gve_dense_evaluate(gve_ctx* ctx, const gve_params* p, gve_grid g, float* d_out) {
+  TRY(check_ctx_params(ctx, p));
+  if (!d_out) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "d_out is NULL");
+  TRY(validate_grid(ctx, g));
+  TRY(check_dense(ctx, p));
+  TRY(set_device(ctx));
+  TRY(prep_only(ctx, p, g));
+  TRY_HIP(ctx, gve::launch_dense_forward(p->rec, p->n, g, ctx->opt.k, nullptr, d_out, nullptr,
+                                         ctx->stream));
+  return GVE_OK;
+}
+
+gve_status gve_dense_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field,
+                               gve_grid g, float* d_grad, double* h_loss) {
+  TRY(check_ctx_params(ctx, p));
+  if (!d_field) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "d_field is NULL");
+  TRY(validate_grid(ctx, g));
+  TRY(check_dense(ctx, p));
+  TRY(set_device(ctx));
+  gve_params* pm = const_cast<gve_params*>(p);
+  const int64_t M = g.nx * g.ny * g.nz;
+  const int64_t nblk = gve::dense_blocks(g);
+  TRY(ensure(ctx, ctx->ws.dense, sizeof(float) * (size_t)M));
+  TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)nblk));
+  TRY(prep_only(ctx, p, g));
+  float* resid = static_cast<float*>(ctx->ws.dense.ptr);
+  float* bl = static_cast<float*>(ctx->ws.brick_loss.ptr);
+  double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
+  TRY_HIP(ctx, gve::launch_dense_forward(p->rec, p->n, g, ctx->opt.k, d_field, resid, bl,
+                                         ctx->stream));
+  TRY_HIP(ctx, gve::launch_loss_reduce(bl, nblk, dl + 16, dl, ctx->stream));
+  if (d_grad) {
+    TRY_HIP(ctx, gve::fill_f32(pm->acc, gve::kAccStride * p->n, 0.0f, ctx->stream));
+    TRY_HIP(ctx, gve::launch_dense_backward(p->rec, p->n, g, ctx->opt.k, resid, pm->acc,
+                                            ctx->stream));
+    TRY_HIP(ctx, gve::launch_update(0, pm->theta, pm->m, pm->v, pm->acc, nullptr, p->offset,
+                                    nullptr, d_grad, p->n, p->t, ctx->opt, nullptr, ctx->stream));
+  }
+  if (h_loss) {
+    TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, dl, sizeof(double), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *h_loss = *static_cast<double*>(ctx->ws.h_pinned);
     if (!std::isfinite(*h_loss)) return fail(ctx, GVE_ERR_NUMERIC, "loss is not finite");
   }
   return GVE_OK;
@@ -1100,7 +1172,7 @@ gve_status gve_get_stats(const gve_ctx* ctx, gve_stats* out) {
                                &w.order_keys[0], &w.order_keys[1], &w.order_vals[0],
                                &w.order_vals[1], &w.queue, &w.p_cls, &w.p_pts, &w.p_acc,
                                &w.p_coef, &w.p_keys[0], &w.p_keys[1], &w.p_idx[0], &w.p_idx[1],
-                               &w.p_start, &w.p_loss};
+                               &w.p_start, &w.p_loss, &w.dense};
   static_assert(sizeof(all) / sizeof(all[0]) * sizeof(gve::Scratch) + sizeof(void*) ==
                     sizeof(gve::Workspace),
                 "every scratch buffer of the workspace is counted");

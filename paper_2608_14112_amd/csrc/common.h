@@ -86,6 +86,7 @@ struct Workspace {
   // the paper's training loop: class block counts / offsets, sample points,
   // their float64 accumulators, gradient coefficients, cell sort, losses
   Scratch p_cls, p_pts, p_acc, p_coef, p_keys[2], p_idx[2], p_start, p_loss;
+  Scratch dense;                 // float [M] residual of the dense reference path
   void* h_pinned = nullptr;      // pinned host staging (64 bytes)
 };
 
@@ -217,6 +218,19 @@ hipError_t launch_loss_reduce(const float* brick_loss, int64_t nbricks, double* 
 hipError_t launch_item_loss(const float* brick_loss, const ItemDesc* items, int nitems,
                             int64_t nbricks, double* out, hipStream_t s);
 hipError_t fill_u32(uint32_t* p, int64_t n, hipStream_t s);
+
+// ---- dense reference path (dense.hip) ---------------------------------------
+// Every (primitive, voxel) pair of grid g, no binning.  Forward: field ==
+// nullptr writes Vhat to out [M]; otherwise out = 2 (Vhat - field) and
+// block_loss [dense_blocks(g)] the per-block sums of (Vhat - field)^2.
+// Backward: the ten gradient sums of every primitive from the residual, added
+// to acc [n][kAccStride] with float atomics.  Records come from launch_prep.
+int64_t dense_blocks(const gve_grid& g);
+hipError_t launch_dense_forward(const Record* rec, int64_t n, const gve_grid& g, float k,
+                                const float* field, float* out, float* block_loss,
+                                hipStream_t s);
+hipError_t launch_dense_backward(const Record* rec, int64_t n, const gve_grid& g, float k,
+                                 const float* resid, float* acc, hipStream_t s);
 
 // Small utility kernels.
 hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t s);
