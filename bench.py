@@ -35,6 +35,8 @@ sys.path.insert(0, ROOT)
 
 FLOPS_PER_PAIR = 58          # fused kernel: 20 forward + 17 recompute + 21 gradient terms
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+EXP2_PEAK_PER_S = 256 * 16 * 2.4e9   # quarter-rate transcendental: 16 lanes per CU per clock
+HBM_PEAK_BYTES_PER_S = 8e12
 METRIC = "fwd+bwd+Adam s/iter at 1024^3 x 1.4M Gaussians; time-to-PSNR warm vs plain"
 
 
@@ -282,6 +284,17 @@ def batched_bench(args):
         },
         "stages_ms": {"bin": st["ms_bin"] / args.steps, "fused": fused_ms,
                       "update": st["ms_update"] / args.steps},
+        "iter_ms": {"median": per_iter[len(per_iter) // 2],
+                    "p90": per_iter[min(len(per_iter) - 1, int(0.9 * len(per_iter)))],
+                    "n": len(per_iter)},
+        # algorithmic fractions: 58 flops and 2 exp2 per in-support pair in the
+        # fused kernel; 4.29 GB target + 86 floats of parameter state per
+        # primitive per iteration against HBM
+        "fractions": {
+            "valu_fp32": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "transcendental": 2.0 * pairs / (fused_ms * 1e-3) / EXP2_PEAK_PER_S,
+            "hbm": (4.0 * M + 86 * 4.0 * P.n) / (ms_step * 1e-3) / HBM_PEAK_BYTES_PER_S,
+        },
         "work": {"pairs_in_support": pairs, "candidate_evals": 0.5 * (cand0 + cand1)},
         "autotune": [{"brick": [t[0], t[0], t[1]], "schedule": sched_names[t[2]], "ms": t[3]}
                      for t in table],
@@ -536,8 +549,19 @@ def main():
     wall = time.perf_counter() - w0
     ctx.set_timing(False)
     st = ctx.stats()
-    in1, cand1 = g.count_pairs(ctx, P, grid)
     ms_step = ev0.elapsed_time(ev1) / args.steps
+    # spread of single iterations (after the timed region, same stream)
+    per_iter = []
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.refine(ctx, P, field, grid, 1)
+        e1.record()
+        torch.cuda.synchronize()
+        per_iter.append(e0.elapsed_time(e1))
+    per_iter.sort()
+    in1, cand1 = g.count_pairs(ctx, P, grid)
     pairs = 0.5 * (in0 + in1)
     cand = 0.5 * (cand0 + cand1)
     fused_ms = st["ms_fused"] / args.steps
@@ -588,6 +612,17 @@ def main():
         },
         "stages_ms": {"bin": st["ms_bin"] / args.steps, "fused": fused_ms,
                       "update": st["ms_update"] / args.steps},
+        "iter_ms": {"median": per_iter[len(per_iter) // 2],
+                    "p90": per_iter[min(len(per_iter) - 1, int(0.9 * len(per_iter)))],
+                    "n": len(per_iter)},
+        # algorithmic fractions: 58 flops and 2 exp2 per in-support pair in the
+        # fused kernel; 4.29 GB target + 86 floats of parameter state per
+        # primitive per iteration against HBM
+        "fractions": {
+            "valu_fp32": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "transcendental": 2.0 * pairs / (fused_ms * 1e-3) / EXP2_PEAK_PER_S,
+            "hbm": (4.0 * M + 86 * 4.0 * P.n) / (ms_step * 1e-3) / HBM_PEAK_BYTES_PER_S,
+        },
         "work": {"pairs_in_support": pairs, "candidate_evals": cand,
                  "lane_efficiency": pairs / cand if cand else None,
                  "overlaps": st["n_overlaps"], "bricks": st["n_bricks"]},
