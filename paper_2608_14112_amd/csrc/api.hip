@@ -78,15 +78,21 @@ gve_status ensure(gve_ctx* ctx, Scratch& s, size_t bytes) {
   return GVE_OK;
 }
 
-// Small device block: [0] loss (double), [1] pair total (u64), [2] clamp
-// count (u64), [16 ..] loss-reduction partials.  Zeroed when first allocated.
+// Small device block: [0] loss (double), [2] clamp count (u64), [4 ..] small
+// counters, [16 ..] loss-reduction partials, then kTotalSlots pair-total
+// counters (u64).  Zeroed when first allocated.
 gve_status ensure_dloss(gve_ctx* ctx) {
   if (ctx->ws.dloss.ptr) return GVE_OK;
-  const size_t nd = 16 + gve::loss_reduce_tmp_doubles();
+  const size_t nd = 16 + gve::loss_reduce_tmp_doubles() + gve::kTotalSlots;
   TRY(ensure(ctx, ctx->ws.dloss, sizeof(double) * nd));
   TRY_HIP(ctx, gve::fill_u64(static_cast<unsigned long long*>(ctx->ws.dloss.ptr), (int64_t)nd,
                              ctx->stream));
   return GVE_OK;
+}
+
+unsigned long long* pair_total_slots(gve_ctx* ctx) {
+  return reinterpret_cast<unsigned long long*>(ctx->ws.dloss.ptr) + 16 +
+         gve::loss_reduce_tmp_doubles();
 }
 
 gve_status validate_options(const gve_ctx* ctx, const gve_options& o) {
@@ -200,8 +206,8 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   const gve::ItemDesc* items = static_cast<const gve::ItemDesc*>(ws.items.ptr);
   TRY(ensure(ctx, ws.scan_tmp, gve::scan_tmp_bytes(n + 1)));
   TRY(ensure_dloss(ctx));
-  unsigned long long* total = reinterpret_cast<unsigned long long*>(ws.dloss.ptr) + 1;
-  TRY_HIP(ctx, gve::fill_u64(total, 1, s));
+  unsigned long long* total = pair_total_slots(ctx);
+  TRY_HIP(ctx, gve::fill_u64(total, gve::kTotalSlots, s));
   TRY_HIP(ctx, gve::launch_prep(p->theta, n, items, vol.n, ctx->opt.k, bg, p->rec, p->count,
                                 total, s));
   // Culling drops bricks a separating plane parts from the support.  The box
@@ -219,9 +225,13 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
     TRY_HIP(ctx, gve::scan_exclusive_u32(p->count, bo, n, ws.scan_tmp.ptr, s));
     box_off = bo;
   }
-  TRY_HIP(ctx, hipMemcpyAsync(hp, total, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  static_assert(sizeof(unsigned long long) * gve::kTotalSlots <= 256, "pinned staging size");
+  TRY_HIP(ctx, hipMemcpyAsync(hp, total, sizeof(unsigned long long) * gve::kTotalSlots,
+                              hipMemcpyDeviceToHost, s));
   TRY_HIP(ctx, hipStreamSynchronize(s));
-  const unsigned long long box_total = *reinterpret_cast<unsigned long long*>(hp);
+  unsigned long long box_total = 0;
+  for (int j = 0; j < gve::kTotalSlots; ++j)
+    box_total += reinterpret_cast<const unsigned long long*>(hp)[j];
   if (box_total >= 0xFFFFFFF0ull)
     return fail(ctx, GVE_ERR_UNSUPPORTED,
                 "more than 2^32 (primitive, brick) pairs; use larger bricks or a smaller k");
@@ -310,13 +320,15 @@ gve_status prep_only(gve_ctx* ctx, const gve_params* p, const gve_grid& g) {
   int64_t nbricks = 0;
   TRY(upload_items(ctx, Vol{&g, off, 1}, brick_xy(ctx), brick_z(ctx), &nbricks));
   TRY(ensure_dloss(ctx));
-  unsigned long long* total = reinterpret_cast<unsigned long long*>(ctx->ws.dloss.ptr) + 1;
+  unsigned long long* total = pair_total_slots(ctx);
+  TRY_HIP(ctx, gve::fill_u64(total, gve::kTotalSlots, ctx->stream));
   gve::BrickGeom bg;
   bg.Bxy = brick_xy(ctx);
   bg.Bz = brick_z(ctx);
   bg.nbricks = nbricks;
-  TRY_HIP(ctx, gve::launch_prep(p->theta, p->n, static_cast<const gve::ItemDesc*>(ctx->ws.items.ptr),
-                                1, ctx->opt.k, bg, p->rec, p->count, total, ctx->stream));
+  const gve::ItemDesc* items = static_cast<const gve::ItemDesc*>(ctx->ws.items.ptr);
+  TRY_HIP(ctx, gve::launch_prep(p->theta, p->n, items, 1, ctx->opt.k, bg, p->rec, p->count, total,
+                                ctx->stream));
   return GVE_OK;
 }
 

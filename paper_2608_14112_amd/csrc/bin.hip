@@ -128,11 +128,12 @@ __global__ __launch_bounds__(kThreads) void k_prep(const float* __restrict__ the
   uint32_t cnt = 0;
   if (i < n) cnt = prep_one(theta, n, i, items[item_of_prim(items, nitems, (uint32_t)i)], k, bg, rec);
   if (i < n) count[i] = cnt;
-  // 64-bit pair total (the scan itself is 32-bit): one atomic per wave
+  // 64-bit pair total (the scan itself is 32-bit): one atomic per wave, into
+  // one of kTotalSlots counters
   unsigned long long w = cnt;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) w += __shfl_xor(w, d, 64);
-  if ((threadIdx.x & 63) == 0 && w) atomicAdd(total, w);
+  if ((threadIdx.x & 63) == 0 && w) atomicAdd(&total[blockIdx.x % kTotalSlots], w);
 }
 
 // ---- culling of bricks that miss the support -----------------------------

@@ -167,6 +167,10 @@ struct Schedule {
 
 // Writes rec and count for every primitive and adds the pair total to *total
 // (which the caller zeroes first).
+// The prep kernel adds each wave's box brick count to total[block % kTotalSlots]
+// (64-bit): spreading the atomics over several addresses keeps them from
+// queueing on one; the host sums the slots.
+constexpr int kTotalSlots = 32;
 hipError_t launch_prep(const float* theta, int64_t n, const ItemDesc* items, int nitems, float k,
                        BrickGeom bg, Record* rec, uint32_t* count, unsigned long long* total,
                        hipStream_t s);
