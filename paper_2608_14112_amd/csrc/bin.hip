@@ -128,12 +128,20 @@ __global__ __launch_bounds__(kThreads) void k_prep(const float* __restrict__ the
   uint32_t cnt = 0;
   if (i < n) cnt = prep_one(theta, n, i, items[item_of_prim(items, nitems, (uint32_t)i)], k, bg, rec);
   if (i < n) count[i] = cnt;
-  // 64-bit pair total (the scan itself is 32-bit): one atomic per wave, into
+  // 64-bit pair total (the scan itself is 32-bit): one atomic per block, into
   // one of kTotalSlots counters
+  __shared__ unsigned long long wsum[kThreads / 64];
   unsigned long long w = cnt;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) w += __shfl_xor(w, d, 64);
-  if ((threadIdx.x & 63) == 0 && w) atomicAdd(&total[blockIdx.x % kTotalSlots], w);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int v = 0; v < kThreads / 64; ++v) t += wsum[v];
+    if (t) atomicAdd(&total[blockIdx.x % kTotalSlots], t);
+  }
 }
 
 // ---- culling of bricks that miss the support -----------------------------

@@ -167,7 +167,7 @@ struct Schedule {
 
 // Writes rec and count for every primitive and adds the pair total to *total
 // (which the caller zeroes first).
-// The prep kernel adds each wave's box brick count to total[block % kTotalSlots]
+// The prep kernel adds each block's box brick count to total[block % kTotalSlots]
 // (64-bit): spreading the atomics over several addresses keeps them from
 // queueing on one; the host sums the slots.
 constexpr int kTotalSlots = 32;
