@@ -284,17 +284,6 @@ def batched_bench(args):
         },
         "stages_ms": {"bin": st["ms_bin"] / args.steps, "fused": fused_ms,
                       "update": st["ms_update"] / args.steps},
-        "iter_ms": {"median": per_iter[len(per_iter) // 2],
-                    "p90": per_iter[min(len(per_iter) - 1, int(0.9 * len(per_iter)))],
-                    "n": len(per_iter)},
-        # algorithmic fractions: 58 flops and 2 exp2 per in-support pair in the
-        # fused kernel; 4.29 GB target + 86 floats of parameter state per
-        # primitive per iteration against HBM
-        "fractions": {
-            "valu_fp32": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "transcendental": 2.0 * pairs / (fused_ms * 1e-3) / EXP2_PEAK_PER_S,
-            "hbm": (4.0 * M + 86 * 4.0 * P.n) / (ms_step * 1e-3) / HBM_PEAK_BYTES_PER_S,
-        },
         "work": {"pairs_in_support": pairs, "candidate_evals": 0.5 * (cand0 + cand1)},
         "autotune": [{"brick": [t[0], t[0], t[1]], "schedule": sched_names[t[2]], "ms": t[3]}
                      for t in table],
