@@ -719,6 +719,7 @@ gve_status gve_dense_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d
                                 ctx->stream));
     TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
     *h_loss = *static_cast<double*>(ctx->ws.h_pinned);
+    ctx->stats.last_loss = *h_loss;
     if (!std::isfinite(*h_loss)) return fail(ctx, GVE_ERR_NUMERIC, "loss is not finite");
   }
   return GVE_OK;
