@@ -508,7 +508,11 @@ gve_status gve_destroy(gve_ctx* ctx) {
                     &ws.sat, &ws.feat, &ws.theta_base, &ws.items, &ws.order_keys[0],
                     &ws.order_keys[1], &ws.order_vals[0], &ws.order_vals[1], &ws.queue,
                     &ws.p_cls, &ws.p_pts, &ws.p_acc, &ws.p_coef, &ws.p_keys[0], &ws.p_keys[1],
-                    &ws.p_idx[0], &ws.p_idx[1], &ws.p_start, &ws.p_loss};
+                    &ws.p_idx[0], &ws.p_idx[1], &ws.p_start, &ws.p_loss, &ws.dense,
+                    &ws.box_off, &ws.owner, &ws.slot_gid};
+  static_assert(sizeof(all) / sizeof(all[0]) * sizeof(Scratch) + sizeof(void*) ==
+                    sizeof(gve::Workspace),
+                "every scratch buffer of the workspace is freed");
   for (Scratch* s : all)
     if (s->ptr) hipFree(s->ptr);
   if (ws.h_pinned) hipHostFree(ws.h_pinned);
