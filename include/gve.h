@@ -74,7 +74,7 @@ typedef struct gve_grid {
  * (primitive, brick) pair writes its gradient sums to its own slot and the
  * update sums them per primitive in a fixed order, so gradients are bitwise
  * reproducible and no atomics are issued; 0 = each pair's sums are added to
- * the primitive's accumulators with float atomics (default: about 4 % faster
+ * the primitive's accumulators with float atomics (default: about 6 % faster
  * end to end, result order-dependent at float32 rounding).
  * schedule: the order in which workgroups take bricks (results are identical
  * under every schedule): GVE_SCHED_INDEX one workgroup per brick in brick
