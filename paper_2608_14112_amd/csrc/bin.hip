@@ -397,6 +397,7 @@ hipError_t launch_emit(const uint32_t* offset, int64_t n, const uint32_t* box_of
 
 hipError_t launch_gather_owner(const uint32_t* owner, const uint32_t* slot, int64_t n,
                                uint32_t* gid, hipStream_t s) {
+  if (n <= 0) return hipSuccess;  // no pairs: nothing to gather (an empty grid is invalid)
   const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_gather_owner, dim3(blocks), dim3(kThreads), 0, s, owner, slot, n, gid);
   return hipGetLastError();

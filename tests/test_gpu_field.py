@@ -210,6 +210,36 @@ def test_loss_grad_matches_oracle(brick, k, deterministic):
     check_grad(grad, gr, slack=slack)
 
 
+def test_loss_grad_edge_cases():
+    """Gradient edge cases: every primitive outside the grid (no pairs: zero
+    gradient, L = sum V^2), a single primitive, and a zero quaternion (the
+    identity rotation; its quaternion gradient is zero), on grids thinner than
+    one brick in z."""
+    g, torch = _lib()
+    grid = F.Grid(13, 11, 5, 2, -1, 0)
+    field = np.random.default_rng(17).uniform(-0.5, 1.0, size=grid.shape).astype(np.float32)
+    p = _case(8, grid, 18, scale_range=(0.5, 1.5))
+    p[0] += 200.0
+    for det in (True, False):
+        L, grad = _loss_grad_gpu(g, torch, p, field, grid, 3.0, (8, 32), deterministic=det)
+        assert not np.any(grad)
+        assert abs(L - np.sum(field.astype(np.float64) ** 2)) <= 1e-6 * L
+    p1 = _case(1, grid, 19, scale_range=(1.0, 2.0))
+    L1, g1 = _loss_grad_gpu(g, torch, p1, field, grid, 3.0, (8, 32))
+    Lr1, gr1 = F.loss_grad(p1, field.astype(np.float64), grid, 3.0)
+    assert abs(L1 - Lr1) <= 1e-5 * Lr1
+    slack1, _ = F.boundary_slack(p1, field, grid, 3.0, BAND)
+    check_grad(g1, gr1, slack=slack1)
+    p2 = _case(6, grid, 20, scale_range=(0.8, 2.0))
+    p2[3:7, 0] = 0.0
+    L2, g2 = _loss_grad_gpu(g, torch, p2, field, grid, 3.0, (8, 8))
+    Lr2, gr2 = F.loss_grad(p2, field.astype(np.float64), grid, 3.0)
+    assert abs(L2 - Lr2) <= 1e-5 * Lr2
+    assert np.all(g2[3:7, 0] == 0.0) and np.all(gr2[3:7, 0] == 0.0)
+    slack2, _ = F.boundary_slack(p2, field, grid, 3.0, BAND)
+    check_grad(g2, gr2, slack=slack2)
+
+
 @pytest.mark.parametrize("kind", ["wide", "thin"])
 def test_loss_grad_both_backward_forms(kind):
     """The backward pass evaluates G along each column by a product recurrence
