@@ -224,6 +224,17 @@ def test_loss_grad_edge_cases():
         L, grad = _loss_grad_gpu(g, torch, p, field, grid, 3.0, (8, 32), deterministic=det)
         assert not np.any(grad)
         assert abs(L - np.sum(field.astype(np.float64) ** 2)) <= 1e-6 * L
+    # refinement and the vector-Jacobian product with no pairs: zero gradient,
+    # parameters unchanged, every loss sum V^2
+    gg = g.Grid(grid.nx, grid.ny, grid.nz, grid.x0, grid.y0, grid.z0)
+    f = torch.from_numpy(field).cuda()
+    for det in (True, False):
+        ctx = g.Context(k=3.0, deterministic=det)
+        P = g.Params(ctx, p.shape[1]).upload(p.astype(np.float32))
+        hist = g.refine(ctx, P, f, gg, 3)
+        assert np.allclose(hist, np.sum(field.astype(np.float64) ** 2), rtol=1e-6)
+        assert np.array_equal(P.download(), p.astype(np.float32))
+        assert not np.any(g.vjp(ctx, P, f, gg).cpu().numpy())
     p1 = _case(1, grid, 19, scale_range=(1.0, 2.0))
     L1, g1 = _loss_grad_gpu(g, torch, p1, field, grid, 3.0, (8, 32))
     Lr1, gr1 = F.loss_grad(p1, field.astype(np.float64), grid, 3.0)
