@@ -5,10 +5,10 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  NumPy, float64 except
 where a float32 value decides a discrete choice (then the same float32 value
 that the device computes is used, see below).
 
-Steps, in the paper's order (the constants the paper does not print -- the
-0.02 occupancy threshold's use for both groups, the 4096-seed subsample, the
-7^3 tensor box, the elongation rule and the scale floor -- are readings of it,
-stated where they are used):
+Steps, in the paper's order.  The constants the paper does not print are
+readings of it, stated where they are used: the counter-based random numbers,
+the 4096-seed subsample, the 7^3 tensor box, the 99th-percentile gradient
+scale, the elongation rule and its cap, and the scale floor:
 
 S1a  gradient magnitude: central differences (one-sided at the grid faces) of
      the float32 field; g = |grad V| formed in float64 from the float32
