@@ -221,7 +221,7 @@ def batched_bench(args):
     table = g.autotune(ctx, cat, batch=B, reps=3)
     t_tune = time.perf_counter() - t0
     o = ctx.options
-    sched_names = ["brick order", "XCD-grouped", "persistent queue"]
+    sched_names = ["brick order", "XCD chunks", "persistent queue"]
     print(f"[bench] autotune {t_tune:.1f}s -> {o.brick}x{o.brick}x{o.brick_z}, "
           f"{sched_names[o.schedule]}", file=sys.stderr, flush=True)
     if args.warmup > 0:
@@ -584,7 +584,7 @@ def main():
             "k": args.k,
             "brick": [args.brick, args.brick, args.brick_z],
             "gradient_sums": "per-pair slots, fixed order" if args.deterministic else "float atomics",
-            "schedule": ["brick order", "XCD-grouped", "persistent queue"][ctx.options.schedule],
+            "schedule": ["brick order", "XCD chunks", "persistent queue"][ctx.options.schedule],
             "seed": args.seed,
         },
         "roofline": {

@@ -78,8 +78,9 @@ typedef struct gve_grid {
  * end to end, result order-dependent at float32 rounding).
  * schedule: the order in which workgroups take bricks (results are identical
  * under every schedule): GVE_SCHED_INDEX one workgroup per brick in brick
- * order (default); GVE_SCHED_XCD one workgroup per brick with consecutive
- * bricks kept on one XCD; GVE_SCHED_QUEUE a persistent launch whose
+ * order; GVE_SCHED_XCD (default) one workgroup per brick, runs of 256
+ * consecutive bricks dealt to the XCDs in turn, so that each XCD's L2 holds
+ * the records its bricks share; GVE_SCHED_QUEUE a persistent launch whose
  * workgroups take bricks from a work queue, heaviest first.  gve_autotune
  * measures which is fastest for a workload.
  */
@@ -120,7 +121,7 @@ typedef struct gve_ctx gve_ctx;
 typedef struct gve_params gve_params;
 
 /* Fill *opt with k = 3, brick 8 x 8 x 32, lr = 8e-3, beta = (0.9, 0.999),
- * eps = 1e-8, no clamp, atomic gradient sums.  Returns INVALID_ARGUMENT if
+ * eps = 1e-8, no clamp, atomic gradient sums, the XCD brick schedule.  Returns INVALID_ARGUMENT if
  * opt is NULL. */
 gve_status gve_default_options(gve_options* opt);
 

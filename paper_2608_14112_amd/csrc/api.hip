@@ -470,7 +470,7 @@ gve_status gve_default_options(gve_options* opt) {
   opt->ell_min = -INFINITY;
   opt->ell_max = INFINITY;
   opt->brick_z = 32;
-  opt->schedule = GVE_SCHED_INDEX;
+  opt->schedule = GVE_SCHED_XCD;
   opt->deterministic = 0;
   return GVE_OK;
 }

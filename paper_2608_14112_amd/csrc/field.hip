@@ -285,13 +285,22 @@ __device__ inline Site site_of(const ItemDesc* __restrict__ items, int nitems, u
   return s;
 }
 
-// Workgroup w -> brick when consecutive bricks go to one XCD: the dispatcher
-// deals workgroups round-robin over the 8 XCDs, so XCD x = w % 8 receives the
-// contiguous block of bricks [x q + min(x, r), ...) of size q + (x < r), with
-// nb = 8 q + r (a bijection of [0, nb)).
+// Workgroup w -> brick when runs of consecutive bricks go to one XCD: the
+// dispatcher deals workgroups round-robin over the 8 XCDs, so XCD x = w % 8
+// runs its k-th workgroup (k = w / 8) on brick c C + k % C of chunk
+// c = 8 (k / C) + x.  Chunks of C = 256 bricks (two rows of an 8 x 8 x 32
+// brick grid at 1024^3) are small enough that the records of the primitives a
+// chunk meets stay in that XCD's L2 while it works on it, and dealt in turn,
+// so every XCD moves through the volume at the same pace (one contiguous
+// eighth per XCD left dense regions to a few XCDs).  Bricks past the last
+// whole round of 8 C keep their index (a bijection of [0, nb)).
+constexpr uint32_t kXcdChunk = 256;
+
 __device__ inline uint32_t xcd_brick(uint32_t w, uint32_t nb) {
-  const uint32_t q = nb >> 3, r = nb & 7u, x = w & 7u, k = w >> 3;
-  return x * q + (x < r ? x : r) + k;
+  const uint32_t full = nb / (8u * kXcdChunk) * (8u * kXcdChunk);
+  if (w >= full) return w;
+  const uint32_t x = w & 7u, k = w >> 3;
+  return ((k / kXcdChunk) * 8u + x) * kXcdChunk + k % kXcdChunk;
 }
 
 template <int BXY, int BZ>

@@ -37,7 +37,7 @@ def test_default_options_and_status_strings():
 
     o = g.default_options()
     assert o.k == 3.0 and o.brick == 8 and o.brick_z == 32 and o.deterministic == 0
-    assert o.schedule == g.SCHED_INDEX
+    assert o.schedule == g.SCHED_XCD
     assert abs(o.lr - 8e-3) < 1e-9 and abs(o.beta1 - 0.9) < 1e-7 and abs(o.beta2 - 0.999) < 1e-7
     assert math.isinf(o.ell_min) and math.isinf(o.ell_max)
     for s in range(7):
