@@ -466,7 +466,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2026)
     ap.add_argument("--cpu-block", type=int, default=256)
     ap.add_argument("--schedule", type=int, default=None,
-                    help="brick schedule: 0 brick order, 1 XCD-grouped, 2 persistent queue "
+                    help="brick schedule: 0 brick order, 1 XCD chunks, 2 persistent queue "
                          "(default: the library's)")
     ap.add_argument("--deterministic", action="store_true",
                     help="per-pair gradient slots summed in a fixed order (bitwise reproducible) "
