@@ -180,3 +180,103 @@ def targets(theta_alloc, theta_ref):
     qn[:, flip] *= -1
     r[3:7] = qn
     return (r - a).T
+
+
+# ----------------------------------------------------------------------------- training loop
+
+def column_stats(X):
+    """Per-column mean and population standard deviation of a [rows, cols]
+    matrix, the standardisation the network is trained with.  A column whose
+    deviation is at most 1e-6 keeps a scale of 1 (it carries no information)."""
+    X = np.asarray(X, dtype=np.float64)
+    mean = X.mean(axis=0)
+    sd = np.sqrt(np.maximum((X * X).mean(axis=0) - mean * mean, 0.0))
+    return mean, np.where(sd > 1e-6, sd, 1.0)
+
+
+def epoch_permutation(n, seed, epoch):
+    """Order in which epoch `epoch` visits the n training rows: the rows sorted
+    by a 32-bit key drawn from the counter generator of ``oracle.alloc``
+    (SplitMix64 of (seed, stream = epoch, row), top 32 bits), ties kept in row
+    order.  Random numbers the training draws are thus a function of the seed
+    alone, written here from the generator's published definition."""
+    keys = (A.hash_bits(seed, epoch, np.arange(n, dtype=np.uint64)) >> np.uint64(32))
+    return np.argsort(keys.astype(np.uint64), kind="stable")
+
+
+def flat_to_params(flat):
+    """The library's flat layout (W1, b1, W2, b2, W3, b3) as a dict of float64."""
+    flat = np.asarray(flat, dtype=np.float64)
+    p, off = {}, 0
+    for name, shape in (("W1", (D_H, D_IN)), ("b1", (D_H,)), ("W2", (D_H, D_H)), ("b2", (D_H,)),
+                        ("W3", (D_OUT, D_H)), ("b3", (D_OUT,))):
+        size = int(np.prod(shape))
+        p[name] = flat[off:off + size].reshape(shape).copy()
+        off += size
+    return p
+
+
+def train(p, X, T, epochs, batch, lr, seed, bf16=True, stats_dtype=np.float32):
+    """Mini-batch training of the network on raw features X [n, 16] and raw
+    targets T [n, 11]: standardise both with their column statistics (held in
+    ``stats_dtype``, the precision the statistics are stored in beside the
+    weights), then for every epoch visit the rows in ``epoch_permutation``
+    order in batches of `batch` rows (the last one may be short) and take one
+    Adam step (``adam``) on each batch's mean squared error.
+
+    Returns (weights, stats, per-epoch mean batch loss); stats =
+    (feature mean, feature std, target mean, target std)."""
+    X = np.asarray(X, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    fm, fs = (a.astype(stats_dtype).astype(np.float64) for a in column_stats(X))
+    tm, ts = (a.astype(stats_dtype).astype(np.float64) for a in column_stats(T))
+    Xs = (X - fm) / fs
+    Ts = (T - tm) / ts
+    n = X.shape[0]
+    state = {}
+    hist = []
+    nb = (n + batch - 1) // batch
+    for ep in range(epochs):
+        perm = epoch_permutation(n, seed, ep)
+        tot = 0.0
+        for b in range(nb):
+            rows = perm[b * batch:(b + 1) * batch]
+            L, g = loss_and_grads(p, Xs[rows], Ts[rows], bf16=bf16)
+            tot += L
+            p = adam(p, g, state, lr)
+        hist.append(tot / nb)
+    return p, (fm, fs, tm, ts), np.array(hist)
+
+
+# ----------------------------------------------------------------------------- warm start
+
+def destandardise(Y, tmean, tstd):
+    """Network outputs on the standardised scale [n, 11] -> parameter
+    corrections Delta [n, 11] in the units of the 11 parameters."""
+    return np.asarray(Y, dtype=np.float64) * np.asarray(tstd, dtype=np.float64) \
+        + np.asarray(tmean, dtype=np.float64)
+
+
+WARM_ALPHAS = (1.0, 0.5, 0.25)
+
+
+def warmstart(theta_alloc, Y, tmean, tstd, loss_fn, alphas=WARM_ALPHAS):
+    """Apply the network's correction to an allocation, with plain refinement's
+    starting point as the fallback: theta = theta_alloc + alpha * Delta for
+    alpha = 1, 1/2, 1/4 in turn, keeping the first whose loss (``loss_fn``,
+    the full-grid sum of squares) is below the allocation's; if none is, the
+    allocation is kept unchanged.
+
+    theta_alloc [11, n]; Y [n, 11] standardised outputs.  Returns
+    (applied, losses, theta): applied = 0 (fallback) or the 1-based index of
+    the alpha kept; losses [4] = the allocation's loss and the loss at each
+    alpha tried (NaN where not tried)."""
+    theta_alloc = np.asarray(theta_alloc, dtype=np.float64)
+    delta = destandardise(Y, tmean, tstd).T
+    losses = [float(loss_fn(theta_alloc)), math.nan, math.nan, math.nan]
+    for j, alpha in enumerate(alphas):
+        theta = theta_alloc + alpha * delta
+        losses[j + 1] = float(loss_fn(theta))
+        if math.isfinite(losses[j + 1]) and losses[j + 1] < losses[0]:
+            return j + 1, np.array(losses), theta
+    return 0, np.array(losses), theta_alloc.copy()

@@ -342,3 +342,71 @@ def test_absolute_gradient_bounds_the_gradient_and_matches_single_pair():
     _, g1 = F.loss_grad(p1, f1, one, 3.0)
     a1 = F.loss_grad_absolute(p1, f1, one, 3.0)
     assert np.allclose(np.abs(g1), a1, rtol=1e-10, atol=1e-15)
+
+
+def _one(mu, ell, q=(1.0, 0.0, 0.0, 0.0), c=1.0):
+    p = np.zeros((11, 1))
+    p[0:3, 0] = mu
+    p[3:7, 0] = q
+    p[7:10, 0] = ell
+    p[10, 0] = c
+    return p
+
+
+def test_count_pairs_isotropic_ball_lattice_count():
+    """An isotropic s = 1 Gaussian centred at (0.5, 0.5, 0.5) with k = 3: the
+    in-support voxels are the integer points with |p - mu|^2 < 9, i.e. odd
+    (u, v, w) = 2 (p - mu) with u^2 + v^2 + w^2 < 36.  With squares from
+    {1, 9, 25}: (1,1,1) 8, (1,1,9) 24, (1,9,9) 24, (9,9,9) 8, (1,1,25) 24,
+    (1,9,25) 48 sign/order patterns: 136 voxels, none on the boundary."""
+    grid = F.Grid(20, 20, 20)
+    p = _one((10.5, 10.5, 10.5), (0.0, 0.0, 0.0))
+    assert F.count_pairs(p, grid, 3.0) == 136
+
+
+def test_count_pairs_axis_aligned_ellipsoid_integer_count():
+    """Scales (1, 2, 1/2) centred half-way between voxels: m^2 < 9 becomes
+    4u^2 + v^2 + 16w^2 < 144 over odd integers (u, v, w), counted exactly in
+    integers (the left side is 5 mod 8, so no point lies on the boundary)."""
+    grid = F.Grid(24, 30, 16)
+    p = _one((11.5, 14.5, 7.5), (0.0, math.log(2.0), -math.log(2.0)))
+    odd = range(-31, 32, 2)
+    ref = sum(1 for u in odd for v in odd for w in odd if 4 * u * u + v * v + 16 * w * w < 144)
+    assert F.count_pairs(p, grid, 3.0) == ref
+    # a grid that cuts the ellipsoid counts only what lies inside it
+    cut = F.Grid(12, 30, 16)                       # x in [0, 11]: u = 2x - 23 <= -1
+    ref_cut = sum(1 for u in odd for v in odd for w in odd
+                  if u < 0 and 4 * u * u + v * v + 16 * w * w < 144)
+    assert F.count_pairs(p, cut, 3.0) == ref_cut
+
+
+@pytest.mark.parametrize("k", [2.0, 3.0, 5.0])
+def test_count_pairs_equals_bruteforce_support_count(k):
+    """For rotated anisotropic primitives (some hanging over the grid's faces)
+    the windowed count equals the number of voxels where the brute-force
+    truncated field of each primitive alone (c = 1) is nonzero."""
+    grid = F.Grid(14, 11, 9, 2, -3, 1)
+    params = S.random_params(6, (14, 11, 9), seed=int(k), scale_range=(0.5, 2.5),
+                             unit_quat=False)
+    params[0] += grid.x0 + np.array([-2.0, 0, 0, 3.0, 0, 0])
+    params[1] += grid.y0
+    params[2] += grid.z0
+    params[10] = 1.0
+    ref = 0
+    for i in range(params.shape[1]):
+        ref += int(np.count_nonzero(F.evaluate_bruteforce(params[:, i:i + 1], grid, k)))
+    assert ref > 0
+    assert F.count_pairs(params, grid, k) == ref
+
+
+def test_count_pairs_cut_is_strict_on_lattice_boundary_points():
+    """Centred on a voxel with s = 1 and k = 3, m^2 = |p - mu|^2 is an exact
+    integer; the voxels with |p - mu|^2 < 9 number sum_{n < 9} r3(n) =
+    1 + 6 + 12 + 8 + 6 + 24 + 24 + 0 + 12 = 93 (r3(n): representations of n as a
+    sum of three squares), and the 30 voxels with |p - mu|^2 = 9 ((3,0,0) and
+    (2,2,1) up to sign and order) lie on the cut and are excluded."""
+    grid = F.Grid(15, 15, 15)
+    p = _one((7.0, 7.0, 7.0), (0.0, 0.0, 0.0))
+    assert F.count_pairs(p, grid, 3.0) == 93
+    V = F.evaluate_bruteforce(p, grid, 3.0)
+    assert np.count_nonzero(V) == 93
