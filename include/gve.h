@@ -313,6 +313,27 @@ gve_status gve_count_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, int64_
                            int64_t* h_candidates);
 
 /*
+ * Binning inspection (Sec. III-G: primitives are binned by their k-sigma
+ * support before evaluation).  Bins p on grid g exactly as gve_evaluate does
+ * and reports the (brick key, value) pairs: brick keys are brick ids (x
+ * fastest over the grid's bricks of the context's brick shape); values are
+ * primitive ids, or with options.deterministic the pairs' emission indices.
+ * d_emit_keys / d_emit_vals receive the pairs in emission order (primitive by
+ * primitive, in increasing primitive id, each primitive's kept bricks
+ * consecutively), d_keys / d_vals the same pairs after the stable sort by
+ * brick key, d_brick_start [n_bricks + 1] the first sorted pair of each brick
+ * (the last entry = the pair count).  All five are caller-owned device uint32
+ * arrays; the pair arrays hold `capacity` entries.  *h_npairs and *h_nbricks
+ * (host) receive the counts.  With any of the five pointers NULL only the
+ * counts are returned; if the pairs do not fit in `capacity` the counts are
+ * returned with INVALID_ARGUMENT and nothing is copied.  Synchronises.
+ */
+gve_status gve_bin_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, uint32_t* d_emit_keys,
+                         uint32_t* d_emit_vals, uint32_t* d_keys, uint32_t* d_vals,
+                         uint32_t* d_brick_start, int64_t capacity, int64_t* h_npairs,
+                         int64_t* h_nbricks);
+
+/*
  * Batched volumes: many uneven volumes (bricks of a larger domain, or
  * timesteps) binned together and refined in one launch per stage, every
  * (volume, brick) tile a work item of the same kernels (the work of each

@@ -202,13 +202,12 @@ def group_spacing(mu32):
 # ----------------------------------------------------------------------------- S1d
 
 def structure_tensor(parts, vox_ijk, radius=ST_RADIUS):
-    gx, gy, gz = (p.astype(np.float64) for p in parts)
-    nz, ny, nx = gx.shape
+    nz, ny, nx = parts[0].shape
     i, j, k = vox_ijk
     sl = (slice(max(k - radius, 0), min(k + radius + 1, nz)),
           slice(max(j - radius, 0), min(j + radius + 1, ny)),
           slice(max(i - radius, 0), min(i + radius + 1, nx)))
-    a, b, c = gx[sl].ravel(), gy[sl].ravel(), gz[sl].ravel()
+    a, b, c = (p[sl].astype(np.float64).ravel() for p in parts)
     return np.array([[a @ a, a @ b, a @ c], [a @ b, b @ b, b @ c], [a @ c, b @ c, c @ c]])
 
 
@@ -269,6 +268,22 @@ def lsq_weight(U, V):
     return float(U @ V) / uu if uu > 0 else 0.0
 
 
+def frame_and_scales(parts, gflat, vi, grid: F.Grid, s_base, g99, s_cap):
+    """Orientation and log-scales of the primitive seeded at voxel vi (S1d):
+    the frame of the structure tensor of the 7^3 box around the seed, the
+    tangent axis stretched by 1 + 2 |grad V| / g99 (at most 3x), every scale
+    within [0.25, s_cap].  Returns (quaternion, log-scales, eigenvalues)."""
+    i = int(vi % grid.nx)
+    j = int((vi // grid.nx) % grid.ny)
+    kk = int(vi // (grid.nx * grid.ny))
+    J = structure_tensor(parts, (i, j, kk))
+    R, lam = frame_from_tensor(J)
+    gh = min(max(float(gflat[vi]) / g99, 0.0), 1.0) if g99 > 0 else 0.0
+    st = min(s_base * (1.0 + 2.0 * gh), MAX_ELONGATION * s_base)
+    s = np.clip(np.array([st, s_base, s_base]), MIN_SCALE, max(s_cap, MIN_SCALE))
+    return quat_from_rotation(R), np.log(s), lam
+
+
 @dataclass
 class AllocInfo:
     n_det: int
@@ -306,17 +321,10 @@ def allocate(field, grid: F.Grid, n, seed, k=3.0):
     for group, vox in enumerate((det, cov)):
         sb = s_base[group]
         for t, vi in enumerate(vox):
-            i = int(vi % grid.nx)
-            j = int((vi // grid.nx) % grid.ny)
-            kk = int(vi // (grid.nx * grid.ny))
-            J = structure_tensor(parts, (i, j, kk))
-            R, lam = frame_from_tensor(J)
-            gh = min(max(float(gflat[vi]) / g99, 0.0), 1.0) if g99 > 0 else 0.0
-            st = min(sb * (1.0 + 2.0 * gh), MAX_ELONGATION * sb)
-            s = np.clip(np.array([st, sb, sb]), MIN_SCALE, max(s_cap, MIN_SCALE))
+            q, ell, lam = frame_and_scales(parts, gflat, int(vi), grid, sb, g99, s_cap)
             params[0:3, col] = mus[group][:, t]
-            params[3:7, col] = quat_from_rotation(R)
-            params[7:10, col] = np.log(s)
+            params[3:7, col] = q
+            params[7:10, col] = ell
             params[10, col] = float(v.ravel()[vi])
             eig[col] = lam
             col += 1

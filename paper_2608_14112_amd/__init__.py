@@ -143,6 +143,8 @@ _SIGS = {
     "gve_warmstart": [_vp, _vp, _vp, _vp, GridC, _i64, ctypes.c_double,
                       ctypes.POINTER(ctypes.c_int32), _vp],
     "gve_count_pairs": [_vp, _vp, GridC, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+    "gve_bin_pairs": [_vp, _vp, GridC, _vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64),
+                      ctypes.POINTER(_i64)],
     "gve_batch_create": [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(_vp)],
     "gve_batch_params": [_vp, ctypes.POINTER(_vp)],
     "gve_batch_offsets": [_vp, _vp, _vp],
@@ -488,6 +490,26 @@ MLP_NWEIGHT = 20107
 MLP_NFLAT = MLP_NWEIGHT + 54
 MLP_LAYOUT = (("W1", (128, 16)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)),
               ("W3", (11, 128)), ("b3", (11,)))
+
+
+def bin_pairs(ctx: Context, params: Params, grid: Grid):
+    """gve_bin_pairs: (emitted keys, emitted values, sorted keys, sorted values,
+    brick starts) as uint32 numpy arrays."""
+    import torch
+
+    T = ctypes.c_int64()
+    nb = ctypes.c_int64()
+    _check(_lib.gve_bin_pairs(ctx.handle, params.handle, grid.c(), None, None, None, None, None,
+                              _i64(0), ctypes.byref(T), ctypes.byref(nb)), ctx.handle)
+    cap = max(int(T.value), 1)
+    bufs = [torch.empty(cap, device="cuda", dtype=torch.int32) for _ in range(4)]
+    start = torch.empty(int(nb.value) + 1, device="cuda", dtype=torch.int32)
+    _check(_lib.gve_bin_pairs(ctx.handle, params.handle, grid.c(), *[_ptr(b) for b in bufs],
+                              _ptr(start), _i64(cap), ctypes.byref(T), ctypes.byref(nb)),
+           ctx.handle)
+    n = int(T.value)
+    out = [b[:n].cpu().numpy().view(np.uint32) for b in bufs]
+    return (*out, start.cpu().numpy().view(np.uint32))
 
 
 class MLP:

@@ -157,6 +157,7 @@ struct Binned {
   const uint32_t* gid = nullptr;   // primitive of each sorted pair
   const uint32_t* slot = nullptr;  // its emission index (deterministic sums), else null
   const uint32_t* start = nullptr;
+  const uint32_t* sorted_keys = nullptr;  // brick key of each sorted pair
   int64_t npairs = 0;
 };
 
@@ -193,7 +194,16 @@ int resident_groups(gve_ctx* ctx, int bxy, int bz) {
 // heaviest-first order for the queue schedule).  Reads the box pair total (and
 // with culling the kept total) back to the host, small synchronising copies
 // that size the pair buffers.
-gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* out) {
+// Destination of a copy of the emitted (unsorted) pair list, for inspection.
+struct EmitCopy {
+  uint32_t* keys = nullptr;
+  uint32_t* vals = nullptr;
+  int64_t capacity = 0;
+  bool fits = false;  // set when the list fitted and was copied
+};
+
+gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* out,
+                   EmitCopy* ec = nullptr) {
   hipStream_t s = ctx->stream;
   auto& ws = ctx->ws;
   const int64_t n = p->n;
@@ -267,6 +277,15 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
     owner = static_cast<uint32_t*>(ws.owner.ptr);
   }
   TRY_HIP(ctx, gve::launch_emit(p->offset, n, box_off, kept, keys[0], vals[0], owner, s));
+  if (ec) {
+    ec->fits = (int64_t)T <= ec->capacity;
+    if (ec->fits && T > 0) {
+      TRY_HIP(ctx, hipMemcpyAsync(ec->keys, keys[0], sizeof(uint32_t) * (size_t)T,
+                                  hipMemcpyDeviceToDevice, s));
+      TRY_HIP(ctx, hipMemcpyAsync(ec->vals, vals[0], sizeof(uint32_t) * (size_t)T,
+                                  hipMemcpyDeviceToDevice, s));
+    }
+  }
   int which = 0;
   TRY_HIP(ctx, gve::radix_sort_pairs(keys, vals, (int64_t)T, bits_for(bg.nbricks), ws.sort_hist.ptr,
                                      &which, s));
@@ -306,6 +325,7 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
     out->gid = g;
   }
   out->start = start;
+  out->sorted_keys = keys[which];
   out->npairs = (int64_t)T;
   ctx->stats.n_primitives = n;
   ctx->stats.n_bricks = bg.nbricks;
@@ -951,6 +971,45 @@ gve_status gve_count_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, int64_
   TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
   *h_in_support = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[0];
   *h_candidates = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[1];
+  return GVE_OK;
+}
+
+gve_status gve_bin_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, uint32_t* d_emit_keys,
+                         uint32_t* d_emit_vals, uint32_t* d_keys, uint32_t* d_vals,
+                         uint32_t* d_brick_start, int64_t capacity, int64_t* h_npairs,
+                         int64_t* h_nbricks) {
+  TRY(check_ctx_params(ctx, p));
+  if (!h_npairs || !h_nbricks)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "h_npairs and h_nbricks are required");
+  const bool copy = d_emit_keys && d_emit_vals && d_keys && d_vals && d_brick_start;
+  if (copy && capacity < 0) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "capacity must be >= 0");
+  TRY(validate_grid(ctx, g));
+  TRY(set_device(ctx));
+  const int64_t off[2] = {0, p->n};
+  EmitCopy ec;
+  ec.keys = d_emit_keys;
+  ec.vals = d_emit_vals;
+  ec.capacity = copy ? capacity : -1;
+  Binned bn;
+  TRY(bin_vol(ctx, p, Vol{&g, off, 1}, &bn, &ec));
+  if (copy && ec.fits) {
+    hipStream_t s = ctx->stream;
+    const size_t T = (size_t)bn.npairs;
+    if (T > 0) {
+      TRY_HIP(ctx, hipMemcpyAsync(d_keys, bn.sorted_keys, sizeof(uint32_t) * T,
+                                  hipMemcpyDeviceToDevice, s));
+      TRY_HIP(ctx, hipMemcpyAsync(d_vals, bn.slot ? bn.slot : bn.gid, sizeof(uint32_t) * T,
+                                  hipMemcpyDeviceToDevice, s));
+    }
+    TRY_HIP(ctx, hipMemcpyAsync(d_brick_start, bn.start,
+                                sizeof(uint32_t) * (size_t)(bn.bg.nbricks + 1),
+                                hipMemcpyDeviceToDevice, s));
+  }
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *h_npairs = bn.npairs;
+  *h_nbricks = bn.bg.nbricks;
+  if (copy && !ec.fits)
+    return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "capacity is smaller than the pair count");
   return GVE_OK;
 }
 

@@ -9,7 +9,8 @@ Tolerances (stated once, used by every parity test):
   ||V_gpu - V_ref|| / ||V_ref|| <= 1e-5.
 * Truncation boundary: a pair whose float64 m^2 lies within BAND of k^2 may
   fall on either side in float32.  The oracle reports those pairs; voxels that
-  hold one are checked against the bracket [V_lo, V_hi] instead.
+  hold one are checked against the bracket [V_lo, V_hi] instead, and the
+  norm-wise bound is taken over the other voxels.
 * Gradients: float32 atomics make the summation order vary, so the result is
   one of many correct ones.  Per parameter group (mu, q, l, c) norm-wise
   relative error <= 1e-3, and elementwise |g - g_ref| <= 1e-3 |g_ref| +
@@ -41,10 +42,15 @@ def check_field(gpu, ref, A, bracket=None, rtol=VAL_RTOL):
     nbad = int(np.count_nonzero(bad))
     worst = float(np.max(err / (A + 1e-30))) if err.size else 0.0
     assert nbad == 0, f"{nbad} voxels outside tolerance; worst err/A = {worst:.3e}"
-    nref = float(np.linalg.norm(ref))
-    if nref > 0 and (bracket is None or not bracket[2]):
-        rel = float(np.linalg.norm(gpu - ref)) / nref
-        assert rel <= rtol, f"norm-wise relative error {rel:.3e}"
+    # norm-wise over the voxels that hold no pair near the cut (there the
+    # reference is unique); voxels with such a pair were held to the bracket
+    keep = np.ones(ref.shape, dtype=bool)
+    if bracket is not None and bracket[2]:
+        keep = ~(np.abs(bracket[1] - bracket[0]) > 0)
+    nref = float(np.linalg.norm(ref[keep]))
+    if nref > 0:
+        rel = float(np.linalg.norm((gpu - ref)[keep])) / nref
+        assert rel <= rtol, f"norm-wise relative error {rel:.3e} over {int(keep.sum())} voxels"
     return worst
 
 

@@ -100,3 +100,64 @@ def test_normalize_matches_minmax():
     got = t.cpu().numpy()
     assert np.max(np.abs(got - ref)) < 1e-6
     assert got.min() == 0.0 and abs(got.max() - 1.0) < 1e-6
+
+
+def test_allocate_mid_workload_matches_oracle_steps():
+    """256^3 k^-5/3 field, 65,536 primitives (the mid workload), where the
+    device's seed selection runs its multi-pass radix select over 16.8M keys.
+    Bit-exact: domain counts, both seed sets (through the float32 jittered
+    centres), g99; group spacings to 1e-12; frames and scales of 2,000 sampled
+    primitives against the oracle's per-seed step; weights c_i = kappa V(c_i)
+    with one kappa.  (kappa itself needs the oracle to evaluate all 65,536
+    primitives on the grid; it is compared at 64^3 and 48^3 above.)"""
+    g, torch = _lib()
+    n, budget, seed = 256, 65536, 4
+    print(f"allocate spectral {n}^3 budget {budget}", flush=True)
+    f = S.spectral_field((n, n, n), seed=8).numpy()
+    grid = F.Grid(n, n, n)
+    ctx = g.Context(k=3.0)
+    P, ginfo = g.allocate(ctx, torch.from_numpy(f).cuda(), g.Grid(n, n, n), budget, seed)
+    got = P.download()
+    v = f.astype(np.float32)
+    parts = A.gradient_parts(v)
+    g32 = A.gradient_magnitude32(v)
+    det, cov, n_el, n_oc = A.draw_seeds(v, g32, budget, seed)
+    assert ginfo["n_eligible"] == n_el and ginfo["n_occupied"] == n_oc
+    assert ginfo["n_detail"] == det.size and ginfo["n_coverage"] == cov.size
+    mus = [A.jitter_centers(det, grid.shape, (0, 0, 0), seed, 0),
+           A.jitter_centers(cov, grid.shape, (0, 0, 0), seed, 1)]
+    assert np.array_equal(got[0:3, :det.size], mus[0])
+    assert np.array_equal(got[0:3, det.size:], mus[1])
+    sb = (A.group_spacing(mus[0]), A.group_spacing(mus[1]))
+    assert ginfo["s_base_detail"] == pytest.approx(sb[0], rel=1e-12)
+    assert ginfo["s_base_coverage"] == pytest.approx(sb[1], rel=1e-12)
+    occ = v.ravel() > np.float32(A.OCC_THRESHOLD)
+    g99 = float(A.percentile_order_stat(g32.ravel()[occ]))
+    assert ginfo["g99"] == g99
+    seeds = np.concatenate([det, cov])
+    s_cap = n / A.CAP_DIVISOR
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(budget, size=2000, replace=False))
+    ref = np.zeros((11, idx.size))
+    gap = np.zeros(idx.size)
+    for t, i in enumerate(idx):
+        group = 0 if i < det.size else 1
+        q, ell, lam = A.frame_and_scales(parts, g32.ravel(), int(seeds[i]), grid, sb[group], g99,
+                                         s_cap)
+        ref[3:7, t], ref[7:10, t] = q, ell
+        gap[t] = (lam[1] - lam[2]) / max(lam[0], 1e-300)
+    sub = got[:, idx].astype(np.float64)
+    ref[0:3] = sub[0:3]
+    ref[10] = 1.0
+    assert np.max(np.abs(sub[7:10] - ref[7:10])) < 2e-6
+    ok = gap > 1e-4
+    assert ok.mean() > 0.5
+    Sg = F.covariance(sub)[ok]
+    Sr = F.covariance(ref)[ok]
+    rel = np.max(np.abs(Sg - Sr), axis=(1, 2)) / np.max(np.abs(Sr), axis=(1, 2))
+    assert np.max(rel) < 1e-4, np.max(rel)
+    # one least-squares factor times the value at each seed
+    vals = v.ravel()[seeds].astype(np.float64)
+    ratio = got[10].astype(np.float64) / vals
+    assert np.max(np.abs(ratio - ginfo["kappa"])) <= 1e-6 * abs(ginfo["kappa"])
+    assert ginfo["kappa"] > 0

@@ -185,3 +185,38 @@ def test_bad_batch_arguments():
         g.Batch(ctx, [g.Grid(8, 0, 8)], [5])
     with pytest.raises(g.GveError):
         g.Batch(ctx, [], [])
+
+
+def test_schedules_bitwise_equal_when_xcd_chunks_remap():
+    """The XCD chunk schedule remaps bricks only when there are at least
+    8 x 256 of them: 8^3 bricks on 136 x 128 x 128 voxels give 17 x 16 x 16 =
+    4,352 bricks, two whole rounds of chunks plus a 256-brick tail.  Field,
+    loss, gradient and three refinement steps (deterministic sums) are
+    bitwise equal under all three schedules, and the field matches the oracle."""
+    g, torch = _lib()
+    grid = F.Grid(136, 128, 128)
+    n = 6000
+    print(f"schedules on {grid} n={n} (4352 bricks of 8^3)", flush=True)
+    theta = S.random_params(n, (136, 128, 128), seed=31, scale_range=(0.8, 3.0))
+    theta = theta.astype(np.float32)
+    field = np.random.default_rng(32).uniform(size=grid.shape).astype(np.float32)
+    ft = torch.from_numpy(field).cuda()
+    gg = _ggrid(g, grid)
+    res = []
+    for sched in (0, 1, 2):
+        ctx = g.Context(k=3.0, lr=5e-3, brick=8, brick_z=8, schedule=sched, deterministic=True)
+        p = g.Params(ctx, n).upload(theta)
+        out = g.evaluate(ctx, p, gg).cpu().numpy()
+        assert ctx.stats()["n_bricks"] == 4352
+        grad = torch.empty((11, n), device="cuda")
+        L = g.loss_grad(ctx, p, ft, gg, grad)
+        h = g.refine(ctx, p, ft, gg, 3)
+        res.append((out, L, grad.cpu().numpy(), h, p.download()))
+    for r in res[1:]:
+        assert np.array_equal(r[0], res[0][0])
+        assert r[1] == res[0][1]
+        assert np.array_equal(r[2], res[0][2])
+        assert np.array_equal(r[3], res[0][3])
+        assert np.array_equal(r[4], res[0][4])
+    V, A, bracket = F.evaluate_windowed(theta.astype(np.float64), grid, 3.0, band=BAND)
+    check_field(res[1][0], V, A, bracket)

@@ -1,0 +1,123 @@
+"""GPU checks of the binning (Sec. III-G: primitives are binned by their
+k-sigma support) through gve_bin_pairs.
+
+* The sorted pair list is, bit for bit, the stable sort by brick key of the
+  emitted list (NumPy's stable argsort), at a size where the radix sort runs
+  three passes over thousands of tiles; the brick ranges are its run starts.
+* The kept (brick, primitive) set, compared as a set with the oracle: it
+  holds every brick where the primitive has an in-support voxel (pairs within
+  the band of the cut aside, which float32 may decide either way) and only
+  bricks that meet the primitive's k-sigma box.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import field as F
+from synth import fields as S
+from tests.parity import BAND
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import torch
+
+    import paper_2608_14112_amd as g
+    assert torch.cuda.is_available()
+    return g, torch
+
+
+def _params(n, grid, seed, scale_range):
+    p = S.random_params(n, (grid.nx, grid.ny, grid.nz), seed=seed, scale_range=scale_range,
+                        unit_quat=False)
+    p[0] += grid.x0 + np.random.default_rng(seed).uniform(-3, 3, n)
+    p[1] += grid.y0
+    p[2] += grid.z0
+    return p.astype(np.float32)
+
+
+def test_sorted_pairs_are_the_stable_sort_of_the_emitted_pairs():
+    g, torch = _lib()
+    grid = F.Grid(512, 512, 256)
+    n = 200_000
+    print(f"bin_pairs {grid} n={n} bricks 8^3", flush=True)
+    p = _params(n, grid, 3, (1.0, 3.0))
+    ctx = g.Context(k=3.0, brick=8, brick_z=8)
+    P = g.Params(ctx, n).upload(p)
+    ek, ev, sk, sv, start = g.bin_pairs(ctx, P, g.Grid(grid.nx, grid.ny, grid.nz))
+    nb = (512 // 8) * (512 // 8) * (256 // 8)
+    T = ek.size
+    print(f"bin_pairs: {T} pairs over {nb} bricks", flush=True)
+    assert T >= 2_000_000 and nb > 1 << 16          # three 6-bit passes, > 1000 tiles
+    assert start.size == nb + 1 and start[-1] == T
+    # emission: primitive by primitive in increasing id, distinct bricks each
+    assert np.all(ev[:-1] <= ev[1:])
+    same = ev[:-1] == ev[1:]
+    assert not np.any(ek[:-1][same] == ek[1:][same])
+    assert np.all(ek < nb)
+    order = np.argsort(ek, kind="stable")
+    assert np.array_equal(sk, ek[order])
+    assert np.array_equal(sv, ev[order])
+    assert np.array_equal(start, np.searchsorted(sk, np.arange(nb + 1), side="left"))
+
+
+def _support_and_box_bricks(p, grid, k, bxy, bz):
+    """Per primitive: bricks holding a voxel with m^2 < k^2 - BAND (surely in
+    support), and bricks meeting its k-sigma box widened by 1e-4 relative."""
+    p = p.astype(np.float64)
+    mu, _, _, _ = F.split(p)
+    P = F.precision(p)
+    S_ = F.covariance(p)
+    nbx, nby = -(-grid.nx // bxy), -(-grid.ny // bxy)
+    sure, box = set(), set()
+    k2 = k * k
+    for i in range(p.shape[1]):
+        b = F.support_box(mu[i], S_[i] * (1.0 + 1e-4) ** 2, k, grid)
+        if b is None:
+            continue
+        (ia, ib), (ja, jb), (ka, kb) = b
+        for bzz in range(ka // bz, kb // bz + 1):
+            for byy in range(ja // bxy, jb // bxy + 1):
+                for bxx in range(ia // bxy, ib // bxy + 1):
+                    box.add((bxx + nbx * (byy + nby * bzz), i))
+        b = F.support_box(mu[i], S_[i], k, grid)
+        if b is None:
+            continue
+        (ia, ib), (ja, jb), (ka, kb) = b
+        xs = grid.x0 + np.arange(ia, ib + 1) - mu[i, 0]
+        ys = grid.y0 + np.arange(ja, jb + 1) - mu[i, 1]
+        zs = grid.z0 + np.arange(ka, kb + 1) - mu[i, 2]
+        dz, dy, dx = np.meshgrid(zs, ys, xs, indexing="ij")
+        Q = P[i]
+        m2 = (Q[0, 0] * dx * dx + Q[1, 1] * dy * dy + Q[2, 2] * dz * dz
+              + 2 * (Q[0, 1] * dx * dy + Q[0, 2] * dx * dz + Q[1, 2] * dy * dz))
+        iz, iy, ix = np.nonzero(m2 < k2 - BAND)
+        keys = (ia + ix) // bxy + nbx * ((ja + iy) // bxy + nby * ((ka + iz) // bz))
+        sure.update((int(key), i) for key in np.unique(keys))
+    return sure, box
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (8, 32), (16, 16)])
+def test_kept_bricks_hold_the_support_and_lie_in_the_box(shape):
+    g, torch = _lib()
+    grid = F.Grid(100, 90, 70, -4, 2, 7)
+    n = 1500
+    k = 3.0
+    print(f"kept bricks {grid} n={n} shape {shape}", flush=True)
+    p = _params(n, grid, 5, (0.6, 4.0))
+    ctx = g.Context(k=k, brick=shape[0], brick_z=shape[1])
+    P = g.Params(ctx, n).upload(p)
+    ek, ev, sk, sv, start = g.bin_pairs(ctx, P, g.Grid(grid.nx, grid.ny, grid.nz, grid.x0,
+                                                       grid.y0, grid.z0))
+    kept = set(zip(ek.tolist(), ev.tolist()))
+    assert len(kept) == ek.size
+    sure, box = _support_and_box_bricks(p, grid, k, shape[0], shape[1])
+    missing = sure - kept
+    extra = kept - box
+    print(f"kept {len(kept)}, surely in support {len(sure)}, box {len(box)}", flush=True)
+    assert not missing, sorted(missing)[:10]
+    assert not extra, sorted(extra)[:10]
+    # culling removes a real share of the box bricks
+    assert len(kept) < 0.95 * len(box)
