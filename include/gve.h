@@ -179,6 +179,28 @@ gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field
                          float* d_grad, double* h_loss);
 
 /*
+ * Allocation-free loss and gradient, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and errors as gve_loss_grad, but
+ * every work buffer of the call (volume descriptor, pair lists, sort and scan
+ * buffers, per-brick losses, deterministic partial sums) is carved from a
+ * fixed device array of GVE_STATIC_SCRATCH_BYTES that the library holds on
+ * each device from its first gve_create there until the process ends; the
+ * call itself allocates and frees nothing.  The gradient accumulators and
+ * caches of p (allocated by gve_params_create) are used as by gve_loss_grad.
+ * A workload whose buffers do not fit (roughly: 16 bytes per (primitive,
+ * brick) pair, 40 more with deterministic sums, plus 4 per primitive and
+ * 8 per brick) returns GVE_ERR_UNSUPPORTED with the size it needs, before
+ * anything is written to d_grad or *h_loss.  The array is shared by every
+ * context on a device and keeps the last call's contents: calls of this
+ * entry point that overlap in time on one device (other threads, or other
+ * streams that have not finished) race; calls on one stream are ordered.
+ */
+#define GVE_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+gve_status gve_loss_grad_static(gve_ctx* ctx, const gve_params* p, const float* d_field,
+                                gve_grid g, float* d_grad, double* h_loss);
+
+/*
  * Dense reference evaluation (Sec. III-G: the cost of testing every
  * primitive-sample pair is what binning removes).  Same result as
  * gve_evaluate, Vhat on every voxel of g into d_out [nz][ny][nx] (caller-owned

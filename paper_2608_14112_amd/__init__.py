@@ -115,6 +115,7 @@ _SIGS = {
     "gve_params_set_step": [_vp, _i64],
     "gve_evaluate": [_vp, _vp, GridC, _vp],
     "gve_loss_grad": [_vp, _vp, _vp, GridC, _vp, ctypes.POINTER(ctypes.c_double)],
+    "gve_loss_grad_static": [_vp, _vp, _vp, GridC, _vp, ctypes.POINTER(ctypes.c_double)],
     "gve_dense_evaluate": [_vp, _vp, GridC, _vp],
     "gve_dense_loss_grad": [_vp, _vp, _vp, GridC, _vp, ctypes.POINTER(ctypes.c_double)],
     "gve_adam_step": [_vp, _vp, _vp],
@@ -383,6 +384,20 @@ def loss_grad(ctx: Context, params: Params, field, grid: Grid, grad=None, want_l
     L = ctypes.c_double(0.0)
     _check(_lib.gve_loss_grad(ctx.handle, params.handle, _ptr(field, torch.float32, n), grid.c(),
                               gp, ctypes.byref(L) if want_loss else None), ctx.handle)
+    return L.value if want_loss else None
+
+
+def loss_grad_static(ctx: Context, params: Params, field, grid: Grid, grad=None, want_loss=True):
+    """gve_loss_grad_static: gve_loss_grad with every work buffer taken from the
+    library's fixed device array (no device allocation in the call)."""
+    import torch
+
+    n = grid.nx * grid.ny * grid.nz
+    gp = _ptr(grad, torch.float32, NPARAM * params.n) if grad is not None else None
+    L = ctypes.c_double(0.0)
+    _check(_lib.gve_loss_grad_static(ctx.handle, params.handle, _ptr(field, torch.float32, n),
+                                     grid.c(), gp, ctypes.byref(L) if want_loss else None),
+           ctx.handle)
     return L.value if want_loss else None
 
 

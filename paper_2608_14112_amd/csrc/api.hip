@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -11,6 +12,15 @@
 #include "common.h"
 
 using gve::Scratch;
+
+// Device memory of the allocation-free entry point (gve_loss_grad_static):
+// every workspace buffer of one loss-and-gradient call is carved from it.
+// Each device the library runs on holds its own copy until the process ends;
+// host code reaches a device's copy only through the address that
+// hipGetSymbolAddress returns for it (scratch_address below).
+constexpr size_t kStaticScratchBytes = GVE_STATIC_SCRATCH_BYTES;
+static_assert(kStaticScratchBytes % 256 == 0, "static scratch size");
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -40,6 +50,26 @@ __global__ void k_zero_cols(float* __restrict__ p, int64_t ld, int64_t off, int6
     p[(i / cnt) * ld + off + i % cnt] = 0.0f;
 }
 
+// Address of `scratch` on each device, resolved once per device with that
+// device current (gve_create).  A failed lookup is remembered as its error.
+std::mutex g_scratch_mu;
+std::map<int, std::pair<void*, hipError_t>> g_scratch_addr;
+
+void resolve_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr.count(device)) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_addr[device] = std::make_pair(e == hipSuccess ? ptr : nullptr, e);
+}
+
+std::pair<void*, hipError_t> scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it == g_scratch_addr.end()) return std::make_pair(nullptr, hipErrorNotInitialized);
+  return it->second;
+}
+
 gve_status fail(const gve_ctx* ctx, gve_status st, const std::string& msg) {
   if (ctx) const_cast<gve_ctx*>(ctx)->last_error = msg;
   return st;
@@ -63,9 +93,25 @@ gve_status from_hip(const gve_ctx* ctx, hipError_t e, const char* what) {
     if (s_ != GVE_OK) return s_;         \
   } while (0)
 
+// A buffer of the allocation-free entry point: the next 256-byte aligned
+// piece of the context's fixed region, or UNSUPPORTED when it does not fit.
+gve_status carve(gve_ctx* ctx, Scratch& s, size_t bytes) {
+  const size_t off = (ctx->arena_used + 255) & ~(size_t)255;
+  if (bytes > ctx->arena_cap || off > ctx->arena_cap - bytes)
+    return fail(ctx, GVE_ERR_UNSUPPORTED,
+                "the workload needs more than the " + std::to_string(ctx->arena_cap >> 20) +
+                    " MiB of static scratch of the allocation-free entry point (at least " +
+                    std::to_string((off + bytes + 1048575) >> 20) + " MiB)");
+  s.ptr = ctx->arena_base + off;
+  s.bytes = bytes;
+  ctx->arena_used = off + bytes;
+  return GVE_OK;
+}
+
 // Grow-only device buffer.  Synchronises before freeing the old allocation.
 gve_status ensure(gve_ctx* ctx, Scratch& s, size_t bytes) {
   if (s.bytes >= bytes && s.ptr) return GVE_OK;
+  if (ctx->arena_base) return carve(ctx, s, bytes);
   if (s.ptr) {
     TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
     TRY_HIP(ctx, hipFree(s.ptr));
@@ -513,6 +559,7 @@ gve_status gve_create(gve_ctx** out, const gve_options* opt, void* hip_stream) {
     delete ctx;
     return GVE_ERR_DEVICE;
   }
+  resolve_scratch(ctx->device);
   *out = ctx;
   return GVE_OK;
 }
@@ -698,6 +745,47 @@ gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field
     if (!std::isfinite(*h_loss)) return fail(ctx, GVE_ERR_NUMERIC, "loss is not finite");
   }
   return GVE_OK;
+}
+
+namespace {
+
+// For the duration of one allocation-free call: the context works on an empty
+// workspace whose buffers are carved from the device's static scratch (the
+// host staging buffer is shared), with its own host copy of the volume
+// descriptors; the context's own workspace and descriptors are restored on
+// every exit.
+struct StaticScope {
+  gve_ctx* ctx;
+  gve::Workspace saved;
+  std::vector<gve::ItemDesc> saved_items;
+  StaticScope(gve_ctx* c, void* base) : ctx(c), saved(c->ws) {
+    saved_items.swap(ctx->items_host);
+    gve::Workspace fresh;
+    fresh.h_pinned = saved.h_pinned;
+    ctx->ws = fresh;
+    ctx->arena_base = static_cast<char*>(base);
+    ctx->arena_cap = kStaticScratchBytes;
+    ctx->arena_used = 0;
+  }
+  ~StaticScope() {
+    ctx->ws = saved;
+    ctx->items_host.swap(saved_items);
+    ctx->arena_base = nullptr;
+    ctx->arena_cap = ctx->arena_used = 0;
+  }
+};
+
+}  // namespace
+
+gve_status gve_loss_grad_static(gve_ctx* ctx, const gve_params* p, const float* d_field,
+                                gve_grid g, float* d_grad, double* h_loss) {
+  TRY(check_ctx_params(ctx, p));
+  const auto addr = scratch_address(ctx->device);
+  if (!addr.first)
+    return from_hip(ctx, addr.second == hipSuccess ? hipErrorInvalidSymbol : addr.second,
+                    "static scratch address (hipGetSymbolAddress)");
+  StaticScope scope(ctx, addr.first);
+  return gve_loss_grad(ctx, p, d_field, g, d_grad, h_loss);
 }
 
 gve_status gve_dense_evaluate(gve_ctx* ctx, const gve_params* p, gve_grid g, float* d_out) {

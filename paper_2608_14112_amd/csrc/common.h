@@ -104,6 +104,10 @@ struct gve_ctx {
   std::vector<gve::ItemDesc> items_host;  // copy of ws.items (what the device holds)
   std::map<std::pair<int, int>, int> resident;  // brick shape -> resident fused workgroups
   std::map<std::array<int, 4>, std::array<int, 3>> tuned;  // autotuner cache
+  // While set, workspace buffers are carved from this fixed device region
+  // (the allocation-free entry point) instead of being allocated.
+  char* arena_base = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
 };
 
 struct gve_params {
