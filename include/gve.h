@@ -27,9 +27,13 @@
  *    device); "h_" pointers are host pointers.  The caller owns every buffer it
  *    passes and must keep it alive until the stream has executed the work.
  *  - Work is queued on the context's stream.  Calls that write host memory
- *    (h_ outputs) synchronise that stream before returning; the others are
- *    asynchronous except for one small device-to-host read of the pair count
- *    per evaluation (the binning below sizes its buffers from it).
+ *    (h_ outputs) synchronise that stream before returning.  The others queue
+ *    their kernels asynchronously, but each binning of the primitives (every
+ *    evaluation, loss, gradient and refinement iteration) waits for two small
+ *    device-to-host reads on the stream (the totals of box and kept
+ *    (primitive, brick) pairs, from which the pair buffers are sized), and a
+ *    call whose grids or brick shape differ from the previous call's also
+ *    waits for the upload of its volume descriptors.
  *  - A context is not thread-safe; use one per host thread.  Contexts own
  *    device scratch that grows as needed and is released by gve_destroy.
  */
@@ -115,6 +119,17 @@ typedef struct gve_stats {
    * (gve_params: 4 [11][n] arrays + a 64-byte record, 16 accumulators and
    * two counts per primitive). */
   int64_t workspace_bytes;
+  /* Work of the last counting pass (gve_count_pairs, Sec. III-G): P_in =
+   * (primitive, voxel) pairs with m^2 < k^2 inside the grid (the algorithmic
+   * work), P_cand = lane-voxel evaluations the brick kernels perform, and the
+   * (primitive, brick) pairs whose support meets their brick (one gradient
+   * atomic instruction each in the default mode). */
+  int64_t n_in_support;
+  int64_t n_candidates;
+  int64_t n_atomics;
+  /* Parameters found non-finite after an Adam step (cumulative); gve_refine
+   * returns GVE_ERR_NUMERIC when its steps add to it. */
+  int64_t n_nonfinite;
 } gve_stats;
 
 typedef struct gve_ctx gve_ctx;
@@ -283,14 +298,14 @@ gve_status gve_allocate(gve_ctx* ctx, const float* d_field, gve_grid g, int64_t 
 gve_status gve_normalize(gve_ctx* ctx, float* d_field, int64_t n);
 
 /*
- * Full-precision export (Sec. III-H, Sec. III-I eq:size): a fixed header of
+ * Full-precision export (Sec. III-I; Sec. III-J eq:size): a fixed header of
  * GVE_EXPORT_HEADER bytes followed by 48 bytes per primitive: twelve float32
  * (position 3, log-scale 3, quaternion w x y z 4, scalar attribute a, weight
  * w), so S_enc = 48 N + H.  This library's single weight c maps to a = c,
  * w = 1.  The header holds a magic "GVE1", version 1, N, the grid (6 int64),
  * k, the value range [vmin, vmax] of the normalised field (Sec. III-B), and a
  * default 256-entry RGBA float32 transfer-function table (grey ramp, opacity
- * equal to the value; the renderer applies its own, Sec. III-D) at byte 256;
+ * equal to the value; the renderer applies its own, Sec. III-I) at byte 256;
  * the rest of the header is reserved (zero).  The header's size is the H that
  * the compression ratios printed in Sec. V-A/V-B imply (7,000 bytes).
  * gve_export writes exactly gve_export_size(n) bytes into h_buf (host,
@@ -306,7 +321,7 @@ gve_status gve_import(gve_ctx* ctx, const void* h_buf, size_t buf_bytes, gve_par
                       gve_grid* g_out);
 
 /*
- * Checkpoint / resume (Sec. III-H: periodic checkpoints hold the full
+ * Checkpoint / resume (Sec. III-I: periodic checkpoints hold the full
  * primitive state and accumulated timing, so an interrupted run resumes
  * without repeating allocation).  The buffer holds parameters, both Adam
  * moments, the Adam step and the caller's accumulated seconds; resuming and

@@ -261,22 +261,36 @@ def loss_grad(params, field, grid: Grid, k, return_parts=False):
       dL/dq_n = <dL/dR, dR/dq_n>  (R quadratic in the unit quaternion)
       dL/dq   = (I - q_n q_n^T) dL/dq_n / |q|
     """
+    fld = np.asarray(field, dtype=np.float64).reshape(grid.shape)
+    V, _ = evaluate_windowed(params, grid, k)
+    res = V - fld
+    L = float(np.sum(res * res))
+    grad, parts = grad_from_residual(params, 2.0 * res, grid, k)
+    if return_parts:
+        return L, grad, parts
+    return L, grad
+
+
+def grad_from_residual(params, r, grid: Grid, k, window=True):
+    """The gradient sums of ``loss_grad`` for a given residual r = dL/dV_k
+    (for the squared error, 2 (V_k - V)) on every voxel: returns
+    (dL/dtheta (11, N), the ten per-primitive sums (10, N)).  The primitives
+    enter only through their own pairs, so a subset of the primitives gets
+    exactly its part of the full gradient.  ``window=False`` visits every
+    voxel of the grid for every primitive (brute force) instead of its
+    support box; out-of-support pairs then add exact zeros."""
     mu, q, ell, c = split(params)
     qn, qnorm, qok = normalize_quat(q)
     R = rotation(qn)
     P = precision(params)
     S = covariance(params)
     k2 = float(k) * float(k)
-    fld = np.asarray(field, dtype=np.float64).reshape(grid.shape)
-    V, _ = evaluate_windowed(params, grid, k)
-    res = V - fld
-    L = float(np.sum(res * res))
-    r = 2.0 * res
     N = mu.shape[0]
     grad = np.zeros((NPARAM, N))
     parts = np.zeros((10, N))
+    full = ((0, grid.nx - 1), (0, grid.ny - 1), (0, grid.nz - 1))
     for i in range(N):
-        box = support_box(mu[i], S[i], k, grid)
+        box = support_box(mu[i], S[i], k, grid) if window else full
         if box is None:
             continue
         dx, dy, dz = _box_offsets(box, mu[i], grid)
@@ -304,9 +318,17 @@ def loss_grad(params, field, grid: Grid, k, return_parts=False):
             proj = np.eye(4) - np.outer(qn[i], qn[i])
             grad[3:7, i] = proj @ dqn / qnorm[i]
         grad[10, i] = Se
-    if return_parts:
-        return L, grad, parts
-    return L, grad
+    return grad, parts
+
+
+def loss_grad_bruteforce(params, field, grid: Grid, k):
+    """``loss_grad`` visiting every (primitive, voxel) pair of the grid: the
+    field by ``evaluate_bruteforce``, the gradient by ``grad_from_residual``
+    without support boxes."""
+    fld = np.asarray(field, dtype=np.float64).reshape(grid.shape)
+    res = evaluate_bruteforce(params, grid, k) - fld
+    grad, _ = grad_from_residual(params, 2.0 * res, grid, k, window=False)
+    return float(np.sum(res * res)), grad
 
 
 def loss_grad_absolute(params, field, grid: Grid, k):
@@ -500,10 +522,10 @@ def sampled_mse(pred, field, n, seed):
 
 
 def encoded_bytes(n, header_bytes):
-    """Full-precision encoded size, Sec. III-I eq:size: 48 N + H."""
+    """Full-precision encoded size, Sec. III-J eq:size: 48 N + H."""
     return 48 * int(n) + int(header_bytes)
 
 
 def compression_ratio(n_voxels, bytes_per_voxel, n, header_bytes):
-    """Sec. III-I eq:cr: S_src / S_enc(N)."""
+    """Sec. III-J eq:cr: S_src / S_enc(N)."""
     return n_voxels * bytes_per_voxel / encoded_bytes(n, header_bytes)

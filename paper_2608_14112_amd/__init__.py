@@ -84,7 +84,9 @@ class StatsC(ctypes.Structure):
                 ("iterations", ctypes.c_int64), ("last_loss", ctypes.c_double),
                 ("timed_iterations", ctypes.c_int64), ("ms_bin", ctypes.c_double),
                 ("ms_fused", ctypes.c_double), ("ms_update", ctypes.c_double),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64), ("n_in_support", ctypes.c_int64),
+                ("n_candidates", ctypes.c_int64), ("n_atomics", ctypes.c_int64),
+                ("n_nonfinite", ctypes.c_int64)]
 
 
 class AllocInfoC(ctypes.Structure):

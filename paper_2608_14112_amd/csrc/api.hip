@@ -124,9 +124,10 @@ gve_status ensure(gve_ctx* ctx, Scratch& s, size_t bytes) {
   return GVE_OK;
 }
 
-// Small device block: [0] loss (double), [2] clamp count (u64), [4 ..] small
-// counters, [16 ..] loss-reduction partials, then kTotalSlots pair-total
-// counters (u64).  Zeroed when first allocated.
+// Small device block: [0] loss (double), [2] clamp count and [3] non-finite
+// parameter count (u64, cumulative), [4 .. 6] work counters of the counting
+// pass, [16 ..] loss-reduction partials, then kTotalSlots pair-total counters
+// (u64).  Zeroed when first allocated.
 gve_status ensure_dloss(gve_ctx* ctx) {
   if (ctx->ws.dloss.ptr) return GVE_OK;
   const size_t nd = 16 + gve::loss_reduce_tmp_doubles() + gve::kTotalSlots;
@@ -1052,13 +1053,17 @@ gve_status gve_count_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, int64_
   Binned bn;
   TRY(bin(ctx, p, g, &bn));
   unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ctx->ws.dloss.ptr) + 4;
-  TRY_HIP(ctx, gve::fill_u64(cnt, 2, ctx->stream));
+  TRY_HIP(ctx, gve::fill_u64(cnt, 3, ctx->stream));
   TRY_HIP(ctx, gve::launch_count(p->rec, bn.gid, bn.start, bn.items, bn.nitems, bn.bg, ctx->opt.k,
                                  cnt, ctx->stream));
-  TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, cnt, 16, hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, cnt, 24, hipMemcpyDeviceToHost, ctx->stream));
   TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  *h_in_support = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[0];
-  *h_candidates = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[1];
+  const unsigned long long* hc = static_cast<unsigned long long*>(ctx->ws.h_pinned);
+  *h_in_support = (int64_t)hc[0];
+  *h_candidates = (int64_t)hc[1];
+  ctx->stats.n_in_support = (int64_t)hc[0];
+  ctx->stats.n_candidates = (int64_t)hc[1];
+  ctx->stats.n_atomics = (int64_t)hc[2];
   return GVE_OK;
 }
 
@@ -1158,14 +1163,22 @@ gve_status refine_vol(gve_ctx* ctx, gve_params* p, const float* d_field, const V
     ctx->stats.ms_update = tu;
   }
   if (iters > 0) {
-    TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, clamp_counter(ctx), sizeof(unsigned long long),
-                                hipMemcpyDeviceToHost, ctx->stream));
+    TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, clamp_counter(ctx),
+                                2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                ctx->stream));
     if (h_loss_hist) {
       TRY_HIP(ctx, hipMemcpyAsync(h_loss_hist, hist, sizeof(double) * nl, hipMemcpyDeviceToHost,
                                   ctx->stream));
     }
     TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    ctx->stats.n_clamped = (int64_t) * static_cast<unsigned long long*>(ctx->ws.h_pinned);
+    const unsigned long long* hc = static_cast<unsigned long long*>(ctx->ws.h_pinned);
+    ctx->stats.n_clamped = (int64_t)hc[0];
+    const int64_t bad_before = ctx->stats.n_nonfinite;
+    ctx->stats.n_nonfinite = (int64_t)hc[1];
+    if (ctx->stats.n_nonfinite > bad_before)
+      return fail(ctx, GVE_ERR_NUMERIC,
+                  std::to_string(ctx->stats.n_nonfinite - bad_before) +
+                      " parameter values became non-finite during refinement");
     if (h_loss_hist) {
       double last = 0.0;
       for (int i = 0; i < vol.n; ++i) last += h_loss_hist[(size_t)(iters - 1) * vol.n + i];
@@ -1890,13 +1903,17 @@ gve_status gve_batch_count_pairs(gve_ctx* ctx, const gve_batch* b, int64_t* h_in
   Binned bn;
   TRY(bin_vol(ctx, b->params, vol_of(b), &bn));
   unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ctx->ws.dloss.ptr) + 4;
-  TRY_HIP(ctx, gve::fill_u64(cnt, 2, ctx->stream));
+  TRY_HIP(ctx, gve::fill_u64(cnt, 3, ctx->stream));
   TRY_HIP(ctx, gve::launch_count(b->params->rec, bn.gid, bn.start, bn.items, bn.nitems, bn.bg,
                                  ctx->opt.k, cnt, ctx->stream));
-  TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, cnt, 16, hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, cnt, 24, hipMemcpyDeviceToHost, ctx->stream));
   TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  *h_in_support = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[0];
-  *h_candidates = (int64_t) static_cast<unsigned long long*>(ctx->ws.h_pinned)[1];
+  const unsigned long long* hc = static_cast<unsigned long long*>(ctx->ws.h_pinned);
+  *h_in_support = (int64_t)hc[0];
+  *h_candidates = (int64_t)hc[1];
+  ctx->stats.n_in_support = (int64_t)hc[0];
+  ctx->stats.n_candidates = (int64_t)hc[1];
+  ctx->stats.n_atomics = (int64_t)hc[2];
   return GVE_OK;
 }
 

@@ -326,7 +326,8 @@ hipError_t mlp_apply_delta(float* theta, const float* base, const float* Y, int6
                            const float* tmean, const float* tstd, float alpha, hipStream_t s);
 
 // mode 0: chain rule -> grad_out ([11][n]); mode 1: chain rule + Adam;
-// mode 2: Adam from grad_in.  In modes 0 and 1 the ten sums come from acc
+// mode 2: Adam from grad_in.  In modes 1 and 2 clamp_count[0] counts the
+// log-scale entries clamped and clamp_count[1] the parameters left non-finite.  In modes 0 and 1 the ten sums come from acc
 // (zeroed after use) or, when part is given, from the primitive's partials
 // part[offset[i] .. offset[i+1]) summed in order.
 hipError_t launch_update(int mode, float* theta, float* m, float* v, float* acc,

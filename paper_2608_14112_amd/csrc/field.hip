@@ -651,7 +651,8 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused_queue(const Record* __restri
 // Work counters of one evaluation: [0] in-support (primitive, voxel) pairs
 // inside the grid (m^2 < k^2), [1] lane-voxel evaluations the brick kernels
 // perform after their wave-level skips (the candidate pairs, masked lanes
-// included).
+// included), [2] (primitive, brick) pairs with an active step in some wave of
+// the brick (the pairs whose gradient sums the fused kernel adds atomically).
 template <int BXY, int BZ>
 __global__ __launch_bounds__(BXY* BXY) void k_count(const Record* __restrict__ rec,
                                                 const uint32_t* __restrict__ pair_gid,
@@ -659,20 +660,35 @@ __global__ __launch_bounds__(BXY* BXY) void k_count(const Record* __restrict__ r
                                                 const ItemDesc* __restrict__ items, int nitems,
                                                 float thr,
                                                 unsigned long long* __restrict__ counts) {
+  constexpr int kWaves = (BXY * BXY + 63) / 64;
+  __shared__ uint32_t any[kWaves];
   const uint32_t b = blockIdx.x;
   const Site st = site_of<BXY, BZ>(items, nitems, b);
   const uint64_t cols = __builtin_amdgcn_ballot_w64(st.col_in);
-  unsigned long long nin = 0, ncand = 0;
+  const int wave = threadIdx.x >> 6;
+  unsigned long long nin = 0, ncand = 0, npair = 0;
   for (uint32_t j = brick_start[b]; j < brick_start[b + 1]; ++j) {
     const Record r = load_record(rec, __builtin_amdgcn_readfirstlane(pair_gid[j]));
     const ColumnSetup s = column_setup<BZ>(r, st.px, st.py, st.pz0, st.iz0);
-    if (!column_hit<BZ>(s, r.sz, cols, thr)) continue;
-    for (int zz = s.za; zz <= s.zb; ++zz) {
-      const float q = quad_w(s, w_at<BZ>(s, r.sz, zz));
-      if (__builtin_amdgcn_ballot_w64(q > thr) == 0ull) continue;
-      ncand += 1;
-      nin += (st.col_in && zz < st.zrem && q > thr) ? 1 : 0;
+    uint32_t active = 0u;
+    if (column_hit<BZ>(s, r.sz, cols, thr)) {
+      for (int zz = s.za; zz <= s.zb; ++zz) {
+        const float q = quad_w(s, w_at<BZ>(s, r.sz, zz));
+        if (__builtin_amdgcn_ballot_w64(q > thr) == 0ull) continue;
+        active = 1u;
+        ncand += 1;
+        nin += (st.col_in && zz < st.zrem && q > thr) ? 1 : 0;
+      }
     }
+    // every wave of the brick walks the same pairs, so the barriers match
+    if ((threadIdx.x & 63) == 0) any[wave] = active;
+    if (kWaves > 1) __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t a = 0u;
+      for (int w = 0; w < kWaves; ++w) a |= any[w];
+      npair += a;
+    }
+    if (kWaves > 1) __syncthreads();
   }
   nin = wave_sum_u64(nin);
   ncand = wave_sum_u64(ncand);
@@ -680,6 +696,7 @@ __global__ __launch_bounds__(BXY* BXY) void k_count(const Record* __restrict__ r
     atomicAdd(&counts[0], nin);
     atomicAdd(&counts[1], ncand);
   }
+  if (threadIdx.x == 0 && npair) atomicAdd(&counts[2], npair);
 }
 
 // Deterministic two-level sum of the per-brick losses in double precision.

@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kThreads) void k_update(int mode, float* __restrict
                                                      AdamCoef ac,
                                                      unsigned long long* __restrict__ nclamp) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  unsigned int clamped = 0;
+  unsigned int clamped = 0, nonfinite = 0;
   if (i < n) {
     float th[11], gr[11];
 #pragma unroll
@@ -81,15 +81,20 @@ __global__ __launch_bounds__(kThreads) void k_update(int mode, float* __restrict
           if (p < ac.lmin) { p = ac.lmin; ++clamped; }
           if (p > ac.lmax) { p = ac.lmax; ++clamped; }
         }
+        nonfinite += isfinite(p) ? 0u : 1u;
         theta[a * n + i] = p;
       }
     }
   }
   if (mode != 0 && nclamp) {
-    unsigned long long c = clamped;
+    unsigned long long c = clamped, b = nonfinite;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(nclamp, c);
+    for (int d = 32; d >= 1; d >>= 1) {
+      c += __shfl_xor(c, d, 64);
+      b += __shfl_xor(b, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&nclamp[0], c);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&nclamp[1], b);
   }
 }
 

@@ -340,3 +340,46 @@ def test_refine_trajectory_matches_oracle(deterministic):
     got = p.download().astype(np.float64)
     assert np.max(np.abs(got - ref_p)) < 1e-3
     assert p.step == 20 and losses[-1] < losses[0]
+
+
+@pytest.mark.parametrize("deterministic", [True, False])
+def test_refine_reports_non_finite_parameters_without_a_loss_history(deterministic):
+    """A NaN weight planted from the host spreads through the residual to the
+    gradients of every primitive it overlaps; the update counts the parameters
+    it leaves non-finite and gve_refine returns NUMERIC even when no loss
+    history is requested.  (The kernels take NaN arithmetic without faults: a
+    NaN in mu or a scale gives an empty box, a NaN weight changes only values.)"""
+    g, torch = _lib()
+    grid = F.Grid(40, 36, 33)
+    params = _case(80, grid, 4).astype(np.float32)
+    params[10, 5] = np.nan
+    field = np.random.default_rng(3).uniform(size=grid.shape).astype(np.float32)
+    ctx = g.Context(k=3.0, deterministic=deterministic)
+    p = g.Params(ctx, 80).upload(params)
+    gg = g.Grid(grid.nx, grid.ny, grid.nz, grid.x0, grid.y0, grid.z0)
+    assert ctx.stats()["n_nonfinite"] == 0
+    with pytest.raises(g.GveError) as e:
+        g.refine(ctx, p, torch.from_numpy(field).cuda(), gg, 2, want_losses=False)
+    assert e.value.status == g.NUMERIC
+    st = ctx.stats()
+    assert st["n_nonfinite"] > 0
+    # counted per step: at least the entries non-finite now
+    assert np.count_nonzero(~np.isfinite(p.download())) <= st["n_nonfinite"]
+    # a finite set on the same context refines without the error
+    q = g.Params(ctx, 80).upload(np.nan_to_num(params, nan=0.1))
+    g.refine(ctx, q, torch.from_numpy(field).cuda(), gg, 2, want_losses=False)
+    assert ctx.stats()["n_nonfinite"] == st["n_nonfinite"]
+
+
+def test_count_pairs_fills_the_work_counters():
+    g, torch = _lib()
+    grid = F.Grid(37, 29, 21, 3, -2, 5)
+    params = _case(60, grid, 0)
+    ctx = g.Context(k=3.0)
+    p = g.Params(ctx, 60).upload(params.astype(np.float32))
+    nin, ncand = g.count_pairs(ctx, p, g.Grid(grid.nx, grid.ny, grid.nz, grid.x0, grid.y0,
+                                              grid.z0))
+    st = ctx.stats()
+    assert st["n_in_support"] == nin and st["n_candidates"] == ncand
+    assert 0 < st["n_atomics"] <= st["n_overlaps"]
+    assert nin <= ncand <= 64 * 32 * st["n_atomics"]

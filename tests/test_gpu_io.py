@@ -1,4 +1,4 @@
-"""Export (Sec. III-H, eq:size) and checkpoint/resume on the device library.
+"""Export (Sec. III-I; Sec. III-J eq:size) and checkpoint/resume on the device library.
 
 The export is checked field by field against the parameters it was written
 from (its layout: twelve float32 per primitive, position, log-scale,

@@ -410,3 +410,24 @@ def test_count_pairs_cut_is_strict_on_lattice_boundary_points():
     assert F.count_pairs(p, grid, 3.0) == 93
     V = F.evaluate_bruteforce(p, grid, 3.0)
     assert np.count_nonzero(V) == 93
+
+
+def test_bruteforce_gradient_equals_windowed_and_splits_over_primitives():
+    """Visiting every voxel adds only exact zeros outside each support box, so
+    the brute-force loss and gradient equal the windowed ones (up to the
+    summation order of the sums); and with the residual held fixed each
+    primitive's gradient depends only on its own pairs."""
+    grid = F.Grid(13, 11, 9, 1, -2, 0)
+    params = S.random_params(7, (13, 11, 9), seed=5, scale_range=(0.6, 2.5), unit_quat=False)
+    params[0] += grid.x0 + np.array([-2.0, 0, 0, 3.0, 0, 0, 0])
+    params[1] += grid.y0
+    field = np.random.default_rng(6).uniform(size=grid.shape)
+    L, g = F.loss_grad(params, field, grid, 3.0)
+    Lb, gb = F.loss_grad_bruteforce(params, field, grid, 3.0)
+    assert abs(Lb - L) <= 1e-13 * L
+    assert np.allclose(gb, g, rtol=1e-12, atol=1e-13 * np.max(np.abs(g)))
+    V, _ = F.evaluate_windowed(params, grid, 3.0)
+    r = 2.0 * (V - field)
+    ga, _ = F.grad_from_residual(params[:, :3], r, grid, 3.0)
+    gz, _ = F.grad_from_residual(params[:, 3:], r, grid, 3.0)
+    assert np.array_equal(np.concatenate([ga, gz], axis=1), g)

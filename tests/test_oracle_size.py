@@ -1,6 +1,6 @@
 """Pin of the storage-size helper against the figures the paper prints.
 
-Sec. III-I gives S_enc = 48 N + H (eq:size) and CR = S_src / S_enc (eq:cr);
+Sec. III-J gives S_enc = 48 N + H (eq:size) and CR = S_src / S_enc (eq:cr);
 Sec. V-A/V-B print the resulting ratios and sizes (fixture tests/golden/
 compression_ratios.json, with its citation).  H is not printed: the three
 2,000-primitive ratios put it near 7 kB.
