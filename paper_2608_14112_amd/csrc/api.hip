@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "common.h"
+#include "devmath.h"
 
 using gve::Scratch;
 
@@ -1451,13 +1452,6 @@ gve_status mlp_bwd(gve_ctx* ctx, const gve_mlp* m, const float* Xs, int64_t rows
   return GVE_OK;
 }
 
-uint64_t host_mix64(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 // Loss L of p on the field (forward + fused pass), read back to the host.
 gve_status eval_loss(gve_ctx* ctx, const gve_params* p, const float* d_field, const gve_grid& g,
                      double* out) {
@@ -1496,7 +1490,7 @@ gve_status gve_mlp_create(gve_ctx* ctx, uint64_t seed, gve_mlp** out) {
   auto fill = [&](int64_t off, int64_t count, int fan_in, uint64_t stream) {
     const double bnd = std::sqrt(6.0 / fan_in);
     for (int64_t i = 0; i < count; ++i) {
-      const uint64_t r = host_mix64(host_mix64(seed ^ (stream * 0xD1B54A32D192ED03ull)) ^ (uint64_t)i);
+      const uint64_t r = gve::hash_bits(seed, stream, (uint64_t)i);
       const double u = (double)((r >> 11) + 1) * 0x1.0p-53;
       h[off + i] = (float)((2.0 * u - 1.0) * bnd);
     }

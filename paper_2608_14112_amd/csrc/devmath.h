@@ -12,14 +12,16 @@ namespace gve {
 
 // SplitMix64 finaliser (Steele, Lea and Flood, 2014) applied to a counter:
 // 64 random bits for (seed, stream, idx), and a double uniform in (0, 1].
-static __device__ inline uint64_t splitmix64(uint64_t x) {
+// The one definition of the library's counter generator (host and device).
+static __host__ __device__ inline uint64_t splitmix64(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
 
-static __device__ inline uint64_t hash_bits(uint64_t seed, uint64_t stream, uint64_t idx) {
+static __host__ __device__ inline uint64_t hash_bits(uint64_t seed, uint64_t stream,
+                                                     uint64_t idx) {
   return splitmix64(splitmix64(seed ^ (stream * 0xD1B54A32D192ED03ull)) ^ idx);
 }
 

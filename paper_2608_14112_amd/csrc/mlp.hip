@@ -223,19 +223,12 @@ __global__ void k_standardize(const float* __restrict__ X, const uint32_t* __res
   out[i] = (X[(size_t)src * cols + c] - mean[c]) / stdv[c];
 }
 
-__device__ inline uint64_t mix64(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 // Random 32-bit keys and identity values for an epoch's permutation.
 __global__ void k_perm_keys(uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t n,
                             uint64_t seed, uint64_t epoch) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  keys[i] = (uint32_t)(mix64(mix64(seed ^ (epoch * 0xD1B54A32D192ED03ull)) ^ (uint64_t)i) >> 32);
+  keys[i] = (uint32_t)(hash_bits(seed, epoch, (uint64_t)i) >> 32);
   vals[i] = (uint32_t)i;
 }
 
