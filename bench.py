@@ -644,9 +644,16 @@ def _timed_refine(g, torch, ctx, P, field, grid, iters):
     return e0.elapsed_time(e1) / 1e3, losses
 
 
+def _tuned(ctx):
+    o = ctx.options
+    return {"brick": [o.brick, o.brick, o.brick_z],
+            "schedule": ["brick order", "XCD chunks", "persistent queue"][o.schedule]}
+
+
 def other_configs(g, torch, args, ws_pairs):
     """The tiny (64^3 x 2,048, 20 iterations, lr 1e-3) and mid (256^3 x 65,536,
-    1,000 iterations) workloads: seconds, s/iter and full-grid PSNR.  Appends
+    1,000 iterations) workloads: seconds, s/iter and full-grid PSNR, each with
+    the brick shape and schedule that gve_autotune picks for it (timed apart).  Appends
     the mid workload's (features, 300-iteration targets) to ws_pairs.  Returns
     (report, cpu jobs' inputs)."""
     import paper_2608_14112_amd.warm as W
@@ -660,6 +667,9 @@ def other_configs(g, torch, args, ws_pairs):
     ctx = g.Context(k=args.k, lr=1e-3, ell_min=math.log(0.25), ell_max=math.log(4.0))
     P, _ = g.allocate(ctx, ft, grid, 2048, args.seed)
     cpu_inputs["tiny"] = (P.download(), f, (64, 64, 64, 0, 0, 0), 1e-3)
+    t0 = time.perf_counter()
+    g.autotune(ctx, ft, params=P, grid=grid, reps=3)   # few bricks: the shape matters here
+    t_tune = time.perf_counter() - t0
     g.refine(ctx, _clone(g, ctx, P), ft, grid, 3)            # kernels loaded, buffers sized
     sec, losses = _timed_refine(g, torch, ctx, P, ft, grid, 20)
     Lf = g.loss_grad(ctx, P, ft, grid)
@@ -667,6 +677,7 @@ def other_configs(g, torch, args, ws_pairs):
     out["tiny"] = {"workload": "64^3 signed mixture of 200 Gaussians + 0.01 noise, min-max "
                                "normalised; 2,048 Gaussians from allocation; lr 1e-3",
                    "iterations": 20, "seconds": sec, "s_per_iter": sec / 20,
+                   "tuned": _tuned(ctx), "autotune_seconds": t_tune,
                    "psnr_start_db": W.psnr(losses[0], M), "psnr_final_db": W.psnr(Lf, M)}
     # mid
     f2 = S.spectral_field((256, 256, 256), args.seed, device="cuda")
@@ -676,6 +687,9 @@ def other_configs(g, torch, args, ws_pairs):
     cpu_inputs["mid"] = (P2.download(), f2.cpu().numpy(), (256, 256, 256, 0, 0, 0), args.lr)
     X2 = g.features(ctx2, P2, f2, grid2, info2["n_detail"], info2["g99"])
     A2 = _clone(g, ctx2, P2)
+    t0 = time.perf_counter()
+    g.autotune(ctx2, f2, params=P2, grid=grid2, reps=3)
+    t_tune2 = time.perf_counter() - t0
     g.refine(ctx2, _clone(g, ctx2, P2), f2, grid2, 3)
     s300, l300 = _timed_refine(g, torch, ctx2, P2, f2, grid2, 300)
     ws_pairs.append((X2, g.targets(ctx2, A2, P2)))
@@ -686,6 +700,7 @@ def other_configs(g, torch, args, ws_pairs):
                               "(k^-5/3 shell spectrum), min-max normalised; 65,536 Gaussians "
                               "from allocation; lr 8e-3",
                   "iterations": 1000, "seconds": s300 + s700, "s_per_iter": (s300 + s700) / 1000,
+                  "tuned": _tuned(ctx2), "autotune_seconds": t_tune2,
                   "psnr_start_db": W.psnr(l300[0], M2), "psnr_300_db": W.psnr(l700[0], M2),
                   "psnr_final_db": W.psnr(Lf2, M2)}
     for c in (P, P2, A2):

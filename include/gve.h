@@ -29,11 +29,18 @@
  *  - Work is queued on the context's stream.  Calls that write host memory
  *    (h_ outputs) synchronise that stream before returning.  The others queue
  *    their kernels asynchronously, but each binning of the primitives (every
- *    evaluation, loss, gradient and refinement iteration) waits for two small
- *    device-to-host reads on the stream (the totals of box and kept
- *    (primitive, brick) pairs, from which the pair buffers are sized), and a
- *    call whose grids or brick shape differ from the previous call's also
- *    waits for the upload of its volume descriptors.
+ *    evaluation, loss and gradient) waits for two small device-to-host reads
+ *    on the stream (the totals of box and kept (primitive, brick) pairs, from
+ *    which the pair buffers are sized), and a call whose grids or brick shape
+ *    differ from the previous call's also waits for the upload of its volume
+ *    descriptors.  Refinement (gve_refine, gve_batch_refine) waits so only in
+ *    its first iteration: later iterations bin into buffers of the first
+ *    one's size plus a quarter, with the counts kept on the device, and the
+ *    host reads one overflow flag per 64 iterations.  A binning that did not
+ *    fit skips its updates; the call then restores the parameters and Adam
+ *    state saved at the start of those 64 iterations and redoes them with
+ *    buffers sized from the largest totals seen (stats.n_resized counts such
+ *    redos).  The result equals that of synchronous binning.
  *  - A context is not thread-safe; use one per host thread.  Contexts own
  *    device scratch that grows as needed and is released by gve_destroy.
  */
@@ -130,6 +137,9 @@ typedef struct gve_stats {
   /* Parameters found non-finite after an Adam step (cumulative); gve_refine
    * returns GVE_ERR_NUMERIC when its steps add to it. */
   int64_t n_nonfinite;
+  /* Refinements whose asynchronously sized pair buffers overflowed and that
+   * were rolled back and redone with larger buffers (cumulative). */
+  int64_t n_resized;
 } gve_stats;
 
 typedef struct gve_ctx gve_ctx;

@@ -206,7 +206,10 @@ struct Binned {
   const uint32_t* slot = nullptr;  // its emission index (deterministic sums), else null
   const uint32_t* start = nullptr;
   const uint32_t* sorted_keys = nullptr;  // brick key of each sorted pair
-  int64_t npairs = 0;
+  int64_t npairs = 0;      // pairs (-1: counted on the device only)
+  int64_t capacity = 0;    // pairs the buffers hold (>= npairs)
+  int64_t box_total = -1;  // box pairs before culling (synchronous binning)
+  const uint32_t* fits = nullptr;  // device flag of an asynchronous binning
 };
 
 // Volume descriptors on the device for the current brick shape.  The upload
@@ -250,8 +253,37 @@ struct EmitCopy {
   bool fits = false;  // set when the list fitted and was copied
 };
 
+bool same_items(const std::vector<gve::ItemDesc>& a, const std::vector<gve::ItemDesc>& b) {
+  return a.size() == b.size() &&
+         (a.empty() || std::memcmp(a.data(), b.data(), sizeof(gve::ItemDesc) * a.size()) == 0);
+}
+
+// Flags of the asynchronous binning in the small device block: [7] fits
+// (u32) and sticky (u32), [8] the largest box pair total and [9] the largest
+// kept pair total seen (u64).
+uint32_t* fits_flag(gve_ctx* ctx) {
+  return reinterpret_cast<uint32_t*>(static_cast<unsigned long long*>(ctx->ws.dloss.ptr) + 7);
+}
+uint32_t* sticky_flag(gve_ctx* ctx) { return fits_flag(ctx) + 1; }
+unsigned long long* need_slot(gve_ctx* ctx) {
+  return static_cast<unsigned long long*>(ctx->ws.dloss.ptr) + 8;
+}
+unsigned long long* need_pairs_slot(gve_ctx* ctx) {
+  return static_cast<unsigned long long*>(ctx->ws.dloss.ptr) + 9;
+}
+
+// prep -> scan -> cull -> scan -> emit -> radix sort -> brick ranges (->
+// heaviest-first order for the queue schedule).
+//
+// Synchronous (async = false): reads the box pair total and the kept total
+// back to the host (two small synchronising copies) and sizes the pair
+// buffers from them.  Asynchronous (async = true, refinement after its first
+// iteration): no host read; the buffers hold ctx->pair_cap pairs, every
+// count after the cull is read on the device, and a binning whose box pairs
+// exceed the capacity keeps no pair and raises the fits / sticky flags (the
+// caller redoes the work with larger buffers).  out->npairs = -1 then.
 gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* out,
-                   EmitCopy* ec = nullptr) {
+                   EmitCopy* ec = nullptr, bool async = false) {
   hipStream_t s = ctx->stream;
   auto& ws = ctx->ws;
   const int64_t n = p->n;
@@ -261,6 +293,9 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   TRY(upload_items(ctx, vol, bg.Bxy, bg.Bz, &bg.nbricks));
   if (bg.nbricks >= ((int64_t)1 << 31))
     return fail(ctx, GVE_ERR_UNSUPPORTED, "too many bricks for 32-bit brick keys");
+  // capacity sized for these volumes and this brick shape only
+  if (async && (ctx->box_cap <= 0 || !same_items(ctx->pair_cap_items, ctx->items_host)))
+    async = false;
   const gve::ItemDesc* items = static_cast<const gve::ItemDesc*>(ws.items.ptr);
   TRY(ensure(ctx, ws.scan_tmp, gve::scan_tmp_bytes(n + 1)));
   TRY(ensure_dloss(ctx));
@@ -272,37 +307,46 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   // total bounds the kept total, so below the limit every 32-bit scan is
   // exact.  Deterministic sums address a pair's partials by its emission
   // index, which the sort carries as the value.
-  const bool cull = true;
   const bool slots = ctx->opt.deterministic != 0;
   unsigned char* hp = static_cast<unsigned char*>(ws.h_pinned);
-  const uint32_t* box_off = nullptr;
-  uint32_t* kept = nullptr;
-  if (cull) {
-    TRY(ensure(ctx, ws.box_off, sizeof(uint32_t) * (size_t)(n + 1)));
-    uint32_t* bo = static_cast<uint32_t*>(ws.box_off.ptr);
-    TRY_HIP(ctx, gve::scan_exclusive_u32(p->count, bo, n, ws.scan_tmp.ptr, s));
-    box_off = bo;
+  TRY(ensure(ctx, ws.box_off, sizeof(uint32_t) * (size_t)(n + 1)));
+  uint32_t* box_off = static_cast<uint32_t*>(ws.box_off.ptr);
+  TRY_HIP(ctx, gve::scan_exclusive_u32(p->count, box_off, n, ws.scan_tmp.ptr, s));
+  unsigned long long cap = 0;       // pairs the buffers hold
+  const uint32_t* fits = nullptr;   // device flag of the asynchronous binning
+  const uint32_t* dn = nullptr;     // device pair count (asynchronous)
+  if (async) {
+    cap = (unsigned long long)ctx->box_cap;
+    TRY_HIP(ctx, gve::launch_fits(total, nullptr, cap, fits_flag(ctx), sticky_flag(ctx),
+                                  need_slot(ctx), s));
+    fits = fits_flag(ctx);
+    dn = p->offset + n;
+  } else {
+    static_assert(sizeof(unsigned long long) * gve::kTotalSlots <= 256, "pinned staging size");
+    TRY_HIP(ctx, hipMemcpyAsync(hp, total, sizeof(unsigned long long) * gve::kTotalSlots,
+                                hipMemcpyDeviceToHost, s));
+    TRY_HIP(ctx, hipStreamSynchronize(s));
+    unsigned long long box_total = 0;
+    for (int j = 0; j < gve::kTotalSlots; ++j)
+      box_total += reinterpret_cast<const unsigned long long*>(hp)[j];
+    if (box_total >= 0xFFFFFFF0ull)
+      return fail(ctx, GVE_ERR_UNSUPPORTED,
+                  "more than 2^32 (primitive, brick) pairs; use larger bricks or a smaller k");
+    cap = box_total;
+    out->box_total = (int64_t)box_total;
   }
-  static_assert(sizeof(unsigned long long) * gve::kTotalSlots <= 256, "pinned staging size");
-  TRY_HIP(ctx, hipMemcpyAsync(hp, total, sizeof(unsigned long long) * gve::kTotalSlots,
-                              hipMemcpyDeviceToHost, s));
-  TRY_HIP(ctx, hipStreamSynchronize(s));
-  unsigned long long box_total = 0;
-  for (int j = 0; j < gve::kTotalSlots; ++j)
-    box_total += reinterpret_cast<const unsigned long long*>(hp)[j];
-  if (box_total >= 0xFFFFFFF0ull)
-    return fail(ctx, GVE_ERR_UNSUPPORTED,
-                "more than 2^32 (primitive, brick) pairs; use larger bricks or a smaller k");
-  if (cull) {
-    // the kept keys wait in the sort's second key buffer until emission
-    TRY(ensure(ctx, ws.keys[1], sizeof(uint32_t) * (size_t)(box_total > 0 ? box_total : 1)));
-    kept = static_cast<uint32_t*>(ws.keys[1].ptr);
-    TRY_HIP(ctx, gve::launch_cull(p->rec, n, box_off, items, vol.n, bg, ctx->opt.k, kept,
-                                  p->count, s));
-  }
+  // the kept keys wait in the sort's second key buffer until emission
+  TRY(ensure(ctx, ws.keys[1], sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1)));
+  uint32_t* kept = static_cast<uint32_t*>(ws.keys[1].ptr);
+  TRY_HIP(ctx, gve::launch_cull(p->rec, n, box_off, items, vol.n, bg, ctx->opt.k, kept, p->count,
+                                s, fits));
   TRY_HIP(ctx, gve::scan_exclusive_u32(p->count, p->offset, n, ws.scan_tmp.ptr, s));
-  unsigned long long T = box_total;
-  if (cull) {
+  unsigned long long T = cap;       // pairs (synchronous) or capacity (asynchronous)
+  if (async) {
+    T = (unsigned long long)ctx->pair_cap;
+    TRY_HIP(ctx, gve::launch_fits(nullptr, p->offset + n, T, fits_flag(ctx), sticky_flag(ctx),
+                                  need_pairs_slot(ctx), s));
+  } else {
     TRY_HIP(ctx, hipMemcpyAsync(hp + 8, p->offset + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     TRY_HIP(ctx, hipStreamSynchronize(s));
     T = *reinterpret_cast<uint32_t*>(hp + 8);
@@ -324,9 +368,9 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
     TRY(ensure(ctx, ws.slot_gid, pair_bytes));
     owner = static_cast<uint32_t*>(ws.owner.ptr);
   }
-  TRY_HIP(ctx, gve::launch_emit(p->offset, n, box_off, kept, keys[0], vals[0], owner, s));
+  TRY_HIP(ctx, gve::launch_emit(p->offset, n, box_off, kept, keys[0], vals[0], owner, s, fits));
   if (ec) {
-    ec->fits = (int64_t)T <= ec->capacity;
+    ec->fits = !async && (int64_t)T <= ec->capacity;
     if (ec->fits && T > 0) {
       TRY_HIP(ctx, hipMemcpyAsync(ec->keys, keys[0], sizeof(uint32_t) * (size_t)T,
                                   hipMemcpyDeviceToDevice, s));
@@ -336,9 +380,9 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   }
   int which = 0;
   TRY_HIP(ctx, gve::radix_sort_pairs(keys, vals, (int64_t)T, bits_for(bg.nbricks), ws.sort_hist.ptr,
-                                     &which, s));
+                                     &which, s, dn));
   uint32_t* start = static_cast<uint32_t*>(ws.brick_start.ptr);
-  TRY_HIP(ctx, gve::launch_ranges(keys[which], (int64_t)T, bg.nbricks, start, s));
+  TRY_HIP(ctx, gve::launch_ranges(keys[which], (int64_t)T, bg.nbricks, start, s, dn));
   out->sched = gve::Schedule();
   out->sched.kind = ctx->opt.schedule;
   if (queue) {
@@ -368,16 +412,18 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   out->slot = nullptr;
   if (slots) {
     uint32_t* g = static_cast<uint32_t*>(ws.slot_gid.ptr);
-    TRY_HIP(ctx, gve::launch_gather_owner(owner, vals[which], (int64_t)T, g, s));
+    TRY_HIP(ctx, gve::launch_gather_owner(owner, vals[which], (int64_t)T, g, s, dn));
     out->slot = vals[which];
     out->gid = g;
   }
   out->start = start;
   out->sorted_keys = keys[which];
-  out->npairs = (int64_t)T;
+  out->npairs = async ? -1 : (int64_t)T;
+  out->capacity = (int64_t)T;
+  out->fits = fits;
   ctx->stats.n_primitives = n;
   ctx->stats.n_bricks = bg.nbricks;
-  ctx->stats.n_overlaps = (int64_t)T;
+  if (!async) ctx->stats.n_overlaps = (int64_t)T;
   return GVE_OK;
 }
 
@@ -464,7 +510,7 @@ gve_status loss_and_sums_vol(gve_ctx* ctx, const gve_params* p, const float* d_f
   TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)std::max<int64_t>(bn.bg.nbricks, 1)));
   float* bl = static_cast<float*>(ctx->ws.brick_loss.ptr);
   float* part = nullptr;
-  TRY(partials_for(ctx, bn.npairs, &part));
+  TRY(partials_for(ctx, bn.capacity, &part));
   *part_out = part;
   TRY(fused(ctx, p, bn, d_field, part, bl, false));
   TRY(losses(ctx, bn, bl, d_loss_out));
@@ -577,7 +623,7 @@ gve_status gve_destroy(gve_ctx* ctx) {
                     &ws.sat, &ws.feat, &ws.theta_base, &ws.items, &ws.order_keys[0],
                     &ws.order_keys[1], &ws.order_vals[0], &ws.order_vals[1], &ws.queue,
                     &ws.p_cls, &ws.p_pts, &ws.p_acc, &ws.p_coef, &ws.p_keys[0], &ws.p_keys[1],
-                    &ws.p_idx[0], &ws.p_idx[1], &ws.p_start, &ws.p_loss, &ws.dense,
+                    &ws.p_idx[0], &ws.p_idx[1], &ws.p_start, &ws.p_loss, &ws.dense, &ws.snap,
                     &ws.box_off, &ws.owner, &ws.slot_gid};
   static_assert(sizeof(all) / sizeof(all[0]) * sizeof(Scratch) + sizeof(void*) ==
                     sizeof(gve::Workspace),
@@ -852,7 +898,7 @@ gve_status gve_vjp(gve_ctx* ctx, const gve_params* p, const float* d_upstream, g
   TRY(bin(ctx, p, g, &bn));
   TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)std::max<int64_t>(bn.bg.nbricks, 1)));
   float* part = nullptr;
-  TRY(partials_for(ctx, bn.npairs, &part));
+  TRY(partials_for(ctx, bn.capacity, &part));
   if (!part) TRY_HIP(ctx, gve::fill_f32(pm->acc, gve::kAccStride * p->n, 0.0f, ctx->stream));
   TRY(fused(ctx, p, bn, d_upstream, part, static_cast<float*>(ctx->ws.brick_loss.ptr), true));
   TRY_HIP(ctx, gve::launch_update(0, pm->theta, pm->m, pm->v, pm->acc, part, p->offset, nullptr,
@@ -1109,7 +1155,123 @@ gve_status gve_bin_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, uint32_t
 
 namespace {
 
+// Capacity of the asynchronous binning from a box pair total: a quarter
+// more, so that the primitives can grow for many iterations before a
+// binning no longer fits.
+int64_t pair_capacity(int64_t box_total) { return box_total + box_total / 4 + 4096; }
+
+// Restart point of a refinement (parameters, Adam moments and the clamp and
+// non-finite counters), taken before its first asynchronously binned
+// iteration.
+gve_status snapshot(gve_ctx* ctx, gve_params* p, bool save) {
+  const size_t f11 = sizeof(float) * 11 * (size_t)p->n;
+  TRY(ensure(ctx, ctx->ws.snap, 3 * f11 + 64));
+  char* sp = static_cast<char*>(ctx->ws.snap.ptr);
+  void* dev[3] = {p->theta, p->m, p->v};
+  for (int a = 0; a < 3; ++a) {
+    void* dst = save ? (void*)(sp + a * f11) : dev[a];
+    const void* src = save ? (const void*)dev[a] : (const void*)(sp + a * f11);
+    TRY_HIP(ctx, hipMemcpyAsync(dst, src, f11, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  void* cnt = clamp_counter(ctx);  // clamp and non-finite counts, 16 bytes
+  TRY_HIP(ctx, hipMemcpyAsync(save ? (void*)(sp + 3 * f11) : cnt,
+                              save ? (const void*)cnt : (const void*)(sp + 3 * f11), 16,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+  return GVE_OK;
+}
+
+// Iterations [first, last) of a refinement; asynchronous binning when allowed.
+gve_status refine_iters(gve_ctx* ctx, gve_params* p, const float* d_field, const Vol& vol,
+                        int32_t first, int32_t last, double* hist, bool timing, bool async) {
+  hipStream_t s = ctx->stream;
+  for (int32_t it = first; it < last; ++it) {
+    hipEvent_t* ev = timing ? &ctx->events[4 * (size_t)it] : nullptr;
+    if (timing) TRY_HIP(ctx, hipEventRecord(ev[0], s));
+    Binned bn;
+    TRY(bin_vol(ctx, p, vol, &bn, nullptr, async));
+    if (bn.box_total >= 0) {
+      // sized synchronously: later iterations bin into buffers of this capacity
+      const bool same = same_items(ctx->pair_cap_items, ctx->items_host);
+      ctx->box_cap = same ? std::max(ctx->box_cap, pair_capacity(bn.box_total))
+                          : pair_capacity(bn.box_total);
+      ctx->pair_cap = same ? std::max(ctx->pair_cap, pair_capacity(bn.npairs))
+                           : pair_capacity(bn.npairs);
+      ctx->pair_cap_items = ctx->items_host;
+    }
+    TRY(ensure(ctx, ctx->ws.brick_loss,
+               sizeof(float) * (size_t)std::max<int64_t>(bn.bg.nbricks, 1)));
+    float* bl = static_cast<float*>(ctx->ws.brick_loss.ptr);
+    float* part = nullptr;
+    TRY(partials_for(ctx, bn.capacity, &part));
+    if (timing) TRY_HIP(ctx, hipEventRecord(ev[1], s));
+    TRY(fused(ctx, p, bn, d_field, part, bl, false));
+    if (timing) TRY_HIP(ctx, hipEventRecord(ev[2], s));
+    TRY(losses(ctx, bn, bl, hist + (size_t)it * vol.n));
+    p->t += 1;
+    TRY_HIP(ctx, gve::launch_update(1, p->theta, p->m, p->v, p->acc, part, p->offset, nullptr,
+                                    nullptr, p->n, p->t, ctx->opt, clamp_counter(ctx), s, bn.fits));
+    if (timing) TRY_HIP(ctx, hipEventRecord(ev[3], s));
+  }
+  return GVE_OK;
+}
+
+// End of a refinement: stage timers, clamp and non-finite counts, loss
+// history (synchronises).
+gve_status refine_finish(gve_ctx* ctx, gve_params* p, const Vol& vol, int32_t iters,
+                         const double* hist, double* h_loss_hist, bool timing) {
+  ctx->stats.iterations = p->t;
+  hipStream_t s = ctx->stream;
+  if (timing) {
+    TRY_HIP(ctx, hipStreamSynchronize(s));
+    double tb = 0, tf = 0, tu = 0;
+    for (int32_t it = 0; it < iters; ++it) {
+      hipEvent_t* ev = &ctx->events[4 * (size_t)it];
+      float a = 0, b = 0, c = 0;
+      TRY_HIP(ctx, hipEventElapsedTime(&a, ev[0], ev[1]));
+      TRY_HIP(ctx, hipEventElapsedTime(&b, ev[1], ev[2]));
+      TRY_HIP(ctx, hipEventElapsedTime(&c, ev[2], ev[3]));
+      tb += a; tf += b; tu += c;
+    }
+    ctx->stats.timed_iterations = iters;
+    ctx->stats.ms_bin = tb;
+    ctx->stats.ms_fused = tf;
+    ctx->stats.ms_update = tu;
+  }
+  if (iters <= 0) return GVE_OK;
+  const size_t nl = (size_t)vol.n * (size_t)iters;
+  TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, clamp_counter(ctx),
+                              2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  if (h_loss_hist)
+    TRY_HIP(ctx, hipMemcpyAsync(h_loss_hist, hist, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
+  TRY_HIP(ctx, hipStreamSynchronize(s));
+  const unsigned long long* hc = static_cast<unsigned long long*>(ctx->ws.h_pinned);
+  ctx->stats.n_clamped = (int64_t)hc[0];
+  const int64_t bad_before = ctx->stats.n_nonfinite;
+  ctx->stats.n_nonfinite = (int64_t)hc[1];
+  if (ctx->stats.n_nonfinite > bad_before)
+    return fail(ctx, GVE_ERR_NUMERIC,
+                std::to_string(ctx->stats.n_nonfinite - bad_before) +
+                    " parameter values became non-finite during refinement");
+  if (h_loss_hist) {
+    double last = 0.0;
+    for (int i = 0; i < vol.n; ++i) last += h_loss_hist[(size_t)(iters - 1) * vol.n + i];
+    ctx->stats.last_loss = last;
+    for (size_t i = 0; i < nl; ++i)
+      if (!std::isfinite(h_loss_hist[i])) return fail(ctx, GVE_ERR_NUMERIC, "loss is not finite");
+  }
+  return GVE_OK;
+}
+
 // `iters` fused iterations over a volume set; h_loss_hist [iters][vol.n].
+// The first iteration bins synchronously (sizing the pair buffers); the
+// others bin asynchronously into buffers of that capacity, so that an
+// iteration queues its kernels without waiting for the device.  They run in
+// chunks of kCheckEvery iterations, each from a restart point: should a
+// binning of the chunk not fit (the sticky flag, read after the chunk), the
+// chunk is rolled back and redone with synchronous binning and larger
+// buffers, with the same result.
+constexpr int32_t kCheckEvery = 64;
+
 gve_status refine_vol(gve_ctx* ctx, gve_params* p, const float* d_field, const Vol& vol,
                       int32_t iters, double* h_loss_hist) {
   TRY(set_device(ctx));
@@ -1127,68 +1289,36 @@ gve_status refine_vol(gve_ctx* ctx, gve_params* p, const float* d_field, const V
     }
   }
   hipStream_t s = ctx->stream;
-  for (int32_t it = 0; it < iters; ++it) {
-    hipEvent_t* ev = timing ? &ctx->events[4 * (size_t)it] : nullptr;
-    if (timing) TRY_HIP(ctx, hipEventRecord(ev[0], s));
-    Binned bn;
-    TRY(bin_vol(ctx, p, vol, &bn));
-    TRY(ensure(ctx, ctx->ws.brick_loss,
-               sizeof(float) * (size_t)std::max<int64_t>(bn.bg.nbricks, 1)));
-    float* bl = static_cast<float*>(ctx->ws.brick_loss.ptr);
-    float* part = nullptr;
-    TRY(partials_for(ctx, bn.npairs, &part));
-    if (timing) TRY_HIP(ctx, hipEventRecord(ev[1], s));
-    TRY(fused(ctx, p, bn, d_field, part, bl, false));
-    if (timing) TRY_HIP(ctx, hipEventRecord(ev[2], s));
-    TRY(losses(ctx, bn, bl, hist + (size_t)it * vol.n));
-    p->t += 1;
-    TRY_HIP(ctx, gve::launch_update(1, p->theta, p->m, p->v, p->acc, part, p->offset, nullptr,
-                                    nullptr, p->n, p->t, ctx->opt, clamp_counter(ctx), s));
-    if (timing) TRY_HIP(ctx, hipEventRecord(ev[3], s));
-  }
-  ctx->stats.iterations = p->t;
-  if (timing) {
+  const int32_t first_async = std::min<int32_t>(1, iters);
+  TRY(refine_iters(ctx, p, d_field, vol, 0, first_async, hist, timing, false));
+  for (int32_t c0 = first_async; c0 < iters; c0 += kCheckEvery) {
+    const int32_t c1 = std::min(iters, c0 + kCheckEvery);
+    const int64_t t_restart = p->t;
+    TRY(snapshot(ctx, p, true));
+    TRY(refine_iters(ctx, p, d_field, vol, c0, c1, hist, timing, true));
+    // flags [7]; needs [8], [9]
+    TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, fits_flag(ctx), 3 * sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, s));
     TRY_HIP(ctx, hipStreamSynchronize(s));
-    double tb = 0, tf = 0, tu = 0;
-    for (int32_t it = 0; it < iters; ++it) {
-      hipEvent_t* ev = &ctx->events[4 * (size_t)it];
-      float a = 0, b = 0, c = 0;
-      TRY_HIP(ctx, hipEventElapsedTime(&a, ev[0], ev[1]));
-      TRY_HIP(ctx, hipEventElapsedTime(&b, ev[1], ev[2]));
-      TRY_HIP(ctx, hipEventElapsedTime(&c, ev[2], ev[3]));
-      tb += a; tf += b; tu += c;
+    const unsigned long long* hc = static_cast<unsigned long long*>(ctx->ws.h_pinned);
+    if (reinterpret_cast<const uint32_t*>(hc)[1]) {
+      TRY_HIP(ctx, gve::fill_u32(sticky_flag(ctx), 1, s));
+      TRY(snapshot(ctx, p, false));
+      TRY_HIP(ctx, gve::fill_f32(p->acc, gve::kAccStride * p->n, 0.0f, s));
+      p->t = t_restart;
+      ctx->box_cap = std::max(ctx->box_cap, pair_capacity((int64_t)hc[1]));
+      ctx->pair_cap = std::max(ctx->pair_cap, pair_capacity((int64_t)hc[2]));
+      ctx->stats.n_resized += 1;
+      TRY(refine_iters(ctx, p, d_field, vol, c0, c1, hist, timing, false));
     }
-    ctx->stats.timed_iterations = iters;
-    ctx->stats.ms_bin = tb;
-    ctx->stats.ms_fused = tf;
-    ctx->stats.ms_update = tu;
   }
   if (iters > 0) {
-    TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, clamp_counter(ctx),
-                                2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                                ctx->stream));
-    if (h_loss_hist) {
-      TRY_HIP(ctx, hipMemcpyAsync(h_loss_hist, hist, sizeof(double) * nl, hipMemcpyDeviceToHost,
-                                  ctx->stream));
-    }
-    TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    const unsigned long long* hc = static_cast<unsigned long long*>(ctx->ws.h_pinned);
-    ctx->stats.n_clamped = (int64_t)hc[0];
-    const int64_t bad_before = ctx->stats.n_nonfinite;
-    ctx->stats.n_nonfinite = (int64_t)hc[1];
-    if (ctx->stats.n_nonfinite > bad_before)
-      return fail(ctx, GVE_ERR_NUMERIC,
-                  std::to_string(ctx->stats.n_nonfinite - bad_before) +
-                      " parameter values became non-finite during refinement");
-    if (h_loss_hist) {
-      double last = 0.0;
-      for (int i = 0; i < vol.n; ++i) last += h_loss_hist[(size_t)(iters - 1) * vol.n + i];
-      ctx->stats.last_loss = last;
-      for (size_t i = 0; i < nl; ++i)
-        if (!std::isfinite(h_loss_hist[i])) return fail(ctx, GVE_ERR_NUMERIC, "loss is not finite");
-    }
+    TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, p->offset + p->n, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s));
+    TRY_HIP(ctx, hipStreamSynchronize(s));
+    ctx->stats.n_overlaps = (int64_t) * static_cast<const uint32_t*>(ctx->ws.h_pinned);
   }
-  return GVE_OK;
+  return refine_finish(ctx, p, vol, iters, hist, h_loss_hist, timing);
 }
 
 }  // namespace
@@ -1350,7 +1480,7 @@ gve_status gve_get_stats(const gve_ctx* ctx, gve_stats* out) {
                                &w.order_keys[0], &w.order_keys[1], &w.order_vals[0],
                                &w.order_vals[1], &w.queue, &w.p_cls, &w.p_pts, &w.p_acc,
                                &w.p_coef, &w.p_keys[0], &w.p_keys[1], &w.p_idx[0], &w.p_idx[1],
-                               &w.p_start, &w.p_loss, &w.dense};
+                               &w.p_start, &w.p_loss, &w.dense, &w.snap};
   static_assert(sizeof(all) / sizeof(all[0]) * sizeof(gve::Scratch) + sizeof(void*) ==
                     sizeof(gve::Workspace),
                 "every scratch buffer of the workspace is counted");
@@ -1859,14 +1989,14 @@ gve_status gve_batch_loss_grad(gve_ctx* ctx, const gve_batch* b, const float* d_
   const int ni = (int)b->grids.size();
   TRY(ensure(ctx, ctx->ws.grad_tmp, sizeof(double) * (size_t)ni));
   double* dl = static_cast<double*>(ctx->ws.grad_tmp.ptr);
-  TRY_HIP(ctx, gve::fill_f32(pm->acc, 10 * pm->n, 0.0f, ctx->stream));
+  TRY_HIP(ctx, gve::fill_f32(pm->acc, gve::kAccStride * pm->n, 0.0f, ctx->stream));
   float* part = nullptr;
   TRY(loss_and_sums_vol(ctx, pm, d_fields, vol_of(b), dl, &part));
   if (d_grad) {
     TRY_HIP(ctx, gve::launch_update(0, pm->theta, pm->m, pm->v, pm->acc, part, pm->offset, nullptr,
                                     d_grad, pm->n, pm->t, ctx->opt, nullptr, ctx->stream));
   } else {
-    TRY_HIP(ctx, gve::fill_f32(pm->acc, 10 * pm->n, 0.0f, ctx->stream));
+    TRY_HIP(ctx, gve::fill_f32(pm->acc, gve::kAccStride * pm->n, 0.0f, ctx->stream));
   }
   if (h_loss) {
     TRY_HIP(ctx, hipMemcpyAsync(h_loss, dl, sizeof(double) * (size_t)ni, hipMemcpyDeviceToHost,
@@ -1933,7 +2063,7 @@ gve_status tune_pass(gve_ctx* ctx, const gve_params* p, const float* d_field, co
   TRY(ensure(ctx, ctx->ws.brick_loss, sizeof(float) * (size_t)std::max<int64_t>(bn.bg.nbricks, 1)));
   float* bl = static_cast<float*>(ctx->ws.brick_loss.ptr);
   float* part = nullptr;
-  TRY(partials_for(ctx, bn.npairs, &part));
+  TRY(partials_for(ctx, bn.capacity, &part));
   TRY(fused(ctx, p, bn, d_field, part, bl, false));
   TRY(ensure(ctx, ctx->ws.grad_tmp, sizeof(double) * (size_t)vol.n));
   TRY(losses(ctx, bn, bl, static_cast<double*>(ctx->ws.grad_tmp.ptr)));
@@ -2043,7 +2173,7 @@ gve_status gve_autotune(gve_ctx* ctx, const gve_params* p, const float* d_field,
     }
   }
   // the tuning passes added their sums to the accumulators (atomics mode)
-  TRY_HIP(ctx, gve::fill_f32(P->acc, 10 * P->n, 0.0f, ctx->stream));
+  TRY_HIP(ctx, gve::fill_f32(P->acc, gve::kAccStride * P->n, 0.0f, ctx->stream));
   TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
   ctx->tuned[key] = {best.brick, best.brick_z, best.schedule};
   ctx->opt = best;

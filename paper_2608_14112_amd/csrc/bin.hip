@@ -241,6 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_cull(const Record* __restrict__ re
                                                    const uint32_t* __restrict__ box_off,
                                                    const ItemDesc* __restrict__ items, int nitems,
                                                    BrickGeom bg, float k,
+                                                   const uint32_t* __restrict__ fits,
                                                    uint32_t* __restrict__ kept,
                                                    uint32_t* __restrict__ count) {
   const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kGroup;
@@ -248,11 +249,14 @@ __global__ __launch_bounds__(kThreads) void k_cull(const Record* __restrict__ re
   const int sub = lane & (kGroup - 1);
   const int shift = lane & ~(kGroup - 1);  // first lane of the group
   const bool live = i < n;
+  // buffers sized in advance: when the box pairs do not fit, nothing is kept
+  const bool room = fits == nullptr || *fits != 0u;
   uint32_t o = 0, total = 0;
-  if (live) {
+  if (live && room) {
     o = box_off[i];
     total = box_off[i + 1] - o;
   }
+  if (live && !room && sub == 0) count[i] = 0;
   Record r{};
   BoxBricks bb{};
   const ItemDesc* it = items;
@@ -291,10 +295,11 @@ __global__ __launch_bounds__(kThreads) void k_emit_kept(const uint32_t* __restri
                                                         const uint32_t* __restrict__ kept,
                                                         uint32_t* __restrict__ keys,
                                                         uint32_t* __restrict__ vals,
-                                                        uint32_t* __restrict__ owner) {
+                                                        uint32_t* __restrict__ owner,
+                                                        const uint32_t* __restrict__ fits) {
   const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kGroup;
   const uint32_t sub = threadIdx.x & (kGroup - 1);
-  if (i >= n) return;
+  if (i >= n || (fits && *fits == 0u)) return;
   const uint32_t o = offset[i];
   const uint32_t cnt = offset[i + 1] - o;
   const uint32_t src = box_off[i];
@@ -313,17 +318,23 @@ __global__ __launch_bounds__(kThreads) void k_emit_kept(const uint32_t* __restri
 // emission index.
 __global__ __launch_bounds__(kThreads) void k_gather_owner(const uint32_t* __restrict__ owner,
                                                            const uint32_t* __restrict__ slot,
-                                                           int64_t n, uint32_t* __restrict__ gid) {
+                                                           int64_t n,
+                                                           const uint32_t* __restrict__ dn,
+                                                           uint32_t* __restrict__ gid) {
   const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (dn) n = min(n, (int64_t)*dn);
   if (j < n) gid[j] = owner[slot[j]];
 }
 
 // brick_start[b] = first index whose key >= b, for b in [0, nbricks].
 __global__ __launch_bounds__(kThreads) void k_ranges(const uint32_t* __restrict__ keys,
-                                                     int64_t npairs, int64_t nbricks,
+                                                     int64_t npairs,
+                                                     const uint32_t* __restrict__ dn,
+                                                     int64_t nbricks,
                                                      uint32_t* __restrict__ start) {
   const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (b > nbricks) return;
+  if (dn) npairs = min(npairs, (int64_t)*dn);
   int64_t lo = 0, hi = npairs;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
@@ -343,6 +354,32 @@ __global__ __launch_bounds__(kThreads) void k_order_keys(const uint32_t* __restr
   if (b >= nbricks) return;
   keys[b] = (uint32_t)__clz((int)(start[b + 1] - start[b]));
   vals[b] = (uint32_t)b;
+}
+
+// Whether the box pairs of this binning fit the buffers sized in advance:
+// fits = (sum of prep's 64-bit pair-total slots <= capacity); a binning that
+// does not fit also sets the sticky flag, which only the host clears, and
+// need = the largest box total seen.
+// With `count` (the kept pair total, from the scan of the kept counts)
+// instead of slots, the same for the pair buffers; fits then stays 0 if the
+// box pairs already did not fit, and a count that does not fit is set to 0,
+// so that every later kernel of the binning sees no pair.
+__global__ void k_fits(const unsigned long long* __restrict__ slots, int nslots,
+                       uint32_t* __restrict__ count, unsigned long long capacity,
+                       uint32_t* __restrict__ fits, uint32_t* __restrict__ sticky,
+                       unsigned long long* __restrict__ need) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long t = 0;
+  if (count) {
+    t = *count;
+  } else {
+    for (int j = 0; j < nslots; ++j) t += slots[j];
+  }
+  const bool ok = t <= capacity && (count == nullptr || *fits != 0u);
+  *fits = ok ? 1u : 0u;
+  if (!ok) *sticky = 1u;
+  if (!ok && count) *count = 0u;
+  if (t > *need) *need = t;
 }
 
 }  // namespace
@@ -379,27 +416,35 @@ hipError_t launch_prep(const float* theta, int64_t n, const ItemDesc* items, int
 
 hipError_t launch_cull(const Record* rec, int64_t n, const uint32_t* box_off, const ItemDesc* items,
                        int nitems, BrickGeom bg, float k, uint32_t* kept, uint32_t* count,
-                       hipStream_t s) {
+                       hipStream_t s, const uint32_t* fits) {
   const unsigned blocks = (unsigned)((n * kGroup + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_cull, dim3(blocks), dim3(kThreads), 0, s, rec, n, box_off, items, nitems,
-                     bg, k, kept, count);
+                     bg, k, fits, kept, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fits(const unsigned long long* slots, uint32_t* count,
+                       unsigned long long capacity, uint32_t* fits, uint32_t* sticky,
+                       unsigned long long* need, hipStream_t s) {
+  hipLaunchKernelGGL(k_fits, dim3(1), dim3(64), 0, s, slots, kTotalSlots, count, capacity, fits,
+                     sticky, need);
   return hipGetLastError();
 }
 
 hipError_t launch_emit(const uint32_t* offset, int64_t n, const uint32_t* box_off,
                        const uint32_t* kept, uint32_t* keys, uint32_t* vals, uint32_t* owner,
-                       hipStream_t s) {
+                       hipStream_t s, const uint32_t* fits) {
   const unsigned blocks = (unsigned)((n * kGroup + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_emit_kept, dim3(blocks), dim3(kThreads), 0, s, offset, n, box_off, kept,
-                     keys, vals, owner);
+                     keys, vals, owner, fits);
   return hipGetLastError();
 }
 
 hipError_t launch_gather_owner(const uint32_t* owner, const uint32_t* slot, int64_t n,
-                               uint32_t* gid, hipStream_t s) {
+                               uint32_t* gid, hipStream_t s, const uint32_t* dn) {
   if (n <= 0) return hipSuccess;  // no pairs: nothing to gather (an empty grid is invalid)
   const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_gather_owner, dim3(blocks), dim3(kThreads), 0, s, owner, slot, n, gid);
+  hipLaunchKernelGGL(k_gather_owner, dim3(blocks), dim3(kThreads), 0, s, owner, slot, n, dn, gid);
   return hipGetLastError();
 }
 
@@ -412,10 +457,10 @@ hipError_t launch_order_keys(const uint32_t* brick_start, int64_t nbricks, uint3
 }
 
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t npairs, int64_t nbricks,
-                         uint32_t* brick_start, hipStream_t s) {
+                         uint32_t* brick_start, hipStream_t s, const uint32_t* dn) {
   const unsigned blocks = (unsigned)((nbricks + 1 + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(kThreads), 0, s, sorted_keys, npairs, nbricks,
-                     brick_start);
+  hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(kThreads), 0, s, sorted_keys, npairs, dn,
+                     nbricks, brick_start);
   return hipGetLastError();
 }
 

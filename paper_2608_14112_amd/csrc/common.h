@@ -87,6 +87,8 @@ struct Workspace {
   // their float64 accumulators, gradient coefficients, cell sort, losses
   Scratch p_cls, p_pts, p_acc, p_coef, p_keys[2], p_idx[2], p_start, p_loss;
   Scratch dense;                 // float [M] residual of the dense reference path
+  Scratch snap;                  // float [3][11][n] parameters and Adam moments (refinement
+                                 // restart point) + counters
   void* h_pinned = nullptr;      // pinned host staging (64 bytes)
 };
 
@@ -108,6 +110,11 @@ struct gve_ctx {
   // (the allocation-free entry point) instead of being allocated.
   char* arena_base = nullptr;
   size_t arena_cap = 0, arena_used = 0;
+  // Capacities (box pairs, kept pairs) of the buffers of the asynchronous
+  // binning inside refinement (0: not sized yet); valid for the volume
+  // descriptors and brick shape they were sized for.
+  int64_t box_cap = 0, pair_cap = 0;
+  std::vector<gve::ItemDesc> pair_cap_items;
 };
 
 struct gve_params {
@@ -135,10 +142,11 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void
 
 // Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits of
 // the key.  Ping-pongs between buffers 0 and 1; returns in *which the index of
-// the buffer that holds the result.
+// the buffer that holds the result.  With dn, the item count is
+// min(n, *dn) read on the device (n is then the buffers' capacity).
 size_t sort_hist_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits,
-                            void* hist, int* which, hipStream_t s);
+                            void* hist, int* which, hipStream_t s, const uint32_t* dn = nullptr);
 
 // Bricks are Bxy x Bxy x Bz voxels: a workgroup's lanes own the Bxy^2 voxel
 // columns, each lane Bz voxels of its column.
@@ -181,19 +189,30 @@ hipError_t launch_prep(const float* theta, int64_t n, const ItemDesc* items, int
 // Culling: box_off = exclusive scan of prep's box brick counts; the keys of
 // the box bricks a separating plane does not part from the support m^2 < k^2
 // go to kept[box_off[i] ..] and their number to count[i].
+// With `fits` (launch_fits), a binning whose box pairs exceed the buffers
+// keeps nothing (every count 0) instead of writing past them.
 hipError_t launch_cull(const Record* rec, int64_t n, const uint32_t* box_off, const ItemDesc* items,
                        int nitems, BrickGeom bg, float k, uint32_t* kept, uint32_t* count,
-                       hipStream_t s);
+                       hipStream_t s, const uint32_t* fits = nullptr);
+// *fits = (box pair total from prep's slots, or *count when given, <=
+// capacity; with count also the previous *fits); *sticky = 1 when it does not
+// (cleared by the host only); *need = max(*need, that total); a count that
+// does not fit is set to 0.
+hipError_t launch_fits(const unsigned long long* slots, uint32_t* count,
+                       unsigned long long capacity, uint32_t* fits, uint32_t* sticky,
+                       unsigned long long* need, hipStream_t s);
 // Pairs at the scanned offsets from the kept keys of launch_cull; values are
 // primitive ids, or with `owner` emission indices p (owner[p] = primitive).
+// Nothing is written when *fits is 0.
 hipError_t launch_emit(const uint32_t* offset, int64_t n, const uint32_t* box_off,
                        const uint32_t* kept, uint32_t* keys, uint32_t* vals, uint32_t* owner,
-                       hipStream_t s);
-// gid[j] = owner[slot[j]] for j < n.
+                       hipStream_t s, const uint32_t* fits = nullptr);
+// gid[j] = owner[slot[j]] for j < n (n capped by *dn when given).
 hipError_t launch_gather_owner(const uint32_t* owner, const uint32_t* slot, int64_t n,
-                               uint32_t* gid, hipStream_t s);
+                               uint32_t* gid, hipStream_t s, const uint32_t* dn = nullptr);
+// brick_start[b] = first sorted pair with key >= b; npairs capped by *dn when given.
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t npairs, int64_t nbricks,
-                         uint32_t* brick_start, hipStream_t s);
+                         uint32_t* brick_start, hipStream_t s, const uint32_t* dn = nullptr);
 // Heaviest-first brick order for kSchedQueue: keys = leading zeros of the
 // brick's pair count (sorted ascending, stably), vals = brick ids.
 hipError_t launch_order_keys(const uint32_t* brick_start, int64_t nbricks, uint32_t* keys,
@@ -330,9 +349,12 @@ hipError_t mlp_apply_delta(float* theta, const float* base, const float* Y, int6
 // log-scale entries clamped and clamp_count[1] the parameters left non-finite.  In modes 0 and 1 the ten sums come from acc
 // (zeroed after use) or, when part is given, from the primitive's partials
 // part[offset[i] .. offset[i+1]) summed in order.
+// With `fits` (launch_fits of this iteration's binning) the update does
+// nothing when the binning did not fit its buffers.
 hipError_t launch_update(int mode, float* theta, float* m, float* v, float* acc,
                          const float* part, const uint32_t* offset, const float* grad_in,
                          float* grad_out, int64_t n, int64_t t, const gve_options& opt,
-                         unsigned long long* clamp_count, hipStream_t s);
+                         unsigned long long* clamp_count, hipStream_t s,
+                         const uint32_t* fits = nullptr);
 
 }  // namespace gve

@@ -21,13 +21,25 @@ constexpr int kRounds = 8;
 constexpr int kTile = kThreads * kRounds;
 constexpr int kRadix = 256;
 
+// Items to sort: n, or (with a device count) the smaller of n and *dn.  The
+// launch covers n items; tiles past the device count are empty.
+__device__ inline int64_t items_of(int64_t n, const uint32_t* __restrict__ dn) {
+  return dn ? min(n, (int64_t)*dn) : n;
+}
+
 __global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ keys, int64_t n,
-                                                   int shift, uint32_t mask, int64_t ntiles,
+                                                   const uint32_t* __restrict__ dn, int shift,
+                                                   uint32_t mask, int64_t ntiles,
                                                    uint32_t* __restrict__ hist) {
   __shared__ uint32_t cnt[kRadix];
+  n = items_of(n, dn);
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  if (base >= n) {  // a tile past the items (the launch covers the capacity)
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = 0u;
+    return;
+  }
   cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kTile;
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
@@ -60,9 +72,12 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* __restrict
 // out in that order, so each digit's run of the tile lands as one contiguous
 // stretch of the output.
 __global__ __launch_bounds__(kThreads) void k_scatter(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int64_t n, int shift,
-    uint32_t mask, int wbits, int64_t ntiles, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ offs, uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int64_t n,
+    const uint32_t* __restrict__ dn, int shift, uint32_t mask, int wbits, int64_t ntiles,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ offs,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+  n = items_of(n, dn);
+  if ((int64_t)blockIdx.x * kTile >= n) return;  // a tile past the items: nothing to move
   __shared__ uint32_t skey[kTile], sval[kTile];
   __shared__ uint32_t bstart[kRadix];         // tile-local start of each digit
   __shared__ uint32_t run[kRadix];            // items of each digit already staged
@@ -130,7 +145,7 @@ size_t sort_hist_bytes(int64_t n) {
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits,
-                            void* hist_mem, int* which, hipStream_t s) {
+                            void* hist_mem, int* which, hipStream_t s, const uint32_t* dn) {
   *which = 0;
   if (n <= 1 || bits <= 0) return hipSuccess;
   const int64_t t = ntiles_of(n);
@@ -145,14 +160,14 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int
     const int shift = p * w;
     const int wb = (shift + w <= bits) ? w : (bits - shift);
     const uint32_t mask = (1u << wb) - 1u;
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)t), dim3(kThreads), 0, s, keys[cur], n, shift, mask,
-                       t, hist);
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)t), dim3(kThreads), 0, s, keys[cur], n, dn, shift,
+                       mask, t, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = scan_exclusive_u32(hist, offs, h, stmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)t), dim3(kThreads), 0, s, keys[cur], vals[cur], n,
-                       shift, mask, wb, t, hist, offs, keys[cur ^ 1], vals[cur ^ 1]);
+                       dn, shift, mask, wb, t, hist, offs, keys[cur ^ 1], vals[cur ^ 1]);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur ^= 1;

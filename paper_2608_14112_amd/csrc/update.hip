@@ -32,7 +32,10 @@ __global__ __launch_bounds__(kThreads) void k_update(int mode, float* __restrict
                                                      const float* __restrict__ grad_in,
                                                      float* __restrict__ grad_out, int64_t n,
                                                      AdamCoef ac,
-                                                     unsigned long long* __restrict__ nclamp) {
+                                                     unsigned long long* __restrict__ nclamp,
+                                                     const uint32_t* __restrict__ fits) {
+  // a binning that did not fit its buffers produced no gradient: no step
+  if (fits && *fits == 0u) return;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   unsigned int clamped = 0, nonfinite = 0;
   if (i < n) {
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_parts(const float* __restri
 hipError_t launch_update(int mode, float* theta, float* m, float* v, float* acc,
                          const float* part, const uint32_t* offset, const float* grad_in,
                          float* grad_out, int64_t n, int64_t t, const gve_options& opt,
-                         unsigned long long* clamp_count, hipStream_t s) {
+                         unsigned long long* clamp_count, hipStream_t s, const uint32_t* fits) {
   AdamCoef ac;
   ac.lr = opt.lr;
   ac.b1 = opt.beta1;
@@ -155,7 +158,7 @@ hipError_t launch_update(int mode, float* theta, float* m, float* v, float* acc,
   }
   const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_update, dim3(blocks), dim3(kThreads), 0, s, mode, theta, m, v, acc, part,
-                     offset, grad_in, grad_out, n, ac, clamp_count);
+                     offset, grad_in, grad_out, n, ac, clamp_count, fits);
   return hipGetLastError();
 }
 
