@@ -76,8 +76,16 @@ typedef struct gve_grid {
  * Options.  k: truncation radius in standard deviations (> 0; Sec. III-C uses
  * 5).  brick, brick_z: primitives are binned to bricks of brick x brick x
  * brick_z voxels; supported shapes are 8x8x8, 8x8x16, 8x8x32 and 16x16x16
- * (brick 0 picks 8; brick_z 0 picks the same as brick).  The shape changes
- * only the summation order, not the result beyond float32 rounding.  lr,
+ * (brick_z 0 picks the same as brick).  brick 0 is automatic: the shape and
+ * the schedule are chosen per workload (volumes, total voxels, primitives):
+ * the choice made earlier for that workload if any; else, on a call with a
+ * target field (gve_loss_grad, gve_refine, gve_batch_loss_grad,
+ * gve_batch_refine; not the allocation-free entry point), the fastest of
+ * every shape and schedule, timed as gve_autotune does and then kept; else
+ * 8x8x32 with the XCD schedule (brick_z and schedule are then not used;
+ * stats.bin_brick, bin_brick_z and bin_schedule report the choice).  The
+ * shape changes only the summation order, not the result beyond float32
+ * rounding.  lr,
  * beta1, beta2, eps: Adam (Sec. III-F cites Kingma and Ba; Table
  * tab:training-config gives lr 8e-3).  ell_min/ell_max: clamp of the
  * log-scales after each Adam step (a guard against collapsing or exploding
@@ -140,6 +148,9 @@ typedef struct gve_stats {
   /* Refinements whose asynchronously sized pair buffers overflowed and that
    * were rolled back and redone with larger buffers (cumulative). */
   int64_t n_resized;
+  /* Brick edge, brick depth and schedule of the last binning (with
+   * options.brick = 0, the automatic choice). */
+  int64_t bin_brick, bin_brick_z, bin_schedule;
 } gve_stats;
 
 typedef struct gve_ctx gve_ctx;
@@ -425,7 +436,9 @@ gve_status gve_batch_count_pairs(gve_ctx* ctx, const gve_batch* b, int64_t* h_in
  * every brick shape and schedule on the caller's workload (b == NULL: the
  * single volume p, d_field, g; otherwise the batch b, d_fields) for `reps`
  * passes each after one warm-up pass, keeps the fastest in the context's
- * options, and writes one entry per candidate to h_table (up to table_len;
+ * options (with options.brick = 0 the options stay automatic and the
+ * fastest becomes this workload's automatic choice), and writes one entry
+ * per candidate to h_table (up to table_len;
  * *n_written = number written).  Parameters and Adam state are unchanged.
  * Results are cached in the context under a key of (volumes, voxels,
  * primitives, box coverage per voxel at 8x8x8, each rounded to a power of

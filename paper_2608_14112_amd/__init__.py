@@ -86,7 +86,9 @@ class StatsC(ctypes.Structure):
                 ("ms_fused", ctypes.c_double), ("ms_update", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_int64), ("n_in_support", ctypes.c_int64),
                 ("n_candidates", ctypes.c_int64), ("n_atomics", ctypes.c_int64),
-                ("n_nonfinite", ctypes.c_int64), ("n_resized", ctypes.c_int64)]
+                ("n_nonfinite", ctypes.c_int64), ("n_resized", ctypes.c_int64),
+                ("bin_brick", ctypes.c_int64), ("bin_brick_z", ctypes.c_int64),
+                ("bin_schedule", ctypes.c_int64)]
 
 
 class AllocInfoC(ctypes.Structure):

@@ -146,10 +146,9 @@ unsigned long long* pair_total_slots(gve_ctx* ctx) {
 gve_status validate_options(const gve_ctx* ctx, const gve_options& o) {
   if (!(o.k > 0.0f) || !std::isfinite(o.k) || o.k > 64.0f)
     return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "k must be finite, > 0 and <= 64");
-  {
-    const int bxy = o.brick == 0 ? 8 : o.brick;
-    const int bz = o.brick_z == 0 ? bxy : o.brick_z;
-    if (!gve::brick_shape_supported(bxy, bz))
+  if (o.brick != 0) {  // brick 0: automatic (brick_z is then not used)
+    const int bz = o.brick_z == 0 ? o.brick : o.brick_z;
+    if (!gve::brick_shape_supported(o.brick, bz))
       return fail(ctx, GVE_ERR_UNSUPPORTED,
                   "brick shape must be 8x8x8, 8x8x16, 8x8x32 or 16x16x16");
   }
@@ -181,8 +180,20 @@ gve_status validate_grid(const gve_ctx* ctx, const gve_grid& g) {
   return GVE_OK;
 }
 
-int brick_xy(const gve_ctx* ctx) { return ctx->opt.brick == 0 ? 8 : ctx->opt.brick; }
-int brick_z(const gve_ctx* ctx) { return ctx->opt.brick_z == 0 ? brick_xy(ctx) : ctx->opt.brick_z; }
+// Brick shape and schedule of the next binning: the options', or with
+// options.brick = 0 the automatic choice (select_auto).
+int brick_xy(const gve_ctx* ctx) { return ctx->opt.brick == 0 ? ctx->auto_bxy : ctx->opt.brick; }
+int brick_z(const gve_ctx* ctx) {
+  if (ctx->opt.brick == 0) return ctx->auto_bz;
+  return ctx->opt.brick_z == 0 ? brick_xy(ctx) : ctx->opt.brick_z;
+}
+int sched_of(const gve_ctx* ctx) {
+  return ctx->opt.brick == 0 ? ctx->auto_sched : ctx->opt.schedule;
+}
+
+struct Vol;
+gve_status select_auto(gve_ctx* ctx, const gve_params* p, const float* d_field, const Vol& vol,
+                       bool tune);
 
 int bits_for(int64_t nbricks) {
   int b = 0;
@@ -284,6 +295,7 @@ unsigned long long* need_pairs_slot(gve_ctx* ctx) {
 // caller redoes the work with larger buffers).  out->npairs = -1 then.
 gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* out,
                    EmitCopy* ec = nullptr, bool async = false) {
+  TRY(select_auto(ctx, p, nullptr, vol, false));
   hipStream_t s = ctx->stream;
   auto& ws = ctx->ws;
   const int64_t n = p->n;
@@ -356,7 +368,7 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
     TRY(ensure(ctx, ws.keys[b], pair_bytes));  // keys[1] already holds >= T: kept
     TRY(ensure(ctx, ws.vals[b], pair_bytes));
   }
-  const bool queue = ctx->opt.schedule == GVE_SCHED_QUEUE;
+  const bool queue = sched_of(ctx) == GVE_SCHED_QUEUE;
   TRY(ensure(ctx, ws.sort_hist,
              gve::sort_hist_bytes(std::max<int64_t>((int64_t)T, queue ? bg.nbricks : 0))));
   TRY(ensure(ctx, ws.brick_start, sizeof(uint32_t) * (size_t)(bg.nbricks + 1)));
@@ -384,7 +396,7 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   uint32_t* start = static_cast<uint32_t*>(ws.brick_start.ptr);
   TRY_HIP(ctx, gve::launch_ranges(keys[which], (int64_t)T, bg.nbricks, start, s, dn));
   out->sched = gve::Schedule();
-  out->sched.kind = ctx->opt.schedule;
+  out->sched.kind = sched_of(ctx);
   if (queue) {
     const size_t ob = sizeof(uint32_t) * (size_t)std::max<int64_t>(bg.nbricks, 1);
     for (int b = 0; b < 2; ++b) {
@@ -423,6 +435,9 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   out->fits = fits;
   ctx->stats.n_primitives = n;
   ctx->stats.n_bricks = bg.nbricks;
+  ctx->stats.bin_brick = bg.Bxy;
+  ctx->stats.bin_brick_z = bg.Bz;
+  ctx->stats.bin_schedule = sched_of(ctx);
   if (!async) ctx->stats.n_overlaps = (int64_t)T;
   return GVE_OK;
 }
@@ -774,6 +789,11 @@ gve_status gve_loss_grad(gve_ctx* ctx, const gve_params* p, const float* d_field
   TRY(set_device(ctx));
   gve_params* pm = const_cast<gve_params*>(p);
   TRY(ensure_dloss(ctx));
+  {
+    // the allocation-free path never tunes (tuning allocates)
+    const int64_t off[2] = {0, p->n};
+    TRY(select_auto(ctx, p, d_field, Vol{&g, off, 1}, ctx->arena_base == nullptr));
+  }
   TRY_HIP(ctx, gve::fill_f32(pm->acc, gve::kAccStride * p->n, 0.0f, ctx->stream));
   double* dl = static_cast<double*>(ctx->ws.dloss.ptr);
   float* part = nullptr;
@@ -1276,6 +1296,7 @@ gve_status refine_vol(gve_ctx* ctx, gve_params* p, const float* d_field, const V
                       int32_t iters, double* h_loss_hist) {
   TRY(set_device(ctx));
   TRY(ensure_dloss(ctx));
+  if (iters > 0) TRY(select_auto(ctx, p, d_field, vol, true));
   const size_t nl = (size_t)vol.n * (size_t)(iters > 0 ? iters : 1);
   TRY(ensure(ctx, ctx->ws.grad_tmp, sizeof(double) * nl));
   double* hist = static_cast<double*>(ctx->ws.grad_tmp.ptr);
@@ -1986,6 +2007,7 @@ gve_status gve_batch_loss_grad(gve_ctx* ctx, const gve_batch* b, const float* d_
   TRY(set_device(ctx));
   TRY(ensure_dloss(ctx));
   gve_params* pm = b->params;
+  TRY(select_auto(ctx, pm, d_fields, vol_of(b), true));
   const int ni = (int)b->grids.size();
   TRY(ensure(ctx, ctx->ws.grad_tmp, sizeof(double) * (size_t)ni));
   double* dl = static_cast<double*>(ctx->ws.grad_tmp.ptr);
@@ -2074,6 +2096,94 @@ int bucket(double x, double per_octave) {
   return (int)std::lround(std::log2(std::max(x, 1e-6)) * per_octave);
 }
 
+// Times every brick shape and schedule on the workload (a warm-up pass, then
+// the median of `reps` passes) and returns the fastest as (brick, brick_z,
+// schedule).  Entries go to h_table while it has room.  The context's
+// options are restored on return; the passes' gradient sums are cleared.
+gve_status tune_candidates(gve_ctx* ctx, gve_params* P, const float* d_field, const Vol& vol,
+                           int32_t reps, gve_tune_entry* h_table, int32_t table_len,
+                           int32_t* written, std::array<int, 3>* best) {
+  static const int shapes[][2] = {{8, 8}, {8, 16}, {8, 32}, {16, 16}};
+  static const int scheds[] = {GVE_SCHED_INDEX, GVE_SCHED_XCD, GVE_SCHED_QUEUE};
+  OptionsGuard guard(ctx);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TRY_HIP(ctx, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(ctx, GVE_ERR_DEVICE, "hipEventCreate");
+  }
+  struct Events {
+    hipEvent_t a, b;
+    ~Events() {
+      hipEventDestroy(a);
+      hipEventDestroy(b);
+    }
+  } events{e0, e1};
+  float best_ms = INFINITY;
+  *written = 0;
+  for (const auto& sh : shapes) {
+    for (int sc : scheds) {
+      ctx->opt = guard.saved;
+      ctx->opt.brick = sh[0];
+      ctx->opt.brick_z = sh[1];
+      ctx->opt.schedule = sc;
+      TRY(tune_pass(ctx, P, d_field, vol));  // warm-up
+      std::vector<float> ms;
+      for (int32_t r = 0; r < reps; ++r) {
+        TRY_HIP(ctx, hipEventRecord(e0, ctx->stream));
+        TRY(tune_pass(ctx, P, d_field, vol));
+        TRY_HIP(ctx, hipEventRecord(e1, ctx->stream));
+        TRY_HIP(ctx, hipEventSynchronize(e1));
+        float t = 0.0f;
+        TRY_HIP(ctx, hipEventElapsedTime(&t, e0, e1));
+        ms.push_back(t);
+      }
+      std::sort(ms.begin(), ms.end());
+      const float med = ms[ms.size() / 2];
+      if (*written < table_len) h_table[(*written)++] = gve_tune_entry{sh[0], sh[1], sc, med};
+      if (med < best_ms) {
+        best_ms = med;
+        *best = {sh[0], sh[1], sc};
+      }
+    }
+  }
+  // the tuning passes added their sums to the accumulators (atomics mode)
+  TRY_HIP(ctx, gve::fill_f32(P->acc, gve::kAccStride * P->n, 0.0f, ctx->stream));
+  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return GVE_OK;
+}
+
+std::array<int64_t, 3> auto_key(const Vol& vol, const gve_params* p) {
+  int64_t M = 0;
+  for (int i = 0; i < vol.n; ++i) M += vol.grids[i].nx * vol.grids[i].ny * vol.grids[i].nz;
+  return {vol.n, M, p->n};
+}
+
+// options.brick = 0: picks the brick shape and schedule for the workload
+// (the volumes' voxel count and the primitive count): the choice made
+// earlier for it, else, when tuning is allowed and a target field is given,
+// the tuner's choice (then kept), else 8 x 8 x 32 bricks in XCD chunks.
+gve_status select_auto(gve_ctx* ctx, const gve_params* p, const float* d_field, const Vol& vol,
+                       bool tune) {
+  if (ctx->opt.brick != 0) return GVE_OK;
+  const auto key = auto_key(vol, p);
+  auto hit = ctx->auto_choice.find(key);
+  std::array<int, 3> c = {8, 32, GVE_SCHED_XCD};
+  if (hit != ctx->auto_choice.end()) {
+    c = hit->second;
+  } else if (tune && d_field) {
+    TRY(ensure_dloss(ctx));
+    int32_t written = 0;
+    TRY(tune_candidates(ctx, const_cast<gve_params*>(p), d_field, vol, 3, nullptr, 0, &written,
+                        &c));
+    ctx->auto_choice[key] = c;
+  }
+  ctx->auto_bxy = c[0];
+  ctx->auto_bz = c[1];
+  ctx->auto_sched = c[2];
+  return GVE_OK;
+}
+
 }  // namespace
 
 gve_status gve_autotune(gve_ctx* ctx, const gve_params* p, const float* d_field, gve_grid g,
@@ -2117,67 +2227,28 @@ gve_status gve_autotune(gve_ctx* ctx, const gve_params* p, const float* d_field,
   const std::array<int, 4> key = {vol.n, bucket((double)M, 1.0), bucket((double)P->n, 1.0),
                                   bucket(cover, 2.0)};
   auto hit = ctx->tuned.find(key);
-  gve_options best = guard.saved;
+  std::array<int, 3> c{};
+  int32_t written = 0;
   if (hit != ctx->tuned.end()) {
-    best.brick = hit->second[0];
-    best.brick_z = hit->second[1];
-    best.schedule = hit->second[2];
+    c = hit->second;
+  } else {
+    TRY(tune_candidates(ctx, P, d_field, vol, reps, h_table, table_len, &written, &c));
+    ctx->tuned[key] = c;
+  }
+  gve_options best = guard.saved;
+  if (guard.saved.brick == 0) {
+    // automatic mode stays on; the choice becomes this workload's
+    ctx->auto_choice[auto_key(vol, P)] = c;
+    ctx->auto_bxy = c[0];
+    ctx->auto_bz = c[1];
+    ctx->auto_sched = c[2];
+  } else {
+    best.brick = c[0];
+    best.brick_z = c[1];
+    best.schedule = c[2];
     ctx->opt = best;
     guard.keep = true;
-    return GVE_OK;
   }
-  static const int shapes[][2] = {{8, 8}, {8, 16}, {8, 32}, {16, 16}};
-  static const int scheds[] = {GVE_SCHED_INDEX, GVE_SCHED_XCD, GVE_SCHED_QUEUE};
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  TRY_HIP(ctx, hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
-    return fail(ctx, GVE_ERR_DEVICE, "hipEventCreate");
-  }
-  struct Events {
-    hipEvent_t a, b;
-    ~Events() {
-      hipEventDestroy(a);
-      hipEventDestroy(b);
-    }
-  } events{e0, e1};
-  float best_ms = INFINITY;
-  int written = 0;
-  for (const auto& sh : shapes) {
-    for (int sc : scheds) {
-      ctx->opt = guard.saved;
-      ctx->opt.brick = sh[0];
-      ctx->opt.brick_z = sh[1];
-      ctx->opt.schedule = sc;
-      TRY(tune_pass(ctx, P, d_field, vol));  // warm-up
-      std::vector<float> ms;
-      for (int32_t r = 0; r < reps; ++r) {
-        TRY_HIP(ctx, hipEventRecord(e0, ctx->stream));
-        TRY(tune_pass(ctx, P, d_field, vol));
-        TRY_HIP(ctx, hipEventRecord(e1, ctx->stream));
-        TRY_HIP(ctx, hipEventSynchronize(e1));
-        float t = 0.0f;
-        TRY_HIP(ctx, hipEventElapsedTime(&t, e0, e1));
-        ms.push_back(t);
-      }
-      std::sort(ms.begin(), ms.end());
-      const float med = ms[ms.size() / 2];
-      if (written < table_len) h_table[written++] = gve_tune_entry{sh[0], sh[1], sc, med};
-      if (med < best_ms) {
-        best_ms = med;
-        best = guard.saved;
-        best.brick = sh[0];
-        best.brick_z = sh[1];
-        best.schedule = sc;
-      }
-    }
-  }
-  // the tuning passes added their sums to the accumulators (atomics mode)
-  TRY_HIP(ctx, gve::fill_f32(P->acc, gve::kAccStride * P->n, 0.0f, ctx->stream));
-  TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  ctx->tuned[key] = {best.brick, best.brick_z, best.schedule};
-  ctx->opt = best;
-  guard.keep = true;
   if (n_written) *n_written = written;
   return GVE_OK;
 }

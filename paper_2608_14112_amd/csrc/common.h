@@ -106,6 +106,12 @@ struct gve_ctx {
   std::vector<gve::ItemDesc> items_host;  // copy of ws.items (what the device holds)
   std::map<std::pair<int, int>, int> resident;  // brick shape -> resident fused workgroups
   std::map<std::array<int, 4>, std::array<int, 3>> tuned;  // autotuner cache
+  // Brick shape and schedule in use while options.brick is 0 (automatic):
+  // the tuned choice for the current workload once known, else 8 x 8 x 32
+  // bricks in XCD chunks.  auto_choice: (volumes, voxels, primitives) ->
+  // (brick, brick_z, schedule).
+  int auto_bxy = 8, auto_bz = 32, auto_sched = GVE_SCHED_XCD;
+  std::map<std::array<int64_t, 3>, std::array<int, 3>> auto_choice;
   // While set, workspace buffers are carved from this fixed device region
   // (the allocation-free entry point) instead of being allocated.
   char* arena_base = nullptr;

@@ -209,13 +209,47 @@ __device__ inline uint32_t forward_steps(const ColumnSetup& s, float szv, float 
   return active;
 }
 
+// Record prefetch: every 64 pairs each lane touches (vector load) the record
+// of one of those 64 pairs, so that the pairs' scalar record loads find the
+// lines in L2.  The ids of a block of 64 pairs are loaded one block ahead and
+// a touched value is consumed one block later, so the vector loads never
+// hold the wave up; `sink` keeps them live.
+struct Touch {
+  uint32_t gid;  // this lane's pair id of the next block
+  float held;    // the last touched value (consumed at the next block)
+  float sink;
+};
+
+__device__ inline void touch_begin(const uint32_t* __restrict__ pair_gid, uint32_t j0,
+                                   uint32_t j1, Touch& t) {
+  t.gid = pair_gid[min(j0 + (threadIdx.x & 63), j1 - 1)];
+  t.held = 0.0f;
+  t.sink = 0.0f;
+}
+
+__device__ inline void touch_block(const Record* __restrict__ rec,
+                                   const uint32_t* __restrict__ pair_gid, uint32_t j,
+                                   uint32_t j1, Touch& t) {
+  t.sink += t.held;
+  t.held = reinterpret_cast<const float*>(rec + t.gid)[0];
+  t.gid = pair_gid[min(j + 64 + (threadIdx.x & 63), j1 - 1)];
+}
+
+__device__ inline void touch_end(Touch& t) {
+  t.sink += t.held;
+  asm volatile("" ::"v"(t.sink));
+}
+
 template <int BZ>
 __device__ inline void accumulate_brick(const Record* __restrict__ rec,
                                         const uint32_t* __restrict__ pair_gid, uint32_t j0,
                                         uint32_t j1, float px, float py, float pz0, int iz0,
                                         uint64_t cols, float thr, float (&acc)[BZ],
                                         uint32_t* __restrict__ steps) {
+  Touch tc;
+  if (j0 < j1) touch_begin(pair_gid, j0, j1, tc);
   for (uint32_t j = j0; j < j1; ++j) {
+    if (((j - j0) & 63u) == 0u) touch_block(rec, pair_gid, j, j1, tc);
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
     const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
@@ -226,6 +260,7 @@ __device__ inline void accumulate_brick(const Record* __restrict__ rec,
     }
     if (steps && j - j0 < kStepCap && (threadIdx.x & 63) == 0) steps[j - j0] = active;
   }
+  if (j0 < j1) touch_end(tc);
 }
 
 // ---- where a brick lies --------------------------------------------------------

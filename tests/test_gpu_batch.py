@@ -176,6 +176,44 @@ def test_autotune_picks_a_candidate_and_caches():
     assert len(t1) == 12
 
 
+def test_automatic_brick_shape():
+    """options.brick = 0: 8x8x32 bricks in XCD chunks until a call with a
+    target field tunes the workload; the tuned choice is then used by every
+    call on that workload (evaluation included), and the loss and gradient
+    are those of the oracle whatever shape was chosen."""
+    g, torch = _lib()
+    grid, n, seed = VOLUMES[2]
+    theta = _params(grid, n, seed)
+    field = _field(grid, seed)
+    ctx = g.Context(k=3.0, brick=0, deterministic=True)
+    p = g.Params(ctx, n).upload(theta.astype(np.float32))
+    gg, ft = _ggrid(g, grid), torch.from_numpy(field).cuda()
+
+    def choice():
+        st = ctx.stats()
+        return st["bin_brick"], st["bin_brick_z"], st["bin_schedule"]
+
+    g.evaluate(ctx, p, gg)
+    assert choice() == (8, 32, 1)
+    grad = torch.empty((11, n), device="cuda")
+    L = g.loss_grad(ctx, p, ft, gg, grad)
+    tuned = choice()
+    assert tuned[:2] in {(8, 8), (8, 16), (8, 32), (16, 16)} and tuned[2] in (0, 1, 2)
+    assert ctx.options.brick == 0                                 # stays automatic
+    Lr, gr = F.loss_grad(theta, field.astype(np.float64), grid, 3.0)
+    assert abs(L - Lr) <= 1e-5 * Lr
+    slack, _ = F.boundary_slack(theta, field, grid, 3.0, BAND)
+    check_grad(grad.cpu().numpy().astype(np.float64), gr, slack=slack)
+    # the kept choice: no second tuning, the same deterministic result
+    grad2 = torch.empty((11, n), device="cuda")
+    assert g.loss_grad(ctx, p, ft, gg, grad2) == L
+    assert torch.equal(grad2, grad) and choice() == tuned
+    g.evaluate(ctx, p, gg)
+    assert choice() == tuned
+    g.refine(ctx, p, ft, gg, 2)                                   # refinement too
+    assert choice() == tuned
+
+
 def test_bad_batch_arguments():
     g, torch = _lib()
     ctx = g.Context()
