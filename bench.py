@@ -18,7 +18,9 @@ Gaussians, the network trained in the same run on pairs the encoder produced.
 
 Also reported: the 300- and 2,000-iteration schedules at 1024^3 (wall seconds,
 PSNR), the 64^3 x 2,048 (20 iterations) and 256^3 x 65,536 (1,000
-iterations) workloads, and the CPU oracle (float64 NumPy) on the host's cores:
+iterations) workloads, the batched workload (32 uneven volumes refined in one
+launch per stage, aggregate in-support evaluations per second; ``--batched``
+runs it alone), and the CPU oracle (float64 NumPy) on the host's cores:
 one iteration on a bounded block of the paper-scale workload scaled by
 in-support pairs (``cpu_baseline``), plus measured brute-force and windowed
 iterations of the small and mid workloads.
@@ -260,15 +262,59 @@ class CpuOracle:
         shutil.rmtree(self.folder, ignore_errors=True)
 
 
+WS_SOURCES = ("10 tiny 64^3 mixtures / 2,048 (20 it, lr 1e-3); config-2 256^3 spectral / "
+              "65,536; 7 fronts 512^3 / 262,144 (seeds 700-706, the paper-scale generator at "
+              "the evaluation size)")
+
+
+def warm_training_set(g, torch, args, mid_pairs=None):
+    """(features, refined - allocated) pairs that the encoder produces on the
+    generators of the three plain workloads: the tiny mixture (64^3, 2,048
+    Gaussians, 20 iterations, lr 1e-3; seeds 500-509), the mid spectral field
+    (256^3, 65,536 Gaussians; the run's own mid workload when given, else
+    seed 600) and the paper-scale fronts generator at the evaluation's size
+    (512^3, 262,144 Gaussians; seeds 700-706, disjoint from the evaluation's
+    9001-9003), each refined args.ws_train_iters iterations.  Returns (pairs,
+    seconds)."""
+    import paper_2608_14112_amd.warm as W
+    from synth import fields as S
+
+    t0 = time.perf_counter()
+
+    def ctx_for(n, lr):
+        return g.Context(k=args.k, lr=lr, ell_min=math.log(0.25),
+                         ell_max=math.log(max(n / 16.0, 0.25)))
+
+    pairs = []
+    for s in range(10):
+        f, _ = S.tiny_mixture(seed=500 + s, normalize=True)
+        pairs.append(W.training_pairs(ctx_for(64, 1e-3), torch.from_numpy(f).cuda(),
+                                      g.Grid(64, 64, 64), 2048, 500 + s, 20))
+    if mid_pairs is not None:
+        pairs.extend(mid_pairs)
+    else:
+        ft = S.spectral_field((256, 256, 256), 600, device="cuda")
+        pairs.append(W.training_pairs(ctx_for(256, args.lr), ft, g.Grid(256, 256, 256), 65536,
+                                      600, args.ws_train_iters))
+        del ft
+    for s in range(7):
+        ft = S.fronts_field(512, 700 + s, device="cuda")
+        pairs.append(W.training_pairs(ctx_for(512, args.lr), ft, g.Grid(512, 512, 512), 262_144,
+                                      700 + s, args.ws_train_iters))
+        del ft
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return pairs, time.perf_counter() - t0
+
+
 def warm_start_bench(args):
     """Time-to-PSNR of warm-started vs plain refinement at equal final PSNR.
 
     Training pairs (allocation -> refined) come from the encoder itself on the
-    tiny mixture (64^3, 2,048 Gaussians, 20 iterations, lr 1e-3), mid spectral
-    fields (256^3, 65,536 Gaussians) and the paper-scale fronts field (1024^3,
-    1.4M Gaussians); the evaluation uses unseen-seed 512^3 fronts fields with
-    262,144 Gaussians.  Both arms start from the same allocation; the warm arm's
-    time includes features, network inference and the fallback check.
+    generators of the three plain workloads (warm_training_set); the
+    evaluation uses unseen-seed 512^3 fronts fields with 262,144 Gaussians.
+    Both arms start from the same allocation; the warm arm's time includes
+    features, network inference and the fallback check.
     """
     import numpy as np
     import torch
@@ -278,29 +324,13 @@ def warm_start_bench(args):
     from synth import fields as S
 
     torch.cuda.set_device(0)
-    t_all = time.perf_counter()
     iters_train = args.ws_train_iters
-    pairs = []
+    pairs, t_pairs = warm_training_set(g, torch, args)
 
     def ctx_for(n, lr):
         return g.Context(k=args.k, brick=args.brick, brick_z=args.brick_z, lr=lr,
                          ell_min=math.log(0.25), ell_max=math.log(max(n / 16.0, 0.25)))
 
-    for s in range(10):
-        f, _ = S.tiny_mixture(seed=500 + s, normalize=True)
-        ft = torch.from_numpy(f).cuda()
-        pairs.append(W.training_pairs(ctx_for(64, 1e-3), ft, g.Grid(64, 64, 64), 2048, 500 + s, 20))
-    for s in range(9):
-        ft = S.spectral_field((256, 256, 256), 600 + s, device="cuda")
-        pairs.append(W.training_pairs(ctx_for(256, args.lr), ft, g.Grid(256, 256, 256), 65536,
-                                      600 + s, iters_train))
-        del ft
-    ft = S.fronts_field(1024, args.seed, device="cuda")
-    pairs.append(W.training_pairs(ctx_for(1024, args.lr), ft, g.Grid(1024, 1024, 1024), 1_400_000,
-                                  args.seed, iters_train))
-    del ft
-    torch.cuda.empty_cache()
-    t_pairs = time.perf_counter() - t_all
     ctx = ctx_for(512, args.lr)
     t0 = time.perf_counter()
     mlp, hist, npairs = W.train_network(ctx, pairs, epochs=args.ws_epochs, batch=4096, lr=1e-3,
@@ -344,8 +374,8 @@ def warm_start_bench(args):
         "n_gpus": 1,
         "dtype": "f32 (network bf16 on MFMA, fp32 accumulation)",
         "data": "synthetic",
-        "config": {"workload": "train: 10x mixture 64^3 / 2,048, 9x spectral 256^3 / 65,536, "
-                               "1x fronts 1024^3 / 1.4M; eval: fronts 512^3 / 262,144, unseen seeds",
+        "config": {"workload": "train: " + WS_SOURCES + "; eval: fronts 512^3 / 262,144, "
+                               "unseen seeds 9001-9003",
                    "train_iterations": iters_train, "epochs": args.ws_epochs,
                    "schedules": args.ws_schedules, "pairs": npairs},
         "summary": summary,
@@ -357,17 +387,24 @@ def warm_start_bench(args):
 
 
 def batched_bench(args):
+    """--batched: the batched workload's own JSON line."""
+    import torch
+
+    torch.cuda.set_device(0)
+    print(json.dumps(batched_report(args, args.steps, args.warmup)), flush=True)
+
+
+def batched_report(args, steps, warmup):
     """Many uneven volumes refined together (one launch per stage over every
     (volume, brick) tile), autotuned brick shape and schedule; reports the
     aggregate in-support voxel-Gaussian evaluations per second of the full
-    fwd + bwd + Adam iteration."""
+    fwd + bwd + Adam iteration over `steps` timed iterations."""
     import numpy as np
     import torch
 
     import paper_2608_14112_amd as g
     from synth import fields as S
 
-    torch.cuda.set_device(0)
     t0 = time.perf_counter()
     shapes = S.batch_shapes(args.batch_items, args.seed)
     fields = [S.batch_item_field(sh, args.seed * 1000 + i, device="cuda")
@@ -399,23 +436,23 @@ def batched_bench(args):
     sched_names = ["brick order", "XCD chunks", "persistent queue"]
     print(f"[bench] autotune {t_tune:.1f}s -> {o.brick}x{o.brick}x{o.brick_z}, "
           f"{sched_names[o.schedule]}", file=sys.stderr, flush=True)
-    if args.warmup > 0:
-        g.batch_refine(ctx, B, cat, args.warmup, want_losses=False)
+    if warmup > 0:
+        g.batch_refine(ctx, B, cat, warmup, want_losses=False)
     in0, cand0 = g.batch_count_pairs(ctx, B)
     ctx.set_timing(True)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
-    hist = g.batch_refine(ctx, B, cat, args.steps)
+    hist = g.batch_refine(ctx, B, cat, steps)
     ev1.record()
     torch.cuda.synchronize()
     ctx.set_timing(False)
     st = ctx.stats()
     in1, cand1 = g.batch_count_pairs(ctx, B)
-    ms_step = ev0.elapsed_time(ev1) / args.steps
+    ms_step = ev0.elapsed_time(ev1) / steps
     pairs = 0.5 * (in0 + in1)
-    fused_ms = st["ms_fused"] / args.steps
+    fused_ms = st["ms_fused"] / steps
     achieved = FLOPS_PER_PAIR * pairs / (fused_ms * 1e-3) / 1e12
     evals = pairs / (ms_step * 1e-3)
     print(f"[bench] batched {ms_step:.2f} ms/iter, fused {fused_ms:.2f} ms, "
@@ -427,8 +464,8 @@ def batched_bench(args):
         "value": evals,
         "unit": "evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -457,8 +494,8 @@ def batched_bench(args):
             "kernel": "k_fused",
             "kernel_ms": fused_ms,
         },
-        "stages_ms": {"bin": st["ms_bin"] / args.steps, "fused": fused_ms,
-                      "update": st["ms_update"] / args.steps},
+        "stages_ms": {"bin": st["ms_bin"] / steps, "fused": fused_ms,
+                      "update": st["ms_update"] / steps},
         "work": {"pairs_in_support": pairs, "candidate_evals": 0.5 * (cand0 + cand1)},
         "autotune": [{"brick": [t[0], t[0], t[1]], "schedule": sched_names[t[2]], "ms": t[3]}
                      for t in table],
@@ -466,7 +503,11 @@ def batched_bench(args):
                     "psnr_db_max": float(10 * np.log10(1.0 / mse.min()))},
         "seconds": {"fields": t_fields, "allocation": t_alloc, "autotune": t_tune},
     }
-    print(json.dumps(out), flush=True)
+    B.close()
+    ctx.close()
+    del cat
+    torch.cuda.empty_cache()
+    return out
 
 
 def sampled_psnr(g, ctx, Pp, grid, opts, field, n_points, seed):
@@ -711,33 +752,21 @@ def other_configs(g, torch, args, ws_pairs):
     return out, cpu_inputs
 
 
-def time_to_psnr(g, torch, args, ws_pairs):
+def time_to_psnr(g, torch, args, mid_pairs):
     """Metric 2: time-to-PSNR of warm-started vs plain refinement at equal
     final PSNR on unseen-seed 512^3 fronts fields with 262,144 Gaussians.  The
     network is trained here, on (features, refined - allocated) pairs that the
-    encoder produced in this run (ws_pairs: the paper-scale and mid workloads)
-    plus tiny and mid fields of their own seeds."""
+    encoder produced in this run (warm_training_set; mid_pairs: the mid
+    workload's own)."""
     import paper_2608_14112_amd.warm as W
     from synth import fields as S
 
-    t0 = time.perf_counter()
-    pairs = list(ws_pairs)
+    pairs, t_pairs = warm_training_set(g, torch, args, mid_pairs)
 
     def ctx_for(n, lr):
         return g.Context(k=args.k, lr=lr, ell_min=math.log(0.25),
                          ell_max=math.log(max(n / 16.0, 0.25)))
 
-    for s in range(10):
-        f, _ = S.tiny_mixture(seed=500 + s, normalize=True)
-        pairs.append(W.training_pairs(ctx_for(64, 1e-3), torch.from_numpy(f).cuda(),
-                                      g.Grid(64, 64, 64), 2048, 500 + s, 20))
-    for s in range(8):
-        ft = S.spectral_field((256, 256, 256), 600 + s, device="cuda")
-        pairs.append(W.training_pairs(ctx_for(256, args.lr), ft, g.Grid(256, 256, 256), 65536,
-                                      600 + s, args.ws_train_iters))
-        del ft
-    torch.cuda.synchronize()
-    t_pairs = time.perf_counter() - t0
     ctx = ctx_for(512, args.lr)
     t1 = time.perf_counter()
     mlp, hist, npairs = W.train_network(ctx, pairs, epochs=args.ws_epochs, batch=4096, lr=1e-3,
@@ -779,8 +808,7 @@ def time_to_psnr(g, torch, args, ws_pairs):
         "runs": runs,
         "training": {"pairs": npairs, "epochs": args.ws_epochs,
                      "target_iterations": args.ws_train_iters,
-                     "sources": "paper-scale 1024^3 (this run's allocation, 300 it), 9 mid "
-                                "256^3, 10 tiny 64^3 (20 it, lr 1e-3)",
+                     "sources": WS_SOURCES,
                      "loss_first_epoch": float(hist[0]), "loss_last_epoch": float(hist[-1]),
                      "pair_seconds": t_pairs, "train_seconds": t_train},
     }
@@ -822,10 +850,8 @@ def _default_bench(args, cpu):
     print(f"[bench] field {t_field:.1f}s, allocation {t_alloc:.2f}s, "
           f"s_base {info['s_base_detail']:.3f}/{info['s_base_coverage']:.3f}", file=sys.stderr,
           flush=True)
-    # the schedules start from this allocation (and so do the warm start's
-    # paper-scale training pairs)
+    # the schedules start from this allocation
     A = _clone(g, ctx, P)
-    X3 = g.features(ctx, P, field, grid, info["n_detail"], info["g99"])
 
     # ---- metric 1: seconds per fwd + bwd + Adam iteration
     if args.warmup > 0:
@@ -954,7 +980,6 @@ def _default_bench(args, cpu):
     B = _clone(g, ctx, A)
     g.refine(ctx, _clone(g, ctx, A), field, grid, 2)
     s300, l300 = _timed_refine(g, torch, ctx, B, field, grid, 300)
-    ws_pairs = [(X3, g.targets(ctx, A, B))]
     L300 = g.loss_grad(ctx, B, field, grid)
     s1700, l1700 = _timed_refine(g, torch, ctx, B, field, grid, 1700)
     L2000 = g.loss_grad(ctx, B, field, grid)
@@ -970,10 +995,17 @@ def _default_bench(args, cpu):
           f"{s300 + s1700:.2f}s ({W.psnr(L2000, M):.2f} dB)", file=sys.stderr, flush=True)
     for c in (A, B):
         c.close()
-    del X3
 
     # ---- the tiny and mid workloads
+    ws_pairs = []
     out["configs"], cpu_inputs = other_configs(g, torch, args, ws_pairs)
+
+    # ---- the batched workload (uneven volumes in one launch per stage)
+    if not args.no_batched:
+        bt = batched_report(args, 10, 3)
+        out["batched"] = {k: bt[k] for k in ("metric", "value", "unit", "ms_per_step", "steps",
+                                             "warmup", "config", "roofline", "stages_ms",
+                                             "work", "quality", "seconds")}
 
     # ---- metric 2: time-to-PSNR, warm start vs plain
     if not args.no_time_to_psnr:
@@ -1040,8 +1072,10 @@ def main():
                     help="run the full warm-start time-to-PSNR comparison instead")
     ap.add_argument("--ws-train-iters", type=int, default=300)
     ap.add_argument("--ws-eval-iters", type=int, default=300)
-    ap.add_argument("--ws-epochs", type=int, default=20)
+    ap.add_argument("--ws-epochs", type=int, default=30)
     ap.add_argument("--ws-schedules", type=int, nargs="+", default=[300, 2000])
+    ap.add_argument("--no-batched", action="store_true",
+                    help="leave the batched workload out of the default run")
     ap.add_argument("--batched", action="store_true",
                     help="run the batched uneven-volumes benchmark instead")
     ap.add_argument("--batch-items", type=int, default=32)
