@@ -386,6 +386,21 @@ def warm_start_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_calibration(args):
+    """--calibrate-copy: three 1 GiB device-to-device copies (torch copy_), the
+    reference a counter of HBM bytes (FETCH_SIZE, WRITE_SIZE) is scaled by."""
+    import torch
+
+    torch.cuda.set_device(0)
+    n = 1 << 28                                   # float32 values: 1 GiB
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 4 * n, "copies": 3}), flush=True)
+
+
 def batched_bench(args):
     """--batched: the batched workload's own JSON line."""
     import torch
@@ -816,7 +831,7 @@ def time_to_psnr(g, torch, args, mid_pairs):
 
 def default_bench(args):
     workers = max(1, min(16, os.cpu_count() or 1))
-    cpu = None if args.no_cpu_baseline else CpuOracle(workers)
+    cpu = None if (args.no_cpu_baseline or args.iteration_only) else CpuOracle(workers)
     try:
         return _default_bench(args, cpu)
     finally:
@@ -956,6 +971,13 @@ def _default_bench(args, cpu):
         "allocation": {"seconds": t_alloc, **{k: v for k, v in info.items()}},
         "wall_s_per_iter": wall / args.steps,
     }
+    if args.iteration_only:
+        # metric 1 alone (the profiling runs): no schedules, other workloads,
+        # warm start or CPU baseline
+        A.close()
+        out["bench_seconds"] = time.perf_counter() - t_begin
+        print(json.dumps(out), flush=True)
+        return
     cpu_block = None
     if cpu is not None:
         # bounded sample for the CPU oracle: the central block of the
@@ -1074,6 +1096,11 @@ def main():
     ap.add_argument("--ws-eval-iters", type=int, default=300)
     ap.add_argument("--ws-epochs", type=int, default=30)
     ap.add_argument("--ws-schedules", type=int, nargs="+", default=[300, 2000])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="three 1 GiB device copies (reference for the HBM byte counters)")
+    ap.add_argument("--iteration-only", action="store_true",
+                    help="metric 1 alone (for profiling): skip the schedules, the other "
+                         "workloads, the warm start and the CPU baseline")
     ap.add_argument("--no-batched", action="store_true",
                     help="leave the batched workload out of the default run")
     ap.add_argument("--batched", action="store_true",
@@ -1088,11 +1115,13 @@ def main():
     if args.cpu_worker:
         return cpu_worker_main(args.cpu_worker)
     if args.gpus != 1:
-        sys.exit(f"bench.py: --gpus {args.gpus} requested, but this encoder is measured on one "
-                 "GPU only; multi-GPU runs are not part of this build.")
+        sys.exit(f"bench.py: --gpus {args.gpus} requested, but this encoder runs and is "
+                 "measured on one GPU only (it has no multi-GPU path).")
 
     if args.warm_start:
         return warm_start_bench(args)
+    if args.calibrate_copy:
+        return copy_calibration(args)
     if args.batched:
         return batched_bench(args)
     if args.paper:
