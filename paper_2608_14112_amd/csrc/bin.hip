@@ -300,16 +300,33 @@ __global__ __launch_bounds__(kThreads) void k_emit_kept(const uint32_t* __restri
   const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kGroup;
   const uint32_t sub = threadIdx.x & (kGroup - 1);
   if (i >= n || (fits && *fits == 0u)) return;
-  const uint32_t o = offset[i];
-  const uint32_t cnt = offset[i + 1] - o;
-  const uint32_t src = box_off[i];
-  for (uint32_t j = sub; j < cnt; j += kGroup) {
-    keys[o + j] = kept[src + j];
-    if (owner) {
-      vals[o + j] = o + j;
-      owner[o + j] = (uint32_t)i;
-    } else {
-      vals[o + j] = (uint32_t)i;
+  // the three loads waited for together (pinning src here keeps its load
+  // from moving into the loop below, behind the offsets' latency)
+  const uint32_t o = offset[i], o1 = offset[i + 1];
+  uint32_t src = box_off[i];
+  asm volatile("" : "+v"(src));
+  const uint32_t cnt = o1 - o;
+  // four strides of the group at a time, loads issued before the stores
+  constexpr int kUnroll = 4;
+  for (uint32_t j0 = sub; j0 < cnt; j0 += kUnroll * kGroup) {
+    uint32_t key[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint32_t j = j0 + u * kGroup;
+      key[u] = j < cnt ? kept[src + j] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint32_t j = j0 + u * kGroup;
+      if (j < cnt) {
+        keys[o + j] = key[u];
+        if (owner) {
+          vals[o + j] = o + j;
+          owner[o + j] = (uint32_t)i;
+        } else {
+          vals[o + j] = (uint32_t)i;
+        }
+      }
     }
   }
 }

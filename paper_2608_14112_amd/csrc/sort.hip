@@ -38,12 +38,19 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ 
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = 0u;
     return;
   }
+  // the tile's keys, all loads issued before the first count
+  uint32_t tk[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    tk[r] = i < n ? keys[i] : 0u;
+  }
   cnt[threadIdx.x] = 0;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
-    int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1u);
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(tk[r] >> shift) & mask], 1u);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
@@ -78,30 +85,41 @@ __global__ __launch_bounds__(kThreads) void k_scatter(
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
   n = items_of(n, dn);
   if ((int64_t)blockIdx.x * kTile >= n) return;  // a tile past the items: nothing to move
+  // the tile's items, all loads issued at once (the rounds below are
+  // separated by barriers, which would otherwise expose one load latency
+  // per round)
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  uint32_t tk[kRounds], tv[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    tk[r] = i < n ? kin[i] : 0u;
+    tv[r] = i < n ? vin[i] : 0u;
+  }
   __shared__ uint32_t skey[kTile], sval[kTile];
   __shared__ uint32_t bstart[kRadix];         // tile-local start of each digit
   __shared__ uint32_t run[kRadix];            // items of each digit already staged
   __shared__ uint32_t wcnt[kWaves][kRadix];   // this round's count per wave and digit
   __shared__ uint32_t wsum[kWaves];
+  __shared__ uint32_t delta[kRadix];          // output position - tile-local position, per digit
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const uint32_t mine = hist[(int64_t)threadIdx.x * ntiles + blockIdx.x];
-  bstart[threadIdx.x] = block_exclusive_scan(mine, wsum);
+  const uint32_t out0 = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+  const uint32_t start = block_exclusive_scan(mine, wsum);
+  bstart[threadIdx.x] = start;
+  delta[threadIdx.x] = out0 - start;
   run[threadIdx.x] = 0;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
   for (int r = 0; r < kRounds; ++r) {
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
     __syncthreads();
     const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
     const bool valid = i < n;
-    uint32_t key = 0, val = 0, d = 0;
-    if (valid) {
-      key = kin[i];
-      val = vin[i];
-      d = (key >> shift) & mask;
-    }
+    const uint32_t key = tk[r], val = tv[r];
+    const uint32_t d = valid ? (key >> shift) & mask : 0u;
     // lanes holding the same digit (invalid lanes excluded)
     uint64_t same = __ballot(valid);
     for (int b = 0; b < wbits; ++b) {
@@ -127,8 +145,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(
   const int64_t cnt = (n - base) < kTile ? (n - base) : kTile;
   for (int j = threadIdx.x; j < cnt; j += kThreads) {
     const uint32_t key = skey[j];
-    const uint32_t d = (key >> shift) & mask;
-    const uint32_t pos = offs[(int64_t)d * ntiles + blockIdx.x] + ((uint32_t)j - bstart[d]);
+    const uint32_t pos = (uint32_t)j + delta[(key >> shift) & mask];
     kout[pos] = key;
     vout[pos] = sval[j];
   }
