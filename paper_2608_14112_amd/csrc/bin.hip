@@ -252,16 +252,24 @@ __global__ __launch_bounds__(kThreads) void k_cull(const Record* __restrict__ re
   // buffers sized in advance: when the box pairs do not fit, nothing is kept
   const bool room = fits == nullptr || *fits != 0u;
   uint32_t o = 0, total = 0;
+  Record r{};
   if (live && room) {
+    // the offsets and the record loaded together, one wait for all (pinning
+    // the record here keeps its loads from following the offsets' latency)
     o = box_off[i];
     total = box_off[i + 1] - o;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4* src = reinterpret_cast<const u32x4*>(rec + i);
+    u32x4 q[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) q[h] = src[h];
+    asm volatile("" ::"v"(q[0]), "v"(q[1]), "v"(q[2]), "v"(q[3]));
+    __builtin_memcpy(&r, q, sizeof(Record));
   }
   if (live && !room && sub == 0) count[i] = 0;
-  Record r{};
   BoxBricks bb{};
   const ItemDesc* it = items;
   if (total > 0) {
-    r = rec[i];
     bb = box_bricks(r, bg);
     it = &items[item_of_prim(items, nitems, (uint32_t)i)];
   }
