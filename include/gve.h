@@ -151,6 +151,9 @@ typedef struct gve_stats {
   /* Brick edge, brick depth and schedule of the last binning (with
    * options.brick = 0, the automatic choice). */
   int64_t bin_brick, bin_brick_z, bin_schedule;
+  /* Primitives whose quaternion had |q| < 1e-12 at the last binning; they
+   * are evaluated with the identity rotation. */
+  int64_t n_degenerate_q;
 } gve_stats;
 
 typedef struct gve_ctx gve_ctx;
@@ -359,6 +362,25 @@ gve_status gve_checkpoint_load(gve_ctx* ctx, const void* h_buf, size_t buf_bytes
  * Timing records events between the stages of every iteration; it does not
  * add synchronisation (the elapsed times are read at the end of the call). */
 gve_status gve_set_timing(gve_ctx* ctx, int32_t enable);
+
+/*
+ * Measured rates of the units that bound the brick kernels (Sec. III-G's cost
+ * is these kernels), from the library's own probe kernels timed with HIP
+ * events on the context's stream (median of five launches after a warm-up):
+ *   fma_flops_per_s    fp32 FMA issue, eight independent chains per lane,
+ *                      2 flops per FMA (non-packed instructions);
+ *   exp_per_s          v_exp_f32, eight independent chains per lane;
+ *   copy_bytes_per_s   a 1 GiB device copy (0.5 GiB read + 0.5 GiB written);
+ *   atomic_instr_per_s float atomic instructions whose ten active lanes add
+ *                      into one 64-byte line (the fused kernel's pattern),
+ *                      over 2^20 distinct lines.
+ * Allocates and frees 1 GiB of device memory; synchronises.  OUT_OF_MEMORY if
+ * the buffer cannot be allocated, DEVICE on a launch failure.
+ */
+typedef struct gve_probe_rates {
+  double fma_flops_per_s, exp_per_s, copy_bytes_per_s, atomic_instr_per_s;
+} gve_probe_rates;
+gve_status gve_probe(gve_ctx* ctx, gve_probe_rates* h_out);
 
 /*
  * Work counters of one truncated evaluation on grid g (Sec. III-G measures the

@@ -88,7 +88,12 @@ class StatsC(ctypes.Structure):
                 ("n_candidates", ctypes.c_int64), ("n_atomics", ctypes.c_int64),
                 ("n_nonfinite", ctypes.c_int64), ("n_resized", ctypes.c_int64),
                 ("bin_brick", ctypes.c_int64), ("bin_brick_z", ctypes.c_int64),
-                ("bin_schedule", ctypes.c_int64)]
+                ("bin_schedule", ctypes.c_int64), ("n_degenerate_q", ctypes.c_int64)]
+
+
+class ProbeC(ctypes.Structure):
+    _fields_ = [("fma_flops_per_s", ctypes.c_double), ("exp_per_s", ctypes.c_double),
+                ("copy_bytes_per_s", ctypes.c_double), ("atomic_instr_per_s", ctypes.c_double)]
 
 
 class AllocInfoC(ctypes.Structure):
@@ -148,6 +153,7 @@ _SIGS = {
     "gve_warmstart": [_vp, _vp, _vp, _vp, GridC, _i64, ctypes.c_double,
                       ctypes.POINTER(ctypes.c_int32), _vp],
     "gve_count_pairs": [_vp, _vp, GridC, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+    "gve_probe": [_vp, ctypes.POINTER(ProbeC)],
     "gve_bin_pairs": [_vp, _vp, GridC, _vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64),
                       ctypes.POINTER(_i64)],
     "gve_batch_create": [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(_vp)],
@@ -503,6 +509,13 @@ def count_pairs(ctx: Context, params: Params, grid: Grid):
     _check(_lib.gve_count_pairs(ctx.handle, params.handle, grid.c(), ctypes.byref(a),
                                 ctypes.byref(b)), ctx.handle)
     return a.value, b.value
+
+
+def probe(ctx: Context):
+    """gve_probe: measured fp32 FMA, exponential, copy and atomic rates (dict)."""
+    r = ProbeC()
+    _check(_lib.gve_probe(ctx.handle, ctypes.byref(r)), ctx.handle)
+    return {f: getattr(r, f) for f, _ in ProbeC._fields_}
 
 
 MLP_NWEIGHT = 20107

@@ -128,10 +128,10 @@ gve_status ensure(gve_ctx* ctx, Scratch& s, size_t bytes) {
 // Small device block: [0] loss (double), [2] clamp count and [3] non-finite
 // parameter count (u64, cumulative), [4 .. 6] work counters of the counting
 // pass, [16 ..] loss-reduction partials, then kTotalSlots pair-total counters
-// (u64).  Zeroed when first allocated.
+// and the degenerate-quaternion counter (u64).  Zeroed when first allocated.
 gve_status ensure_dloss(gve_ctx* ctx) {
   if (ctx->ws.dloss.ptr) return GVE_OK;
-  const size_t nd = 16 + gve::loss_reduce_tmp_doubles() + gve::kTotalSlots;
+  const size_t nd = 16 + gve::loss_reduce_tmp_doubles() + gve::kTotalSlots + 1;
   TRY(ensure(ctx, ctx->ws.dloss, sizeof(double) * nd));
   TRY_HIP(ctx, gve::fill_u64(static_cast<unsigned long long*>(ctx->ws.dloss.ptr), (int64_t)nd,
                              ctx->stream));
@@ -312,7 +312,7 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   TRY(ensure(ctx, ws.scan_tmp, gve::scan_tmp_bytes(n + 1)));
   TRY(ensure_dloss(ctx));
   unsigned long long* total = pair_total_slots(ctx);
-  TRY_HIP(ctx, gve::fill_u64(total, gve::kTotalSlots, s));
+  TRY_HIP(ctx, gve::fill_u64(total, gve::kTotalSlots + 1, s));
   TRY_HIP(ctx, gve::launch_prep(p->theta, n, items, vol.n, ctx->opt.k, bg, p->rec, p->count,
                                 total, s));
   // Culling drops bricks a separating plane parts from the support.  The box
@@ -334,13 +334,16 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
     fits = fits_flag(ctx);
     dn = p->offset + n;
   } else {
-    static_assert(sizeof(unsigned long long) * gve::kTotalSlots <= 256, "pinned staging size");
-    TRY_HIP(ctx, hipMemcpyAsync(hp, total, sizeof(unsigned long long) * gve::kTotalSlots,
+    static_assert(sizeof(unsigned long long) * (gve::kTotalSlots + 1) <= 512,
+                  "pinned staging size");
+    TRY_HIP(ctx, hipMemcpyAsync(hp, total, sizeof(unsigned long long) * (gve::kTotalSlots + 1),
                                 hipMemcpyDeviceToHost, s));
     TRY_HIP(ctx, hipStreamSynchronize(s));
     unsigned long long box_total = 0;
     for (int j = 0; j < gve::kTotalSlots; ++j)
       box_total += reinterpret_cast<const unsigned long long*>(hp)[j];
+    ctx->stats.n_degenerate_q =
+        (int64_t) reinterpret_cast<const unsigned long long*>(hp)[gve::kTotalSlots];
     if (box_total >= 0xFFFFFFF0ull)
       return fail(ctx, GVE_ERR_UNSUPPORTED,
                   "more than 2^32 (primitive, brick) pairs; use larger bricks or a smaller k");
@@ -450,7 +453,7 @@ gve_status prep_only(gve_ctx* ctx, const gve_params* p, const gve_grid& g) {
   TRY(upload_items(ctx, Vol{&g, off, 1}, brick_xy(ctx), brick_z(ctx), &nbricks));
   TRY(ensure_dloss(ctx));
   unsigned long long* total = pair_total_slots(ctx);
-  TRY_HIP(ctx, gve::fill_u64(total, gve::kTotalSlots, ctx->stream));
+  TRY_HIP(ctx, gve::fill_u64(total, gve::kTotalSlots + 1, ctx->stream));
   gve::BrickGeom bg;
   bg.Bxy = brick_xy(ctx);
   bg.Bz = brick_z(ctx);
@@ -618,7 +621,7 @@ gve_status gve_create(gve_ctx** out, const gve_options* opt, void* hip_stream) {
   }
   ctx->opt = o;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
-  if (hipGetDevice(&ctx->device) != hipSuccess || hipHostMalloc(&ctx->ws.h_pinned, 256) != hipSuccess) {
+  if (hipGetDevice(&ctx->device) != hipSuccess || hipHostMalloc(&ctx->ws.h_pinned, 512) != hipSuccess) {
     delete ctx;
     return GVE_ERR_DEVICE;
   }
@@ -1110,6 +1113,69 @@ gve_status gve_set_timing(gve_ctx* ctx, int32_t enable) {
   return GVE_OK;
 }
 
+gve_status gve_probe(gve_ctx* ctx, gve_probe_rates* h_out) {
+  if (!ctx) return GVE_ERR_INVALID_ARGUMENT;
+  ctx->last_error.clear();
+  if (!h_out) return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "h_out is NULL");
+  TRY(set_device(ctx));
+  const int64_t n = (int64_t)1 << 28;  // floats: 1 GiB
+  float* buf = nullptr;
+  if (hipMalloc(&buf, sizeof(float) * (size_t)n) != hipSuccess)
+    return fail(ctx, GVE_ERR_OUT_OF_MEMORY, "probe buffer (1 GiB)");
+  struct Free {
+    float* p;
+    ~Free() { hipFree(p); }
+  } guard{buf};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TRY_HIP(ctx, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(ctx, GVE_ERR_DEVICE, "hipEventCreate");
+  }
+  struct Events {
+    hipEvent_t a, b;
+    ~Events() {
+      hipEventDestroy(a);
+      hipEventDestroy(b);
+    }
+  } events{e0, e1};
+  hipStream_t s = ctx->stream;
+  // 8 waves per SIMD on 256 CUs: 2,048 blocks of 4 waves
+  const int blocks = 2048;
+  const double threads = (double)blocks * gve::probe_threads();
+  const double chains = gve::probe_chains();
+  auto timed = [&](int kind, int64_t len, int iters, int nblocks, double* ms) -> gve_status {
+    TRY_HIP(ctx, gve::launch_probe(kind, buf, len, iters, nblocks, s));  // warm-up
+    std::vector<float> t;
+    for (int r = 0; r < 5; ++r) {
+      TRY_HIP(ctx, hipEventRecord(e0, s));
+      TRY_HIP(ctx, gve::launch_probe(kind, buf, len, iters, nblocks, s));
+      TRY_HIP(ctx, hipEventRecord(e1, s));
+      TRY_HIP(ctx, hipEventSynchronize(e1));
+      float v = 0.0f;
+      TRY_HIP(ctx, hipEventElapsedTime(&v, e0, e1));
+      t.push_back(v);
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return GVE_OK;
+  };
+  TRY_HIP(ctx, hipMemsetAsync(buf, 0, sizeof(float) * (size_t)n, s));
+  double ms = 0.0;
+  const int it_fma = 16384, it_exp = 4096, it_atomic = 256;
+  TRY(timed(gve::kProbeFma, n, it_fma, blocks, &ms));
+  h_out->fma_flops_per_s = 2.0 * chains * it_fma * threads / (ms * 1e-3);
+  TRY(timed(gve::kProbeExp, n, it_exp, blocks, &ms));
+  h_out->exp_per_s = chains * it_exp * threads / (ms * 1e-3);
+  TRY(timed(gve::kProbeCopy, n, 1, blocks * 4, &ms));
+  h_out->copy_bytes_per_s = (double)sizeof(float) * (double)n / (ms * 1e-3);
+  const int64_t lines = (int64_t)1 << 20;
+  TRY_HIP(ctx, gve::fill_f32(buf, gve::kAccStride * lines, 0.0f, s));
+  TRY(timed(gve::kProbeAtomic, gve::kAccStride * lines, it_atomic, blocks, &ms));
+  h_out->atomic_instr_per_s = (threads / 64.0) * it_atomic / (ms * 1e-3);
+  return GVE_OK;
+}
+
 gve_status gve_count_pairs(gve_ctx* ctx, const gve_params* p, gve_grid g, int64_t* h_in_support,
                            int64_t* h_candidates) {
   TRY(check_ctx_params(ctx, p));
@@ -1334,10 +1400,14 @@ gve_status refine_vol(gve_ctx* ctx, gve_params* p, const float* d_field, const V
     }
   }
   if (iters > 0) {
-    TRY_HIP(ctx, hipMemcpyAsync(ctx->ws.h_pinned, p->offset + p->n, sizeof(uint32_t),
-                                hipMemcpyDeviceToHost, s));
+    // pair and degenerate-quaternion counts of the last (asynchronous) binning
+    unsigned char* hp = static_cast<unsigned char*>(ctx->ws.h_pinned);
+    TRY_HIP(ctx, hipMemcpyAsync(hp, p->offset + p->n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    TRY_HIP(ctx, hipMemcpyAsync(hp + 8, pair_total_slots(ctx) + gve::kTotalSlots,
+                                sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     TRY_HIP(ctx, hipStreamSynchronize(s));
-    ctx->stats.n_overlaps = (int64_t) * static_cast<const uint32_t*>(ctx->ws.h_pinned);
+    ctx->stats.n_overlaps = (int64_t) * reinterpret_cast<const uint32_t*>(hp);
+    ctx->stats.n_degenerate_q = (int64_t) * reinterpret_cast<const unsigned long long*>(hp + 8);
   }
   return refine_finish(ctx, p, vol, iters, hist, h_loss_hist, timing);
 }

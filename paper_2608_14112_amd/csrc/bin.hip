@@ -33,14 +33,15 @@ __device__ inline int item_of_prim(const ItemDesc* __restrict__ items, int nitem
 
 __device__ inline uint32_t prep_one(const float* __restrict__ theta, int64_t n, int64_t i,
                                     const ItemDesc& g, float k, BrickGeom bg,
-                                    Record* __restrict__ rec) {
+                                    Record* __restrict__ rec, bool& degenerate) {
   const float mx = theta[0 * n + i], my = theta[1 * n + i], mz = theta[2 * n + i];
   float qw = theta[3 * n + i], qx = theta[4 * n + i], qy = theta[5 * n + i],
         qz = theta[6 * n + i];
   const float lx = theta[7 * n + i], ly = theta[8 * n + i], lz = theta[9 * n + i];
   const float c = theta[10 * n + i];
   const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-  if (qn >= 1e-12f) {
+  degenerate = !(qn >= 1e-12f);
+  if (!degenerate) {
     const float inv = 1.0f / qn;
     qw *= inv; qx *= inv; qy *= inv; qz *= inv;
   } else {
@@ -126,8 +127,15 @@ __global__ __launch_bounds__(kThreads) void k_prep(const float* __restrict__ the
                                                    unsigned long long* __restrict__ total) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   uint32_t cnt = 0;
-  if (i < n) cnt = prep_one(theta, n, i, items[item_of_prim(items, nitems, (uint32_t)i)], k, bg, rec);
+  bool degenerate = false;
+  if (i < n)
+    cnt = prep_one(theta, n, i, items[item_of_prim(items, nitems, (uint32_t)i)], k, bg, rec,
+                   degenerate);
   if (i < n) count[i] = cnt;
+  // degenerate quaternions (rare): one atomic per wave that has any
+  const uint64_t deg = __builtin_amdgcn_ballot_w64(degenerate);
+  if (deg != 0ull && (threadIdx.x & 63) == 0)
+    atomicAdd(&total[kTotalSlots], (unsigned long long)__popcll(deg));
   // 64-bit pair total (the scan itself is 32-bit): one atomic per block, into
   // one of kTotalSlots counters
   __shared__ unsigned long long wsum[kThreads / 64];

@@ -89,7 +89,7 @@ struct Workspace {
   Scratch dense;                 // float [M] residual of the dense reference path
   Scratch snap;                  // float [3][11][n] parameters and Adam moments (refinement
                                  // restart point) + counters
-  void* h_pinned = nullptr;      // pinned host staging (64 bytes)
+  void* h_pinned = nullptr;      // pinned host staging (512 bytes)
 };
 
 }  // namespace gve
@@ -184,10 +184,11 @@ struct Schedule {
 };
 
 // Writes rec and count for every primitive and adds the pair total to *total
-// (which the caller zeroes first).
+// (which the caller zeroes first, kTotalSlots + 1 counters).
 // The prep kernel adds each block's box brick count to total[block % kTotalSlots]
 // (64-bit): spreading the atomics over several addresses keeps them from
-// queueing on one; the host sums the slots.
+// queueing on one; the host sums the slots.  total[kTotalSlots] counts the
+// primitives whose quaternion has |q| < 1e-12 (taken as the identity).
 constexpr int kTotalSlots = 32;
 hipError_t launch_prep(const float* theta, int64_t n, const ItemDesc* items, int nitems, float k,
                        BrickGeom bg, Record* rec, uint32_t* count, unsigned long long* total,
@@ -264,6 +265,16 @@ hipError_t launch_dense_forward(const Record* rec, int64_t n, const gve_grid& g,
                                 hipStream_t s);
 hipError_t launch_dense_backward(const Record* rec, int64_t n, const gve_grid& g, float k,
                                  const float* resid, float* acc, hipStream_t s);
+
+// Rate probes (probe.hip): kProbeFma / kProbeExp run `iters` steps of
+// probe_chains() independent chains per thread over `blocks` blocks of
+// probe_threads() threads, writing one float per thread to buf; kProbeCopy
+// copies buf[0, n/2) to buf[n/2, n) (n a multiple of 8); kProbeAtomic adds into
+// buf viewed as n / kAccStride 64-byte lines, `iters` instructions per wave.
+enum { kProbeFma = 0, kProbeExp = 1, kProbeCopy = 2, kProbeAtomic = 3 };
+hipError_t launch_probe(int kind, float* buf, int64_t n, int iters, int blocks, hipStream_t s);
+int probe_threads();
+int probe_chains();
 
 // Small utility kernels.
 hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t s);

@@ -177,9 +177,11 @@ def test_edge_cases():
     grid2 = F.Grid(9, 8, 17)
     p2 = _case(6, grid2, 8)
     p2[3:7, 0] = 0.0
-    got2, _ = _eval_gpu(g, torch, p2, grid2, 3.0, 16)
+    p2[3:7, 3] = 1e-14                       # |q| = 2e-14: also below the limit
+    got2, st2 = _eval_gpu(g, torch, p2, grid2, 3.0, 16)
     V2, A2, br = F.evaluate_windowed(p2, grid2, 3.0, band=BAND)
     check_field(got2, V2, A2, br)
+    assert st2["n_degenerate_q"] == 2        # counted
 
 
 # ----------------------------------------------------------------------------- gradient
