@@ -449,7 +449,8 @@ def batched_report(args, steps, warmup):
     o = ctx.options
     sched_names = ["brick order", "XCD chunks", "persistent queue"]
     print(f"[bench] autotune {t_tune:.1f}s -> {o.brick}x{o.brick}x{o.brick_z}, "
-          f"{sched_names[o.schedule]}", file=sys.stderr, flush=True)
+          f"{o.brick_waves} wave(s) per brick, {sched_names[o.schedule]}", file=sys.stderr,
+          flush=True)
     if warmup > 0:
         g.batch_refine(ctx, B, cat, warmup, want_losses=False)
     in0, cand0 = g.batch_count_pairs(ctx, B)
@@ -496,7 +497,8 @@ def batched_report(args, steps, warmup):
             "voxels": M,
             "gaussians": int(B.params.n),
             "seed": args.seed,
-            "tuned": {"brick": [o.brick, o.brick, o.brick_z], "schedule": sched_names[o.schedule]},
+            "tuned": {"brick": [o.brick, o.brick, o.brick_z], "waves": o.brick_waves,
+                      "schedule": sched_names[o.schedule]},
         },
         "roofline": {
             "bound": "alu",
@@ -511,8 +513,8 @@ def batched_report(args, steps, warmup):
         "stages_ms": {"bin": st["ms_bin"] / steps, "fused": fused_ms,
                       "update": st["ms_update"] / steps},
         "work": {"pairs_in_support": pairs, "candidate_evals": 0.5 * (cand0 + cand1)},
-        "autotune": [{"brick": [t[0], t[0], t[1]], "schedule": sched_names[t[2]], "ms": t[3]}
-                     for t in table],
+        "autotune": [{"brick": [t[0], t[0], t[1]], "waves": t[4], "schedule": sched_names[t[2]],
+                      "ms": t[3]} for t in table],
         "quality": {"psnr_db_min": float(10 * np.log10(1.0 / mse.max())),
                     "psnr_db_max": float(10 * np.log10(1.0 / mse.min()))},
         "seconds": {"fields": t_fields, "allocation": t_alloc, "autotune": t_tune},
@@ -701,7 +703,7 @@ def _timed_refine(g, torch, ctx, P, field, grid, iters):
 
 def _tuned(ctx):
     o = ctx.options
-    return {"brick": [o.brick, o.brick, o.brick_z],
+    return {"brick": [o.brick, o.brick, o.brick_z], "waves": o.brick_waves,
             "schedule": ["brick order", "XCD chunks", "persistent queue"][o.schedule]}
 
 

@@ -77,7 +77,8 @@ typedef struct gve_grid {
  * 5).  brick, brick_z: primitives are binned to bricks of brick x brick x
  * brick_z voxels; supported shapes are 8x8x8, 8x8x16, 8x8x32 and 16x16x16
  * (brick_z 0 picks the same as brick).  brick 0 is automatic: the shape and
- * the schedule are chosen per workload (volumes, total voxels, primitives):
+ * the schedule are chosen per workload (each volume's dimensions and
+ * primitive count):
  * the choice made earlier for that workload if any; else, on a call with a
  * target field (gve_loss_grad, gve_refine, gve_batch_loss_grad,
  * gve_batch_refine; not the allocation-free entry point), the fastest of
@@ -102,6 +103,11 @@ typedef struct gve_grid {
  * the records its bricks share; GVE_SCHED_QUEUE a persistent launch whose
  * workgroups take bricks from a work queue, heaviest first.  gve_autotune
  * measures which is fastest for a workload.
+ * brick_waves: waves per brick in the fused kernel (0 or 1: one; 2 or 4 with
+ * 8 x 8 columns: the waves share the brick's columns and split its
+ * (primitive, brick) pairs, which puts more waves to work when a workload has
+ * few bricks; the field's summation order then depends on it, within float32
+ * rounding).  Evaluation alone always uses one.
  */
 enum { GVE_SCHED_INDEX = 0, GVE_SCHED_XCD = 1, GVE_SCHED_QUEUE = 2 };
 typedef struct gve_options {
@@ -112,6 +118,7 @@ typedef struct gve_options {
   int32_t brick_z;
   int32_t deterministic;
   int32_t schedule;
+  int32_t brick_waves;
 } gve_options;
 
 /* Counters of the most recent evaluation / refinement iteration. */
@@ -154,6 +161,8 @@ typedef struct gve_stats {
   /* Primitives whose quaternion had |q| < 1e-12 at the last binning; they
    * are evaluated with the identity rotation. */
   int64_t n_degenerate_q;
+  /* Waves per brick of the last binning's fused kernel (brick_waves). */
+  int64_t bin_waves;
 } gve_stats;
 
 typedef struct gve_ctx gve_ctx;
@@ -470,6 +479,7 @@ gve_status gve_batch_count_pairs(gve_ctx* ctx, const gve_batch* b, int64_t* h_in
 typedef struct gve_tune_entry {
   int32_t brick, brick_z, schedule;
   float ms;  /* median over the reps */
+  int32_t waves;
 } gve_tune_entry;
 gve_status gve_autotune(gve_ctx* ctx, const gve_params* p, const float* d_field, gve_grid g,
                         const gve_batch* b, int32_t reps, gve_tune_entry* h_table,

@@ -59,7 +59,7 @@ class OptionsC(ctypes.Structure):
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("ell_min", ctypes.c_float), ("ell_max", ctypes.c_float),
                 ("brick_z", ctypes.c_int32), ("deterministic", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("brick_waves", ctypes.c_int32)]
 
 
 class PaperOptionsC(ctypes.Structure):
@@ -72,7 +72,7 @@ class PaperOptionsC(ctypes.Structure):
 
 class TuneEntryC(ctypes.Structure):
     _fields_ = [("brick", ctypes.c_int32), ("brick_z", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("ms", ctypes.c_float)]
+                ("schedule", ctypes.c_int32), ("ms", ctypes.c_float), ("waves", ctypes.c_int32)]
 
 
 SCHED_INDEX, SCHED_XCD, SCHED_QUEUE = 0, 1, 2
@@ -88,7 +88,8 @@ class StatsC(ctypes.Structure):
                 ("n_candidates", ctypes.c_int64), ("n_atomics", ctypes.c_int64),
                 ("n_nonfinite", ctypes.c_int64), ("n_resized", ctypes.c_int64),
                 ("bin_brick", ctypes.c_int64), ("bin_brick_z", ctypes.c_int64),
-                ("bin_schedule", ctypes.c_int64), ("n_degenerate_q", ctypes.c_int64)]
+                ("bin_schedule", ctypes.c_int64), ("n_degenerate_q", ctypes.c_int64),
+                ("bin_waves", ctypes.c_int64)]
 
 
 class ProbeC(ctypes.Structure):
@@ -253,7 +254,7 @@ class Context:
 
     def __init__(self, k=3.0, brick=8, lr=8e-3, beta1=0.9, beta2=0.999, eps=1e-8,
                  ell_min=-math.inf, ell_max=math.inf, brick_z=None, deterministic=False,
-                 schedule=None, stream=None):
+                 schedule=None, stream=None, brick_waves=1):
         import torch
 
         if brick_z is None:                       # library default shape 8 x 8 x 32
@@ -262,7 +263,7 @@ class Context:
             schedule = default_options().schedule
         self._torch_stream = stream if stream is not None else torch.cuda.current_stream()
         o = OptionsC(k, brick, lr, beta1, beta2, eps, ell_min, ell_max, brick_z,
-                     1 if deterministic else 0, schedule)
+                     1 if deterministic else 0, schedule, brick_waves)
         h = _vp()
         st = _lib.gve_create(ctypes.byref(h), ctypes.byref(o),
                              _vp(self._torch_stream.cuda_stream))
@@ -799,27 +800,29 @@ def batch_count_pairs(ctx: Context, batch: Batch):
 
 def autotune(ctx: Context, field, params: Params = None, grid: Grid = None, batch: Batch = None,
              reps=3):
-    """gve_autotune: pick the fastest brick shape and schedule for this workload.
+    """gve_autotune: pick the fastest brick shape, waves per brick and schedule for
+    this workload.
 
-    Returns a list of (brick, brick_z, schedule, ms) per candidate timed (empty
-    when the context's cache already held the answer); the context keeps the
-    choice.
+    Returns a list of (brick, brick_z, schedule, ms, waves) per candidate timed
+    (empty when the context's cache already held the answer); the context keeps
+    the choice.
     """
     import torch
 
-    table = (TuneEntryC * 16)()
+    cap = 64
+    table = (TuneEntryC * cap)()
     nw = ctypes.c_int32()
     if batch is not None:
         fp = _ptr(field, torch.float32, int(batch.voxel_offsets[-1]))
         st = _lib.gve_autotune(ctx.handle, None, fp, GridC(), batch.handle, ctypes.c_int32(reps),
-                               ctypes.cast(table, _vp), 16, ctypes.byref(nw))
+                               ctypes.cast(table, _vp), cap, ctypes.byref(nw))
     else:
         fp = _ptr(field, torch.float32, grid.nx * grid.ny * grid.nz)
         st = _lib.gve_autotune(ctx.handle, params.handle, fp, grid.c(), None,
-                               ctypes.c_int32(reps), ctypes.cast(table, _vp), 16,
+                               ctypes.c_int32(reps), ctypes.cast(table, _vp), cap,
                                ctypes.byref(nw))
     _check(st, ctx.handle)
-    return [(e.brick, e.brick_z, e.schedule, e.ms) for e in table[:nw.value]]
+    return [(e.brick, e.brick_z, e.schedule, e.ms, e.waves) for e in table[:nw.value]]
 
 
 # ---- the paper's own training loop ------------------------------------------------------

@@ -146,11 +146,14 @@ unsigned long long* pair_total_slots(gve_ctx* ctx) {
 gve_status validate_options(const gve_ctx* ctx, const gve_options& o) {
   if (!(o.k > 0.0f) || !std::isfinite(o.k) || o.k > 64.0f)
     return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "k must be finite, > 0 and <= 64");
-  if (o.brick != 0) {  // brick 0: automatic (brick_z is then not used)
+  if (o.brick != 0) {  // brick 0: automatic (brick_z and brick_waves are then not used)
     const int bz = o.brick_z == 0 ? o.brick : o.brick_z;
     if (!gve::brick_shape_supported(o.brick, bz))
       return fail(ctx, GVE_ERR_UNSUPPORTED,
                   "brick shape must be 8x8x8, 8x8x16, 8x8x32 or 16x16x16");
+    if (!gve::brick_waves_supported(o.brick, bz, o.brick_waves == 0 ? 1 : o.brick_waves))
+      return fail(ctx, GVE_ERR_UNSUPPORTED,
+                  "brick_waves must be 0 or 1, or 2 or 4 with 8 x 8 columns");
   }
   if (!(o.lr >= 0.0f) || !std::isfinite(o.lr))
     return fail(ctx, GVE_ERR_INVALID_ARGUMENT, "lr must be finite and >= 0");
@@ -189,6 +192,10 @@ int brick_z(const gve_ctx* ctx) {
 }
 int sched_of(const gve_ctx* ctx) {
   return ctx->opt.brick == 0 ? ctx->auto_sched : ctx->opt.schedule;
+}
+int waves_of(const gve_ctx* ctx) {
+  if (ctx->opt.brick == 0) return ctx->auto_waves;
+  return ctx->opt.brick_waves == 0 ? 1 : ctx->opt.brick_waves;
 }
 
 struct Vol;
@@ -243,11 +250,11 @@ gve_status upload_items(gve_ctx* ctx, const Vol& vol, int Bxy, int Bz, int64_t* 
   return GVE_OK;
 }
 
-int resident_groups(gve_ctx* ctx, int bxy, int bz) {
-  auto key = std::make_pair(bxy, bz);
+int resident_groups(gve_ctx* ctx, int bxy, int bz, int waves) {
+  const std::array<int, 3> key = {bxy, bz, waves};
   auto it = ctx->resident.find(key);
   if (it != ctx->resident.end()) return it->second;
-  const int r = gve::fused_resident_groups(bxy, bz, ctx->device);
+  const int r = gve::fused_resident_groups(bxy, bz, waves, ctx->device);
   ctx->resident[key] = r;
   return r;
 }
@@ -302,6 +309,7 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   gve::BrickGeom bg;
   bg.Bxy = brick_xy(ctx);
   bg.Bz = brick_z(ctx);
+  bg.waves = waves_of(ctx);
   TRY(upload_items(ctx, vol, bg.Bxy, bg.Bz, &bg.nbricks));
   if (bg.nbricks >= ((int64_t)1 << 31))
     return fail(ctx, GVE_ERR_UNSUPPORTED, "too many bricks for 32-bit brick keys");
@@ -416,7 +424,7 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
     TRY_HIP(ctx, gve::radix_sort_pairs(ok, ov, bg.nbricks, 6, ws.sort_hist.ptr, &ow, s));
     out->sched.order = ov[ow];
     out->sched.counter = static_cast<uint32_t*>(ws.queue.ptr);
-    out->sched.persistent_groups = resident_groups(ctx, bg.Bxy, bg.Bz);
+    out->sched.persistent_groups = resident_groups(ctx, bg.Bxy, bg.Bz, bg.waves);
     if (out->sched.persistent_groups <= 0)
       return fail(ctx, GVE_ERR_DEVICE, "occupancy query for the persistent launch failed");
   }
@@ -441,6 +449,7 @@ gve_status bin_vol(gve_ctx* ctx, const gve_params* p, const Vol& vol, Binned* ou
   ctx->stats.bin_brick = bg.Bxy;
   ctx->stats.bin_brick_z = bg.Bz;
   ctx->stats.bin_schedule = sched_of(ctx);
+  ctx->stats.bin_waves = bg.waves;
   if (!async) ctx->stats.n_overlaps = (int64_t)T;
   return GVE_OK;
 }
@@ -604,6 +613,7 @@ gve_status gve_default_options(gve_options* opt) {
   opt->brick_z = 32;
   opt->schedule = GVE_SCHED_XCD;
   opt->deterministic = 0;
+  opt->brick_waves = 1;
   return GVE_OK;
 }
 
@@ -2166,14 +2176,16 @@ int bucket(double x, double per_octave) {
   return (int)std::lround(std::log2(std::max(x, 1e-6)) * per_octave);
 }
 
-// Times every brick shape and schedule on the workload (a warm-up pass, then
-// the median of `reps` passes) and returns the fastest as (brick, brick_z,
-// schedule).  Entries go to h_table while it has room.  The context's
+// Times every brick shape, waves per brick and schedule on the workload (a
+// warm-up pass, then the median of `reps` passes) and returns the fastest as
+// (brick, brick_z, schedule, waves).  Entries go to h_table while it has room.  The context's
 // options are restored on return; the passes' gradient sums are cleared.
 gve_status tune_candidates(gve_ctx* ctx, gve_params* P, const float* d_field, const Vol& vol,
                            int32_t reps, gve_tune_entry* h_table, int32_t table_len,
-                           int32_t* written, std::array<int, 3>* best) {
-  static const int shapes[][2] = {{8, 8}, {8, 16}, {8, 32}, {16, 16}};
+                           int32_t* written, std::array<int, 4>* best) {
+  // (brick, depth, waves per brick)
+  static const int shapes[][3] = {{8, 8, 1},  {8, 8, 2},  {8, 8, 4},  {8, 16, 1}, {8, 16, 2},
+                                  {8, 16, 4}, {8, 32, 1}, {8, 32, 2}, {8, 32, 4}, {16, 16, 1}};
   static const int scheds[] = {GVE_SCHED_INDEX, GVE_SCHED_XCD, GVE_SCHED_QUEUE};
   OptionsGuard guard(ctx);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -2196,6 +2208,7 @@ gve_status tune_candidates(gve_ctx* ctx, gve_params* P, const float* d_field, co
       ctx->opt = guard.saved;
       ctx->opt.brick = sh[0];
       ctx->opt.brick_z = sh[1];
+      ctx->opt.brick_waves = sh[2];
       ctx->opt.schedule = sc;
       TRY(tune_pass(ctx, P, d_field, vol));  // warm-up
       std::vector<float> ms;
@@ -2210,10 +2223,11 @@ gve_status tune_candidates(gve_ctx* ctx, gve_params* P, const float* d_field, co
       }
       std::sort(ms.begin(), ms.end());
       const float med = ms[ms.size() / 2];
-      if (*written < table_len) h_table[(*written)++] = gve_tune_entry{sh[0], sh[1], sc, med};
+      if (*written < table_len)
+        h_table[(*written)++] = gve_tune_entry{sh[0], sh[1], sc, med, sh[2]};
       if (med < best_ms) {
         best_ms = med;
-        *best = {sh[0], sh[1], sc};
+        *best = {sh[0], sh[1], sc, sh[2]};
       }
     }
   }
@@ -2223,10 +2237,15 @@ gve_status tune_candidates(gve_ctx* ctx, gve_params* P, const float* d_field, co
   return GVE_OK;
 }
 
-std::array<int64_t, 3> auto_key(const Vol& vol, const gve_params* p) {
-  int64_t M = 0;
-  for (int i = 0; i < vol.n; ++i) M += vol.grids[i].nx * vol.grids[i].ny * vol.grids[i].nz;
-  return {vol.n, M, p->n};
+// The workload an automatic choice belongs to: primitive count, then every
+// volume's dimensions and primitive range.
+std::vector<int64_t> auto_key(const Vol& vol, const gve_params* p) {
+  std::vector<int64_t> k = {p->n};
+  for (int i = 0; i < vol.n; ++i) {
+    const gve_grid& g = vol.grids[i];
+    k.insert(k.end(), {g.nx, g.ny, g.nz, vol.prim_off[i + 1] - vol.prim_off[i]});
+  }
+  return k;
 }
 
 // options.brick = 0: picks the brick shape and schedule for the workload
@@ -2238,7 +2257,7 @@ gve_status select_auto(gve_ctx* ctx, const gve_params* p, const float* d_field, 
   if (ctx->opt.brick != 0) return GVE_OK;
   const auto key = auto_key(vol, p);
   auto hit = ctx->auto_choice.find(key);
-  std::array<int, 3> c = {8, 32, GVE_SCHED_XCD};
+  std::array<int, 4> c = {8, 32, GVE_SCHED_XCD, 1};
   if (hit != ctx->auto_choice.end()) {
     c = hit->second;
   } else if (tune && d_field) {
@@ -2251,6 +2270,7 @@ gve_status select_auto(gve_ctx* ctx, const gve_params* p, const float* d_field, 
   ctx->auto_bxy = c[0];
   ctx->auto_bz = c[1];
   ctx->auto_sched = c[2];
+  ctx->auto_waves = c[3];
   return GVE_OK;
 }
 
@@ -2288,6 +2308,7 @@ gve_status gve_autotune(gve_ctx* ctx, const gve_params* p, const float* d_field,
   // cache key: box coverage per voxel measured at 8x8x8
   ctx->opt.brick = 8;
   ctx->opt.brick_z = 8;
+  ctx->opt.brick_waves = 1;
   ctx->opt.schedule = GVE_SCHED_INDEX;
   {
     Binned bn;
@@ -2297,7 +2318,7 @@ gve_status gve_autotune(gve_ctx* ctx, const gve_params* p, const float* d_field,
   const std::array<int, 4> key = {vol.n, bucket((double)M, 1.0), bucket((double)P->n, 1.0),
                                   bucket(cover, 2.0)};
   auto hit = ctx->tuned.find(key);
-  std::array<int, 3> c{};
+  std::array<int, 4> c{};
   int32_t written = 0;
   if (hit != ctx->tuned.end()) {
     c = hit->second;
@@ -2312,10 +2333,12 @@ gve_status gve_autotune(gve_ctx* ctx, const gve_params* p, const float* d_field,
     ctx->auto_bxy = c[0];
     ctx->auto_bz = c[1];
     ctx->auto_sched = c[2];
+    ctx->auto_waves = c[3];
   } else {
     best.brick = c[0];
     best.brick_z = c[1];
     best.schedule = c[2];
+    best.brick_waves = c[3];
     ctx->opt = best;
     guard.keep = true;
   }

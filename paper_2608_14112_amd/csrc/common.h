@@ -104,14 +104,15 @@ struct gve_ctx {
   bool timing = false;
   std::vector<hipEvent_t> events;  // stage-timer pool, 4 per refinement iteration
   std::vector<gve::ItemDesc> items_host;  // copy of ws.items (what the device holds)
-  std::map<std::pair<int, int>, int> resident;  // brick shape -> resident fused workgroups
-  std::map<std::array<int, 4>, std::array<int, 3>> tuned;  // autotuner cache
+  std::map<std::array<int, 3>, int> resident;  // (brick, depth, waves) -> resident fused workgroups
+  std::map<std::array<int, 4>, std::array<int, 4>> tuned;  // autotuner cache
   // Brick shape and schedule in use while options.brick is 0 (automatic):
   // the tuned choice for the current workload once known, else 8 x 8 x 32
-  // bricks in XCD chunks.  auto_choice: (volumes, voxels, primitives) ->
-  // (brick, brick_z, schedule).
-  int auto_bxy = 8, auto_bz = 32, auto_sched = GVE_SCHED_XCD;
-  std::map<std::array<int64_t, 3>, std::array<int, 3>> auto_choice;
+  // bricks in XCD chunks.  auto_choice: workload (primitive count, each
+  // volume's dimensions and primitive count) -> (brick, brick_z, schedule,
+  // waves per brick).
+  int auto_bxy = 8, auto_bz = 32, auto_sched = GVE_SCHED_XCD, auto_waves = 1;
+  std::map<std::vector<int64_t>, std::array<int, 4>> auto_choice;
   // While set, workspace buffers are carved from this fixed device region
   // (the allocation-free entry point) instead of being allocated.
   char* arena_base = nullptr;
@@ -159,6 +160,7 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int
 struct BrickGeom {
   int Bxy, Bz;           // brick edges in voxels
   int64_t nbricks;       // over every volume of the set
+  int waves = 1;         // fused kernel: waves per brick splitting its pairs
 };
 
 
@@ -227,8 +229,11 @@ hipError_t launch_order_keys(const uint32_t* brick_start, int64_t nbricks, uint3
 
 // Brick shapes (Bxy, Bz) the field kernels are compiled for.
 bool brick_shape_supported(int bxy, int bz);
+// Waves per brick the fused kernels are compiled for with that shape (1; 2
+// and 4 for 8 x 8 columns, which then split a brick's pairs).
+bool brick_waves_supported(int bxy, int bz, int waves);
 // Workgroups of the fused kernel that fit on the device at once.
-int fused_resident_groups(int bxy, int bz, int device);
+int fused_resident_groups(int bxy, int bz, int waves, int device);
 hipError_t launch_forward(const Record* rec, const uint32_t* pair_gid,
                           const uint32_t* brick_start, const ItemDesc* items, int nitems,
                           BrickGeom bg, float k, float* out, const Schedule& sc, hipStream_t s);

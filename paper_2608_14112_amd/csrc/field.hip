@@ -220,19 +220,22 @@ struct Touch {
   float sink;
 };
 
+// A wave visits pairs j0, j0 + stride, j0 + 2 stride, ... (< j1); its k-th
+// pair is j0 + stride k.
 __device__ inline void touch_begin(const uint32_t* __restrict__ pair_gid, uint32_t j0,
-                                   uint32_t j1, Touch& t) {
-  t.gid = pair_gid[min(j0 + (threadIdx.x & 63), j1 - 1)];
+                                   uint32_t stride, uint32_t j1, Touch& t) {
+  t.gid = pair_gid[min(j0 + stride * (threadIdx.x & 63), j1 - 1)];
   t.held = 0.0f;
   t.sink = 0.0f;
 }
 
+// At the wave's k-th pair (k a multiple of 64).
 __device__ inline void touch_block(const Record* __restrict__ rec,
-                                   const uint32_t* __restrict__ pair_gid, uint32_t j,
-                                   uint32_t j1, Touch& t) {
+                                   const uint32_t* __restrict__ pair_gid, uint32_t j0,
+                                   uint32_t stride, uint32_t k, uint32_t j1, Touch& t) {
   t.sink += t.held;
   t.held = reinterpret_cast<const float*>(rec + t.gid)[0];
-  t.gid = pair_gid[min(j + 64 + (threadIdx.x & 63), j1 - 1)];
+  t.gid = pair_gid[min(j0 + stride * (k + 64 + (threadIdx.x & 63)), j1 - 1)];
 }
 
 __device__ inline void touch_end(Touch& t) {
@@ -240,16 +243,21 @@ __device__ inline void touch_end(Touch& t) {
   asm volatile("" ::"v"(t.sink));
 }
 
+// Forward accumulation of the wave's pairs of one brick: jw, jw + stride, ...
+// (< j1; stride > 1 when several waves split a brick's pairs).  With
+// `steps`, the active offsets of pair j go to steps[j - jb] (jb = the
+// brick's first pair) for j - jb < kStepCap.
 template <int BZ>
 __device__ inline void accumulate_brick(const Record* __restrict__ rec,
-                                        const uint32_t* __restrict__ pair_gid, uint32_t j0,
-                                        uint32_t j1, float px, float py, float pz0, int iz0,
-                                        uint64_t cols, float thr, float (&acc)[BZ],
-                                        uint32_t* __restrict__ steps) {
+                                        const uint32_t* __restrict__ pair_gid, uint32_t jb,
+                                        uint32_t jw, uint32_t stride, uint32_t j1, float px,
+                                        float py, float pz0, int iz0, uint64_t cols, float thr,
+                                        float (&acc)[BZ], uint32_t* __restrict__ steps) {
   Touch tc;
-  if (j0 < j1) touch_begin(pair_gid, j0, j1, tc);
-  for (uint32_t j = j0; j < j1; ++j) {
-    if (((j - j0) & 63u) == 0u) touch_block(rec, pair_gid, j, j1, tc);
+  if (jw < j1) touch_begin(pair_gid, jw, stride, j1, tc);
+  uint32_t k = 0;
+  for (uint32_t j = jw; j < j1; j += stride, ++k) {
+    if ((k & 63u) == 0u) touch_block(rec, pair_gid, jw, stride, k, j1, tc);
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
     const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
@@ -258,9 +266,9 @@ __device__ inline void accumulate_brick(const Record* __restrict__ rec,
     if (column_hit<BZ>(s, szv, cols, thr)) {
       active = forward_steps<BZ>(s, szv, r.c, thr, acc);
     }
-    if (steps && j - j0 < kStepCap && (threadIdx.x & 63) == 0) steps[j - j0] = active;
+    if (steps && j - jb < kStepCap && (threadIdx.x & 63) == 0) steps[j - jb] = active;
   }
-  if (j0 < j1) touch_end(tc);
+  if (jw < j1) touch_end(tc);
 }
 
 // ---- where a brick lies --------------------------------------------------------
@@ -296,8 +304,11 @@ struct Site {
   }
 };
 
+// c = the thread's column in the brick (x fastest): threadIdx.x, or its lane
+// when several waves share the brick's columns.
 template <int BXY, int BZ>
-__device__ inline Site site_of(const ItemDesc* __restrict__ items, int nitems, uint32_t b) {
+__device__ inline Site site_of(const ItemDesc* __restrict__ items, int nitems, uint32_t b,
+                               uint32_t c = threadIdx.x) {
   const ItemDesc& it = items[item_of_brick(items, nitems, b)];
   const uint32_t lb = b - it.brick0;
   const uint32_t nbx = (uint32_t)it.nbx, nby = (uint32_t)it.nby;
@@ -305,8 +316,8 @@ __device__ inline Site site_of(const ItemDesc* __restrict__ items, int nitems, u
   s.bx = (int)(lb % nbx);
   s.by = (int)((lb / nbx) % nby);
   s.bz = (int)(lb / (nbx * nby));
-  const int ix = s.bx * BXY + (int)(threadIdx.x % BXY);
-  const int iy = s.by * BXY + (int)(threadIdx.x / BXY);
+  const int ix = s.bx * BXY + (int)(c % BXY);
+  const int iy = s.by * BXY + (int)(c / BXY);
   s.iz0 = s.bz * BZ;
   s.zrem = (int)it.nz - s.iz0;
   s.px = (float)(it.x0 + ix);
@@ -316,7 +327,7 @@ __device__ inline Site site_of(const ItemDesc* __restrict__ items, int nitems, u
   s.plane = (size_t)it.nx * (size_t)it.ny;
   s.org = (size_t)it.vox + (size_t)(s.bx * BXY) + (size_t)it.nx * (size_t)(s.by * BXY) +
           s.plane * (size_t)s.iz0;
-  s.lbytes = 4u * ((threadIdx.x % BXY) + (uint32_t)it.nx * (threadIdx.x / BXY));
+  s.lbytes = 4u * ((c % BXY) + (uint32_t)it.nx * (c / BXY));
   return s;
 }
 
@@ -348,8 +359,9 @@ __device__ __attribute__((always_inline)) inline void forward_brick(const Record
   float acc[BZ];
 #pragma unroll
   for (int zz = 0; zz < BZ; ++zz) acc[zz] = 0.0f;
-  accumulate_brick<BZ>(rec, pair_gid, brick_start[b], brick_start[b + 1], st.px, st.py, st.pz0,
-                       st.iz0, __builtin_amdgcn_ballot_w64(st.col_in), thr, acc, nullptr);
+  accumulate_brick<BZ>(rec, pair_gid, brick_start[b], brick_start[b], 1u, brick_start[b + 1],
+                       st.px, st.py, st.pz0, st.iz0, __builtin_amdgcn_ballot_w64(st.col_in), thr,
+                       acc, nullptr);
   if (st.col_in) {
 #pragma unroll
     for (int zz = 0; zz < BZ; ++zz)
@@ -472,7 +484,11 @@ __device__ inline void load_column_chunk(const float* __restrict__ field, const 
 // VJP = true: no forward pass; r is read from `field` (an upstream gradient
 // dl/dVhat), so the ten sums give the vector-Jacobian product
 // sum_p r(p) dVhat(p)/dtheta.
-template <int BXY, int BZ, bool VJP>
+// W > 1 (8 x 8 columns only): W waves share the brick's columns and split its
+// pairs (wave w takes pairs w, w + W, ...); the forward partial sums are added
+// in wave order through LDS (`comb`, W * BZ * 64 floats), after which every
+// wave holds the whole field of the brick.
+template <int BXY, int BZ, bool VJP, int W>
 __device__ __attribute__((always_inline)) inline void fused_brick(const Record* __restrict__ rec,
                                    const uint32_t* __restrict__ pair_gid,
                                    const uint32_t* __restrict__ brick_start,
@@ -481,17 +497,20 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
                                    float* __restrict__ gacc, int64_t n, float* __restrict__ part,
                                    const uint32_t* __restrict__ pslot,
                                    float* __restrict__ brick_loss,
-                                   float (*red)[10], uint32_t* __restrict__ steps) {
-  constexpr int kWaves = (BXY * BXY + 63) / 64;
-  const Site st = site_of<BXY, BZ>(items, nitems, b);
+                                   float (*red)[10], uint32_t* __restrict__ steps,
+                                   float* __restrict__ comb) {
+  constexpr int kWaves = (BXY * BXY + 63) / 64;  // waves over the columns
+  static_assert(W == 1 || kWaves == 1, "pairs are split only over one wave of columns");
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  const Site st = site_of<BXY, BZ>(items, nitems, b, W > 1 ? (uint32_t)lane : threadIdx.x);
   const int row = lane >> 4;
   const float px = st.px, py = st.py, pz0 = st.pz0;
   const int iz0 = st.iz0;
   const bool col_in = st.col_in;
   const uint64_t cols = __builtin_amdgcn_ballot_w64(col_in);
   const uint32_t j0 = brick_start[b], j1 = brick_start[b + 1];
+  const uint32_t jw = j0 + (W > 1 ? (uint32_t)wave : 0u);  // this wave's first pair
   // target reads: lanes outside the volume read past the record count (0);
   // an inside lane's offset is below one plane and below 2^29 bytes
   static_assert(BZ % kLoadZ == 0, "brick depth must be a multiple of the load chunk");
@@ -511,8 +530,28 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
       asm volatile("" ::: "memory");
     }
   } else {
-    accumulate_brick<BZ>(rec, pair_gid, j0, j1, px, py, pz0, iz0, cols, thr, res,
-                         kWaves == 1 ? steps : nullptr);
+    accumulate_brick<BZ>(rec, pair_gid, j0, jw, (uint32_t)W, j1, px, py, pz0, iz0, cols, thr,
+                         res, kWaves == 1 ? steps : nullptr);
+    if (W > 1) {
+      // the waves' partial sums, added in wave order
+#pragma unroll
+      for (int zz = 0; zz < BZ; ++zz) comb[(wave * BZ + zz) * 64 + lane] = res[zz];
+      __syncthreads();
+#pragma unroll
+      for (int z0 = 0; z0 < BZ; z0 += 8) {
+#pragma unroll
+        for (int zz = z0; zz < z0 + 8; ++zz) {
+          float t = 0.0f;
+#pragma unroll
+          for (int w = 0; w < W; ++w) t += comb[(w * BZ + zz) * 64 + lane];
+          res[zz] = t;
+        }
+        // eight offsets at a time: the next reads wait for these sums, so
+        // the loads in flight stay within 8 W registers
+#pragma unroll
+        for (int zz = z0; zz < z0 + 8; ++zz) asm volatile("" ::"v"(res[zz]) : "memory");
+      }
+    }
     // residual and this brick's share of the loss
     float lsum = 0.0f;
 #pragma unroll
@@ -538,20 +577,24 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
       asm volatile("" : "+v"(lsum)::"memory");
     }
     lsum = wave_sum(lsum);
-    if (lane == 0) red[wave][0] = lsum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float t = 0.0f;
-      for (int w = 0; w < kWaves; ++w) t += red[w][0];
-      brick_loss[b] = t;
+    if (W > 1) {
+      if (threadIdx.x == 0) brick_loss[b] = lsum;  // every wave holds the same residual
+    } else {
+      if (lane == 0) red[wave][0] = lsum;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < kWaves; ++w) t += red[w][0];
+        brick_loss[b] = t;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // support test and reach of the recurrence form of the backward steps
   const float T = __builtin_amdgcn_exp2f(thr);
   const float reach = 100.0f + thr > 0.0f ? sqrtf(100.0f + thr) - sqrtf(-thr) : 0.0f;
-  for (uint32_t j = j0; j < j1; ++j) {
+  for (uint32_t j = jw; j < j1; j += W) {
     const uint32_t gid = __builtin_amdgcn_readfirstlane(pair_gid[j]);
     const Record r = load_record(rec, gid);
     const ColumnSetup s = column_setup<BZ>(r, px, py, pz0, iz0);
@@ -632,9 +675,10 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
   }
 }
 
-// One workgroup per brick (xcd: consecutive bricks grouped per XCD).
-template <int BXY, int BZ, bool VJP>
-__global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ rec,
+// One workgroup per brick (xcd: consecutive bricks grouped per XCD); W waves
+// per brick split its pairs (fused_brick).
+template <int BXY, int BZ, bool VJP, int W>
+__global__ __launch_bounds__(BXY* BXY* W) void k_fused(const Record* __restrict__ rec,
                                                 const uint32_t* __restrict__ pair_gid,
                                                 const uint32_t* __restrict__ brick_start,
                                                 const ItemDesc* __restrict__ items, int nitems,
@@ -647,16 +691,17 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused(const Record* __restrict__ r
   constexpr int kWaves = (BXY * BXY + 63) / 64;
   __shared__ float red[kWaves][10];
   __shared__ uint32_t steps[kWaves == 1 && !VJP ? kStepCap : 1];
+  __shared__ float comb[W > 1 && !VJP ? W * BZ * 64 : 1];
   const uint32_t b = xcd ? xcd_brick(blockIdx.x, nbricks) : blockIdx.x;
-  fused_brick<BXY, BZ, VJP>(rec, pair_gid, brick_start, items, nitems, b, thr, field, gacc, n,
-                            part, pslot, brick_loss, red, steps);
+  fused_brick<BXY, BZ, VJP, W>(rec, pair_gid, brick_start, items, nitems, b, thr, field, gacc, n,
+                               part, pslot, brick_loss, red, steps, comb);
 }
 
 // Persistent: each workgroup takes queue positions from *counter until they
 // run out (every workgroup reaches that exit) and processes brick
 // order[position] (heaviest first).
-template <int BXY, int BZ, bool VJP>
-__global__ __launch_bounds__(BXY* BXY) void k_fused_queue(const Record* __restrict__ rec,
+template <int BXY, int BZ, bool VJP, int W>
+__global__ __launch_bounds__(BXY* BXY* W) void k_fused_queue(const Record* __restrict__ rec,
                                                       const uint32_t* __restrict__ pair_gid,
                                                       const uint32_t* __restrict__ brick_start,
                                                       const ItemDesc* __restrict__ items,
@@ -671,6 +716,7 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused_queue(const Record* __restri
   constexpr int kWaves = (BXY * BXY + 63) / 64;
   __shared__ float red[kWaves][10];
   __shared__ uint32_t steps[kWaves == 1 && !VJP ? kStepCap : 1];
+  __shared__ float comb[W > 1 && !VJP ? W * BZ * 64 : 1];
   __shared__ uint32_t next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
@@ -678,8 +724,8 @@ __global__ __launch_bounds__(BXY* BXY) void k_fused_queue(const Record* __restri
     const uint32_t w = __builtin_amdgcn_readfirstlane(next);
     __syncthreads();
     if (w >= nbricks) break;
-    fused_brick<BXY, BZ, VJP>(rec, pair_gid, brick_start, items, nitems, order[w], thr, field,
-                              gacc, n, part, pslot, brick_loss, red, steps);
+    fused_brick<BXY, BZ, VJP, W>(rec, pair_gid, brick_start, items, nitems, order[w], thr,
+                                 field, gacc, n, part, pslot, brick_loss, red, steps, comb);
   }
 }
 
@@ -794,6 +840,10 @@ __global__ __launch_bounds__(kRedThreads) void k_item_loss(const float* __restri
 }  // namespace
 
 #define GVE_BRICK_SHAPES(X) X(8, 8) X(8, 16) X(8, 32) X(16, 16)
+// (brick edge, depth, waves per brick) of the fused kernels
+#define GVE_FUSED_SHAPES(X)                                                                   \
+  X(8, 8, 1) X(8, 8, 2) X(8, 8, 4) X(8, 16, 1) X(8, 16, 2) X(8, 16, 4) X(8, 32, 1) X(8, 32, 2) \
+  X(8, 32, 4) X(16, 16, 1)
 
 bool brick_shape_supported(int bxy, int bz) {
 #define GVE_CASE(XY, Z) if (bxy == XY && bz == Z) return true;
@@ -802,18 +852,25 @@ bool brick_shape_supported(int bxy, int bz) {
   return false;
 }
 
-int fused_resident_groups(int bxy, int bz, int device) {
+bool brick_waves_supported(int bxy, int bz, int waves) {
+#define GVE_CASE(XY, Z, W) if (bxy == XY && bz == Z && waves == W) return true;
+  GVE_FUSED_SHAPES(GVE_CASE)
+#undef GVE_CASE
+  return false;
+}
+
+int fused_resident_groups(int bxy, int bz, int waves, int device) {
   int per_cu = 0, cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     return 0;
-#define GVE_CASE(XY, Z)                                                                       \
-  if (bxy == XY && bz == Z) {                                                                 \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused_queue<XY, Z, false>,    \
-                                                     XY * XY, 0) != hipSuccess)               \
+#define GVE_CASE(XY, Z, W)                                                                    \
+  if (bxy == XY && bz == Z && waves == W) {                                                   \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused_queue<XY, Z, false, W>, \
+                                                     XY * XY * W, 0) != hipSuccess)           \
       return 0;                                                                               \
     return per_cu * cus;                                                                      \
   }
-  GVE_BRICK_SHAPES(GVE_CASE)
+  GVE_FUSED_SHAPES(GVE_CASE)
 #undef GVE_CASE
   return 0;
 }
@@ -851,27 +908,27 @@ hipError_t launch_fused(const Record* rec, const uint32_t* pair_gid, const uint3
   const uint32_t* order = sc.order;
   uint32_t* counter = sc.counter;
   const uint32_t nb = (uint32_t)bg.nbricks;
-#define GVE_CASE(XY, Z)                                                                       \
-  if (bg.Bxy == XY && bg.Bz == Z) {                                                           \
+#define GVE_CASE(XY, Z, W)                                                                    \
+  if (bg.Bxy == XY && bg.Bz == Z && bg.waves == W) {                                          \
     if (queue && vjp)                                                                         \
-      hipLaunchKernelGGL((k_fused_queue<XY, Z, true>), grid, dim3(XY * XY), 0, s, rec,          \
+      hipLaunchKernelGGL((k_fused_queue<XY, Z, true, W>), grid, dim3(XY * XY * W), 0, s, rec,   \
                          pair_gid, brick_start, items, nitems, nb, order, counter, thr, field,  \
                          acc, n, part, pslot, brick_loss);                                     \
     else if (queue)                                                                           \
-      hipLaunchKernelGGL((k_fused_queue<XY, Z, false>), grid, dim3(XY * XY), 0, s, rec,         \
+      hipLaunchKernelGGL((k_fused_queue<XY, Z, false, W>), grid, dim3(XY * XY * W), 0, s, rec,  \
                          pair_gid, brick_start, items, nitems, nb, order, counter, thr, field,  \
                          acc, n, part, pslot, brick_loss);                                     \
     else if (vjp)                                                                             \
-      hipLaunchKernelGGL((k_fused<XY, Z, true>), grid, dim3(XY * XY), 0, s, rec, pair_gid,      \
-                         brick_start, items, nitems, nb, xcd, thr, field, acc, n, part, pslot,  \
-                         brick_loss);                                                           \
+      hipLaunchKernelGGL((k_fused<XY, Z, true, W>), grid, dim3(XY * XY * W), 0, s, rec,         \
+                         pair_gid, brick_start, items, nitems, nb, xcd, thr, field, acc, n,     \
+                         part, pslot, brick_loss);                                              \
     else                                                                                      \
-      hipLaunchKernelGGL((k_fused<XY, Z, false>), grid, dim3(XY * XY), 0, s, rec, pair_gid,     \
-                         brick_start, items, nitems, nb, xcd, thr, field, acc, n, part, pslot,  \
-                         brick_loss);                                                           \
+      hipLaunchKernelGGL((k_fused<XY, Z, false, W>), grid, dim3(XY * XY * W), 0, s, rec,        \
+                         pair_gid, brick_start, items, nitems, nb, xcd, thr, field, acc, n,     \
+                         part, pslot, brick_loss);                                              \
     return hipGetLastError();                                                                 \
   }
-  GVE_BRICK_SHAPES(GVE_CASE)
+  GVE_FUSED_SHAPES(GVE_CASE)
 #undef GVE_CASE
   return hipErrorInvalidValue;
 }

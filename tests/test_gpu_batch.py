@@ -156,12 +156,14 @@ def test_autotune_picks_a_candidate_and_caches():
     ctx, B, thetas, fields, cat = _setup(g, torch)
     before = B.params.download()
     table = g.autotune(ctx, cat, batch=B, reps=2)
-    assert len(table) == 12
-    assert {(t[0], t[1]) for t in table} == {(8, 8), (8, 16), (8, 32), (16, 16)}
+    assert len(table) == 30
+    assert {(t[0], t[1], t[4]) for t in table} == {
+        (8, 8, 1), (8, 8, 2), (8, 8, 4), (8, 16, 1), (8, 16, 2), (8, 16, 4), (8, 32, 1),
+        (8, 32, 2), (8, 32, 4), (16, 16, 1)}
     assert all(t[3] > 0 for t in table)
     best = min(table, key=lambda t: t[3])
     o = ctx.options
-    assert (o.brick, o.brick_z, o.schedule) == best[:3]
+    assert (o.brick, o.brick_z, o.schedule, o.brick_waves) == best[:3] + best[4:]
     assert np.array_equal(B.params.download(), before) and B.params.step == 0
     assert g.autotune(ctx, cat, batch=B, reps=2) == []          # cached
     # the tuned configuration computes the same thing
@@ -173,7 +175,7 @@ def test_autotune_picks_a_candidate_and_caches():
     p = g.Params(ctx, VOLUMES[2][1]).upload(thetas[2].astype(np.float32))
     t1 = g.autotune(ctx, torch.from_numpy(fields[2]).cuda(), params=p,
                     grid=_ggrid(g, VOLUMES[2][0]), reps=1)
-    assert len(t1) == 12
+    assert len(t1) == 30
 
 
 def test_automatic_brick_shape():
