@@ -99,3 +99,26 @@ def test_gradient_of_sampled_primitives(workload):
               + ", ".join(f"{k} {v:.1e}" for k, v in rel.items())
               + f"; max entry err/|g| {np.max(ea / np.maximum(np.abs(gr[:, j]), 1e-30)):.1e}, "
               f"max entry err/A_g {np.max(ea / np.maximum(absg[:, 0], 1e-30)):.1e}", flush=True)
+
+
+def test_refinement_with_asynchronous_binning_at_full_size(workload):
+    """Deterministic sums at the benchmark's size: one refinement call of four
+    iterations (binning sized on the device after the first) ends bitwise where
+    four one-iteration calls (each binning sized on the host) end, losses
+    included."""
+    g, torch, _, field, grid, P, theta = workload
+    print("[fullsize] refinement, asynchronous vs synchronous binning", flush=True)
+    ctx = g.Context(k=3.0, deterministic=True)
+    a = g.Params(ctx, BUDGET).upload(theta.astype(np.float32))
+    la = g.refine(ctx, a, field, grid, 4)
+    assert ctx.stats()["n_resized"] == 0
+    ta = a.download()
+    a.close()
+    b = g.Params(ctx, BUDGET).upload(theta.astype(np.float32))
+    lb = np.concatenate([g.refine(ctx, b, field, grid, 1) for _ in range(4)])
+    tb = b.download()
+    b.close()
+    print(f"[fullsize] losses {la.tolist()}", flush=True)
+    assert np.array_equal(la, lb)
+    assert np.array_equal(ta, tb)
+    assert la[-1] < la[0]
