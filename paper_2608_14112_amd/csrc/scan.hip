@@ -83,6 +83,36 @@ __global__ __launch_bounds__(kThreads) void k_tile_scan(const uint32_t* __restri
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off + total;
 }
 
+// One workgroup scans up to kSmallTiles tiles in order, carrying the running
+// total: one launch instead of three for the short scans of small workloads.
+constexpr int kSmallTiles = 8;
+
+__global__ __launch_bounds__(kThreads) void k_small_scan(const uint32_t* __restrict__ in,
+                                                         int64_t n, uint32_t* __restrict__ out) {
+  uint32_t carry = 0;
+  for (int64_t base0 = 0; base0 < n; base0 += kTile) {
+    const int64_t base = base0 + (int64_t)threadIdx.x * kPerThread;
+    uint32_t x[kPerThread];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) {
+      const int64_t i = base + j;
+      x[j] = (i < n) ? in[i] : 0u;
+      s += x[j];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, &total) + carry;
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) {
+      const int64_t i = base + j;
+      if (i < n) out[i] = run;
+      run += x[j];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
 __global__ void k_store_zero(uint32_t* p) { *p = 0u; }
 
 int64_t ntiles(int64_t n) { return (n + kTile - 1) / kTile; }
@@ -107,6 +137,10 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void
   }
   if (n <= kTile) {
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kThreads), 0, s, in, n, nullptr, out);
+    return hipGetLastError();
+  }
+  if (n <= (int64_t)kSmallTiles * kTile) {
+    hipLaunchKernelGGL(k_small_scan, dim3(1), dim3(kThreads), 0, s, in, n, out);
     return hipGetLastError();
   }
   const int64_t t = ntiles(n);
