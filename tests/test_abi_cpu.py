@@ -65,7 +65,7 @@ def test_null_arguments_are_rejected():
     ("k", -1.0, 1), ("k", float("nan"), 1), ("k", 0.0, 1), ("brick", 4, 6), ("brick", 7, 6),
     ("brick_z", 4, 6), ("brick_z", 24, 6),
     ("lr", -1.0, 1), ("beta1", 1.0, 1), ("beta2", -0.1, 1), ("eps", 0.0, 1),
-    ("ell_min", 3.0, 1), ("deterministic", 2, 1),
+    ("ell_min", 3.0, 1), ("deterministic", 2, 1), ("brick_waves", 3, 6),
 ])
 def test_bad_options_fail_before_any_device_call(field, value, status):
     import paper_2608_14112_amd as g
@@ -93,3 +93,38 @@ def test_export_and_checkpoint_sizes():
         assert lib.gve_checkpoint_size(n) == 32 + 3 * 44 * n
     assert lib.gve_export_size(0) == g.EXPORT_HEADER
     assert lib.gve_export_size(-5) == g.EXPORT_HEADER
+
+
+STRUCTS = [("gve_grid", "GridC"), ("gve_options", "OptionsC"), ("gve_stats", "StatsC"),
+           ("gve_alloc_info", "AllocInfoC"), ("gve_probe_rates", "ProbeC"),
+           ("gve_tune_entry", "TuneEntryC"), ("gve_paper_options", "PaperOptionsC")]
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Size and field offsets of every ABI struct, as the C compiler lays them
+    out from include/gve.h, equal the binding's ctypes mirrors."""
+    import shutil
+    import subprocess
+
+    import paper_2608_14112_amd as g
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gve.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in getattr(g, pyname)._fields_:
+            lines.append(f'  printf("{cname}.{field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in
+               subprocess.run([str(exe)], check=True, capture_output=True, text=True)
+               .stdout.splitlines())
+    for cname, pyname in STRUCTS:
+        cls = getattr(g, pyname)
+        assert int(out[f"{cname} size"]) == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert int(out[f"{cname}.{field}"]) == getattr(cls, field).offset, (cname, field)
