@@ -106,9 +106,11 @@ __device__ inline uint32_t prep_one(const float* __restrict__ theta, int64_t n, 
   }
   uint32_t cnt = 0;
   if (!empty) {
-    cnt = (uint32_t)(hi[0] / bg.Bxy - lo[0] / bg.Bxy + 1) *
-          (uint32_t)(hi[1] / bg.Bxy - lo[1] / bg.Bxy + 1) *
-          (uint32_t)(hi[2] / bg.Bz - lo[2] / bg.Bz + 1);
+    // brick edges are powers of two; lo, hi >= 0
+    const int sxy = __builtin_ctz(bg.Bxy), sz = __builtin_ctz(bg.Bz);
+    cnt = (uint32_t)((hi[0] >> sxy) - (lo[0] >> sxy) + 1) *
+          (uint32_t)((hi[1] >> sxy) - (lo[1] >> sxy) + 1) *
+          (uint32_t)((hi[2] >> sz) - (lo[2] >> sz) + 1);
   } else {
 #pragma unroll
     for (int j = 0; j < 3; ++j) { lo[j] = 1; hi[j] = 0; }
@@ -171,15 +173,18 @@ __global__ __launch_bounds__(kThreads) void k_prep(const float* __restrict__ the
 //     (-(s0 dx + s1 dy / 2) - sz^2 t gx, -(s1 dx / 2 + s2 dy) - sz^2 t gy, sz^2 t)
 // and (log2 e / 2) d^T P d = sz^2 t^2 - qxy.  The test is conservative: a brick
 // it keeps may still miss (the brick kernels test every column anyway).
-__device__ inline bool brick_meets_support(const Record& r, const ItemDesc& it, BrickGeom bg,
-                                           uint32_t bx, uint32_t by, uint32_t bz, float k) {
+// (ox, oy, oz): the volume's origin minus the primitive's centre (float).
+__device__ inline bool brick_meets_support(const Record& r, float ox, float oy, float oz,
+                                           BrickGeom bg, uint32_t bx, uint32_t by, uint32_t bz,
+                                           float k) {
   const int bxy = bg.Bxy, bzz = bg.Bz;
-  const int xa = max((int)bx * bxy, r.lo[0]), xb = min((int)bx * bxy + bxy - 1, r.hi[0]);
-  const int ya = max((int)by * bxy, r.lo[1]), yb = min((int)by * bxy + bxy - 1, r.hi[1]);
-  const int za = max((int)bz * bzz, r.lo[2]), zb = min((int)bz * bzz + bzz - 1, r.hi[2]);
-  const float dx = 0.5f * (float)(xa + xb) + (float)it.x0 - r.mu[0];
-  const float dy = 0.5f * (float)(ya + yb) + (float)it.y0 - r.mu[1];
-  const float dz = 0.5f * (float)(za + zb) + (float)it.z0 - r.mu[2];
+  const int sxy = __builtin_ctz(bxy), sz = __builtin_ctz(bzz);  // edges are powers of two
+  const int xa = max((int)(bx << sxy), r.lo[0]), xb = min((int)(bx << sxy) + bxy - 1, r.hi[0]);
+  const int ya = max((int)(by << sxy), r.lo[1]), yb = min((int)(by << sxy) + bxy - 1, r.hi[1]);
+  const int za = max((int)(bz << sz), r.lo[2]), zb = min((int)(bz << sz) + bzz - 1, r.hi[2]);
+  const float dx = 0.5f * (float)(xa + xb) + ox;
+  const float dy = 0.5f * (float)(ya + yb) + oy;
+  const float dz = 0.5f * (float)(za + zb) + oz;
   const float hx = 0.5f * (float)(xb - xa), hy = 0.5f * (float)(yb - ya),
               hz = 0.5f * (float)(zb - za);
   const float t = dz - (r.gx * dx + r.gy * dy);
@@ -190,7 +195,8 @@ __device__ inline bool brick_meets_support(const Record& r, const ItemDesc& it, 
   const float nz = sz2 * t;
   const float mm = sz2 * t * t - qxy;
   const float side = fabsf(nx) * hx + fabsf(ny) * hy + fabsf(nz) * hz;
-  const float reach = (1.0f + 1e-3f) * k * sqrtf(kHalfLog2e) * sqrtf(mm);
+  // the hardware square root (within 1 ulp) is ample against the 1e-3 margin
+  const float reach = (1.0f + 1e-3f) * k * sqrtf(kHalfLog2e) * __builtin_amdgcn_sqrtf(mm);
   // NaN anywhere keeps the brick
   return !(mm - side > reach + 1e-5f * (mm + side));
 }
@@ -224,18 +230,16 @@ struct BoxBricks {
 
 __device__ inline BoxBricks box_bricks(const Record& r, BrickGeom bg) {
   BoxBricks b;
-  b.bx0 = (uint32_t)r.lo[0] / bg.Bxy;
-  b.by0 = (uint32_t)r.lo[1] / bg.Bxy;
-  b.bz0 = (uint32_t)r.lo[2] / bg.Bz;
-  b.nbx = (uint32_t)r.hi[0] / bg.Bxy - b.bx0 + 1;
-  b.nby = (uint32_t)r.hi[1] / bg.Bxy - b.by0 + 1;
+  // brick edges are powers of two; box corners are >= 0
+  const uint32_t sxy = (uint32_t)__builtin_ctz(bg.Bxy), sz = (uint32_t)__builtin_ctz(bg.Bz);
+  b.bx0 = (uint32_t)r.lo[0] >> sxy;
+  b.by0 = (uint32_t)r.lo[1] >> sxy;
+  b.bz0 = (uint32_t)r.lo[2] >> sz;
+  b.nbx = ((uint32_t)r.hi[0] >> sxy) - b.bx0 + 1;
+  b.nby = ((uint32_t)r.hi[1] >> sxy) - b.by0 + 1;
   b.inv_nbx = 1.0f / (float)b.nbx;
   b.inv_nby = 1.0f / (float)b.nby;
   return b;
-}
-
-__device__ inline uint32_t brick_key(const ItemDesc& it, uint32_t bx, uint32_t by, uint32_t bz) {
-  return it.brick0 + (uint32_t)it.nbx * (by + (uint32_t)it.nby * bz) + bx;
 }
 
 // Sixteen lanes per primitive (four primitives per wave, so that launching
@@ -276,10 +280,19 @@ __global__ __launch_bounds__(kThreads) void k_cull(const Record* __restrict__ re
   }
   if (live && !room && sub == 0) count[i] = 0;
   BoxBricks bb{};
-  const ItemDesc* it = items;
+  // the volume's descriptor, read once: origin relative to the centre, and
+  // what the brick keys need
+  float ox = 0.f, oy = 0.f, oz = 0.f;
+  uint32_t kb0 = 0, knbx = 0, knby = 0;
   if (total > 0) {
     bb = box_bricks(r, bg);
-    it = &items[item_of_prim(items, nitems, (uint32_t)i)];
+    const ItemDesc& it = items[item_of_prim(items, nitems, (uint32_t)i)];
+    ox = (float)it.x0 - r.mu[0];
+    oy = (float)it.y0 - r.mu[1];
+    oz = (float)it.z0 - r.mu[2];
+    kb0 = it.brick0;
+    knbx = (uint32_t)it.nbx;
+    knby = (uint32_t)it.nby;
   }
   const uint64_t below = ((1ull << lane) - 1ull) & ~((1ull << shift) - 1ull);
   uint32_t nkept = 0;
@@ -291,10 +304,11 @@ __global__ __launch_bounds__(kThreads) void k_cull(const Record* __restrict__ re
     uint32_t bx = 0, by = 0, bz = 0;
     if (j < total) {
       bb.at(j, bx, by, bz);
-      keep = brick_meets_support(r, *it, bg, bx, by, bz, k);
+      keep = brick_meets_support(r, ox, oy, oz, bg, bx, by, bz, k);
     }
     const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
-    if (keep) kept[o + nkept + (uint32_t)__popcll(m & below)] = brick_key(*it, bx, by, bz);
+    // brick key: the global brick id (x fastest within the volume)
+    if (keep) kept[o + nkept + (uint32_t)__popcll(m & below)] = kb0 + knbx * (by + knby * bz) + bx;
     nkept += (uint32_t)__popcll((m >> shift) & ((1ull << kGroup) - 1ull));
   }
   if (live && total > 0 && sub == 0) count[i] = nkept;
