@@ -4,8 +4,13 @@
 // primitives form one contiguous run, in increasing primitive index (the
 // pairs are emitted in primitive order and every pass is stable).  Each pass
 // handles `w` <= 8 key bits:
-//   1. per-tile digit histogram, stored digit-major: hist[d * ntiles + tile];
-//   2. exclusive scan of the flattened histogram -> global write offsets;
+//   1. per-tile digit histogram, stored tile-major: hist[tile * 256 + d] (one
+//      coalesced row per tile);
+//   2. global write offsets offs[tile * 256 + d] = (items of all smaller
+//      digits) + (items of digit d in earlier tiles): column sums over
+//      chunks of tiles, one workgroup scanning the chunk sums and the digit
+//      totals, then the chunks' running column sums (every access a
+//      coalesced row);
 //   3. stable scatter: a tile is ordered by digit in LDS, consumed in rounds
 //      of 256 items in index order (an item's rank among equal digits in its
 //      wave comes from up to eight ballots, across waves from per-wave counts
@@ -38,7 +43,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ 
   n = items_of(n, dn);
   const int64_t base = (int64_t)blockIdx.x * kTile;
   if (base >= n) {  // a tile past the items (the launch covers the capacity)
-    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = 0u;
+    hist[(int64_t)blockIdx.x * kRadix + threadIdx.x] = 0u;
     return;
   }
   // the tile's keys, all loads issued before the first count
@@ -56,7 +61,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint32_t* __restrict__ 
     if (i < n) atomicAdd(&cnt[(tk[r] >> shift) & mask], 1u);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+  hist[(int64_t)blockIdx.x * kRadix + threadIdx.x] = cnt[threadIdx.x];
 }
 
 // Exclusive prefix sum of one value per thread over the block.
@@ -74,6 +79,92 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* __restrict
   uint32_t before = 0;
   for (int w = 0; w < wave; ++w) before += wsum[w];
   return before + incl - v;
+}
+
+// Column sums of the tile-major histogram over chunks of `crows` tiles:
+// csum[chunk * 256 + d] (thread d; every step reads one 1 KB row).
+__global__ __launch_bounds__(kThreads) void k_col_reduce(const uint32_t* __restrict__ hist,
+                                                         int64_t ntiles, int64_t crows,
+                                                         uint32_t* __restrict__ csum) {
+  const int64_t r0 = (int64_t)blockIdx.x * crows;
+  const int64_t r1 = min(r0 + crows, ntiles);
+  uint32_t s = 0;
+#pragma unroll 16
+  for (int64_t r = r0; r < r1; ++r) s += hist[r * kRadix + threadIdx.x];
+  csum[(int64_t)blockIdx.x * kRadix + threadIdx.x] = s;
+}
+
+// One workgroup of 1024 threads: per digit, the exclusive scan of the chunk
+// sums over the `nchunks` (<= 256) chunks, plus the items of all smaller
+// digits; the result (the write offset of each chunk's first tile)
+// overwrites csum.  Thread (q, d) takes digit d over a quarter of the chunks.
+constexpr int kScanParts = 4;
+constexpr int kScanThreads = kScanParts * kRadix;
+__global__ __launch_bounds__(kScanThreads) void k_col_scan(uint32_t* __restrict__ csum,
+                                                           int64_t nchunks) {
+  __shared__ uint32_t part[kScanParts][kRadix];
+  __shared__ uint32_t wsum[kWaves];
+  __shared__ uint32_t dbase[kRadix];
+  const int d = threadIdx.x & (kRadix - 1);
+  const int q = threadIdx.x / kRadix;
+  const int64_t per = (nchunks + kScanParts - 1) / kScanParts;
+  const int64_t c0 = min(q * per, nchunks);
+  const int64_t c1 = min(c0 + per, nchunks);
+  uint32_t sum = 0;
+#pragma unroll 16
+  for (int64_t c = c0; c < c1; ++c) sum += csum[c * kRadix + d];
+  part[q][d] = sum;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+#pragma unroll
+  for (int r = 0; r < kScanParts; ++r) {
+    const uint32_t v = part[r][d];
+    before += r < q ? v : 0u;
+    total += v;
+  }
+  // digit bases: exclusive scan of the totals over the digits (the first
+  // four waves, one digit per thread)
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  uint32_t incl = total;
+  if (q == 0) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+  }
+  __syncthreads();
+  if (q == 0) {
+    uint32_t w = 0;
+    for (int v = 0; v < wave; ++v) w += wsum[v];
+    dbase[d] = w + incl - total;
+  }
+  __syncthreads();
+  uint32_t run = dbase[d] + before;
+#pragma unroll 16
+  for (int64_t c = c0; c < c1; ++c) {
+    const uint32_t v = csum[c * kRadix + d];
+    csum[c * kRadix + d] = run;
+    run += v;
+  }
+}
+
+// The chunk's running column sums: offs[t * 256 + d] for its tiles.
+__global__ __launch_bounds__(kThreads) void k_col_apply(const uint32_t* __restrict__ hist,
+                                                        int64_t ntiles, int64_t crows,
+                                                        const uint32_t* __restrict__ cbase,
+                                                        uint32_t* __restrict__ offs) {
+  const int64_t r0 = (int64_t)blockIdx.x * crows;
+  const int64_t r1 = min(r0 + crows, ntiles);
+  uint32_t run = cbase[(int64_t)blockIdx.x * kRadix + threadIdx.x];
+#pragma unroll 16
+  for (int64_t r = r0; r < r1; ++r) {
+    const uint32_t v = hist[r * kRadix + threadIdx.x];
+    offs[r * kRadix + threadIdx.x] = run;
+    run += v;
+  }
 }
 
 // Stable scatter of one tile: the tile is first ordered by digit in LDS
@@ -107,8 +198,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter(
   __shared__ uint32_t delta[kRadix];          // output position - tile-local position, per digit
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const uint32_t mine = hist[(int64_t)threadIdx.x * ntiles + blockIdx.x];
-  const uint32_t out0 = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+  const uint32_t mine = hist[(int64_t)blockIdx.x * kRadix + threadIdx.x];
+  const uint32_t out0 = offs[(int64_t)blockIdx.x * kRadix + threadIdx.x];
   const uint32_t start = block_exclusive_scan(mine, wsum);
   bstart[threadIdx.x] = start;
   delta[threadIdx.x] = out0 - start;
@@ -156,12 +247,17 @@ __global__ __launch_bounds__(kThreads) void k_scatter(
 
 int64_t ntiles_of(int64_t n) { return (n + kTile - 1) / kTile; }
 
+// At most 256 chunks of tiles, so that one workgroup scans the chunk sums.
+int64_t chunk_rows(int64_t ntiles) { return (ntiles + kRadix - 1) / kRadix; }
+
 }  // namespace
 
 size_t sort_hist_bytes(int64_t n) {
   int64_t t = ntiles_of(n > 0 ? n : 1);
   int64_t h = (int64_t)kRadix * t;
-  return 2 * (size_t)(h + 1) * sizeof(uint32_t) + scan_tmp_bytes(h) + 256;
+  const int64_t crows = chunk_rows(t);
+  const int64_t nchunks = (t + crows - 1) / crows;
+  return (2 * (size_t)h + (size_t)kRadix * nchunks) * sizeof(uint32_t) + 256;
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits,
@@ -171,8 +267,10 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int
   const int64_t t = ntiles_of(n);
   const int64_t h = (int64_t)kRadix * t;
   uint32_t* hist = static_cast<uint32_t*>(hist_mem);
-  uint32_t* offs = hist + (h + 1);
-  void* stmp = offs + (h + 1);
+  uint32_t* offs = hist + h;
+  uint32_t* csum = offs + h;  // [chunks <= 256][256]
+  const int64_t crows = chunk_rows(t);
+  const int64_t nchunks = (t + crows - 1) / crows;
   const int passes = (bits + 7) / 8;
   const int w = (bits + passes - 1) / passes;
   int cur = 0;
@@ -184,7 +282,12 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int
                        mask, t, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = scan_exclusive_u32(hist, offs, h, stmp, s);
+    hipLaunchKernelGGL(k_col_reduce, dim3((unsigned)nchunks), dim3(kThreads), 0, s, hist, t, crows,
+                       csum);
+    hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(kScanThreads), 0, s, csum, nchunks);
+    hipLaunchKernelGGL(k_col_apply, dim3((unsigned)nchunks), dim3(kThreads), 0, s, hist, t, crows,
+                       csum, offs);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)t), dim3(kThreads), 0, s, keys[cur], vals[cur], n,
                        dn, shift, mask, wb, t, hist, offs, keys[cur ^ 1], vals[cur ^ 1]);
