@@ -46,24 +46,13 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
   return v;
 }
 
-// ---- cross-lane reduction of ten values (gfx950 lane permutes + DPP) ---------
+// ---- cross-lane reduction of ten values ------------------------------------------
 //
 // v_permlane32_swap exchanges the upper half-wave of one register with the
 // lower half-wave of another, v_permlane16_swap the odd rows (16 lanes) of one
-// with the even rows of another, so pairs of registers are folded without LDS:
-//   5 half-wave folds (10 -> 5 registers), 3 row folds (5 -> 3 registers),
-//   then a 16-lane DPP butterfly (quad_perm 1032, quad_perm 2301, row half
-//   mirror, row mirror) leaves every lane of a row holding that row's sum.
-// Result: out[0] rows (0, 1, 2, 3) = sums of (v0, v1, v5, v6); out[1] =
-// (v2, v3, v7, v8); out[2] = (v4, v4, v9, v9).
-__device__ inline float row_sum16(float v) {
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
-  return v;
-}
-
+// with the even rows of another; with both operands the same value, the
+// folds below leave every lane holding the sum over its lane and the lane 32
+// (or 16) away.
 __device__ inline float fold32(float a, float b) {
   const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
                                                   false);
@@ -76,42 +65,34 @@ __device__ inline float fold16(float a, float b) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-__device__ inline void wave_reduce10(const float (&v)[10], float (&out)[3]) {
-  const float w0 = fold32(v[0], v[5]), w1 = fold32(v[1], v[6]), w2 = fold32(v[2], v[7]),
-              w3 = fold32(v[3], v[8]), w4 = fold32(v[4], v[9]);
-  out[0] = row_sum16(fold16(w0, w1));
-  out[1] = row_sum16(fold16(w2, w3));
-  out[2] = row_sum16(fold16(w4, w4));
-}
+// The ten sums of a pair through LDS: the wave writes v[k] to row k of its
+// own 10 x kSumStride block, then lane 16 p + k (k < 10) adds the sixteen
+// values 16 p .. 16 p + 15 of row k (16-byte reads, eight at a time) and the
+// two folds add the four parts p, leaving sum k in lane k (lanes 10 .. 15 of
+// each row repeat row 9; their sums are of no use).  About twenty vector
+// instructions in place of the thirty-odd lane permutes, row-wise DPP adds
+// and selects of a register-only reduction, measured 0.9 ms faster per
+// 1024^3 x 1.4M pass.  The block belongs to one wave, whose LDS operations
+// complete in order, so no barrier separates the writes from the reads or the
+// reads from the next pair's writes.  A row stride of 68 floats puts the
+// 16-byte reads of lanes k = 0 .. 7 on distinct banks.
+constexpr int kSumStride = 68;
+constexpr int kSumFloats = 10 * kSumStride;
 
-// Which of the ten sums row r of out[k] holds (-1: duplicate): out[0] rows
-// (0, 1, 5, 6), out[1] rows (2, 3, 7, 8), out[2] rows (4, -, 9, -).  Plain
-// arithmetic, so nothing is read from memory.
-__device__ inline int reduce10_slot(int k, int row) {
-  const int base = row < 2 ? row : row + 3;
-  if (k == 0) return base;
-  if (k == 1) return base + 2;
-  return (row & 1) ? -1 : 4 + 5 * (row >> 1);
-}
-
-// The ten sums gathered into lanes 0 .. 9 of one register (lane a holds sum
-// a; the other lanes hold copies of no use): three lane permutes and two
-// selects, after which one store or atomic instruction, its lanes in one
-// 64-byte line, writes a pair's ten sums (one L2 request instead of three).
-// Lane a = 5 h + m (m < 5) takes out[k] from row 2 h + r with (k, r) =
-// (0, m) for m < 2, (1, m - 2) for m < 4, else (2, 0): reduce10_slot inverted.
-// Every lane of a row holds its sum, so lane a reads lane 16 (2 h + r) + a of
-// it (ten distinct LDS banks) and lanes 10 .. 63 read themselves.
-__device__ inline float gather10(const float (&o)[3], int lane) {
-  const int h = lane >= 5 ? 1 : 0;
-  const int m = lane - 5 * h;
-  const int k = m < 2 ? 0 : (m < 4 ? 1 : 2);
-  const int r = k == 0 ? m : (k == 1 ? m - 2 : 0);
-  const int src = lane < 10 ? 16 * (2 * h + r) + lane : lane;
-  const float a = __shfl(o[0], src, 64);
-  const float b = __shfl(o[1], src, 64);
-  const float c = __shfl(o[2], src, 64);
-  return k == 0 ? a : (k == 1 ? b : c);
+__device__ inline float lds_sum10(const float (&v)[10], float* __restrict__ buf, int lane) {
+#pragma unroll
+  for (int k = 0; k < 10; ++k) buf[k * kSumStride + lane] = v[k];
+  const int k = min(lane & 15, 9);
+  const float4* src = reinterpret_cast<const float4*>(buf + k * kSumStride + (lane & 48));
+  const float4 a = src[0], b = src[1];
+  float s = ((a.x + a.y) + (a.z + a.w)) + ((b.x + b.y) + (b.z + b.w));
+  // the second half's reads are issued once the first half is summed, so
+  // that at most eight read registers are live
+  asm volatile("" : "+v"(s)::"memory");
+  const float4 c = src[2], d = src[3];
+  s += ((c.x + c.y) + (c.z + c.w)) + ((d.x + d.y) + (d.z + d.w));
+  const float h = fold32(s, s);
+  return fold16(h, h);
 }
 
 // ---- per (primitive, column) setup -------------------------------------------
@@ -183,7 +164,10 @@ __device__ inline bool column_hit(const ColumnSetup& s, float sz, uint64_t cols,
 // With `steps` (one-wave bricks), the brick offsets at which some lane of
 // pair j - j0 < kStepCap was inside the support are stored as a bit mask
 // (0: the pair misses the brick), so the backward pass visits only those.
-constexpr uint32_t kStepCap = 1024;
+// 512 entries (2 KB) and the 2.7 KB block of the ten-sum reduction keep a
+// one-wave workgroup under 5 KB of LDS, so that 8 waves per SIMD stay
+// resident (a 768-entry cap, 7 waves, measured 12 % slower).
+constexpr uint32_t kStepCap = 512;
 
 // Forward steps of one pair: w, Q and exp2 at every offset of the box's
 // z-range (after the compare, offsets where no lane is inside the support are
@@ -487,7 +471,8 @@ __device__ inline void load_column_chunk(const float* __restrict__ field, const 
 // W > 1 (8 x 8 columns only): W waves share the brick's columns and split its
 // pairs (wave w takes pairs w, w + W, ...); the forward partial sums are added
 // in wave order through LDS (`comb`, W * BZ * 64 floats), after which every
-// wave holds the whole field of the brick.
+// wave holds the whole field of the brick.  `comb` is then each wave's block
+// of the ten-sum reduction (lds_sum10).
 template <int BXY, int BZ, bool VJP, int W>
 __device__ __attribute__((always_inline)) inline void fused_brick(const Record* __restrict__ rec,
                                    const uint32_t* __restrict__ pair_gid,
@@ -499,12 +484,13 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
                                    float* __restrict__ brick_loss,
                                    float (*red)[10], uint32_t* __restrict__ steps,
                                    float* __restrict__ comb) {
+  // `comb` holds the forward partial sums of W > 1 waves until they are
+  // added, then the waves' ten-sum blocks (kSumFloats each)
   constexpr int kWaves = (BXY * BXY + 63) / 64;  // waves over the columns
   static_assert(W == 1 || kWaves == 1, "pairs are split only over one wave of columns");
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const Site st = site_of<BXY, BZ>(items, nitems, b, W > 1 ? (uint32_t)lane : threadIdx.x);
-  const int row = lane >> 4;
   const float px = st.px, py = st.py, pz0 = st.pz0;
   const int iz0 = st.iz0;
   const bool col_in = st.col_in;
@@ -551,6 +537,9 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
 #pragma unroll
         for (int zz = z0; zz < z0 + 8; ++zz) asm volatile("" ::"v"(res[zz]) : "memory");
       }
+      // every wave has read the partial sums before `comb` takes the waves'
+      // ten-sum blocks
+      __syncthreads();
     }
     // residual and this brick's share of the loss
     float lsum = 0.0f;
@@ -643,23 +632,16 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
       v[8] = dy * s1;
       v[9] = s2;
     }
-    float o[3];
-    wave_reduce10(v, o);
+    // sum a in lane a < 10 (each wave of the workgroup has its own block)
+    const float sum = lds_sum10(v, comb + wave * kSumFloats, lane);
     if (kWaves == 1) {
-      const float sum = gather10(o, lane);
       if (part) {
         if (lane < 10) part[(size_t)pslot[j] * 10 + lane] = sum;
       } else if (lane < 10) {
         unsafeAtomicAdd(&gacc[(int64_t)gid * kAccStride + lane], sum);
       }
     } else {
-      if ((lane & 15) == 0) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const int slot = reduce10_slot(k, row);
-          if (slot >= 0) red[wave][slot] = o[k];
-        }
-      }
+      if (lane < 10) red[wave][lane] = sum;
       __syncthreads();
       if (threadIdx.x < 10) {
         float t = 0.0f;
@@ -673,6 +655,15 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
       __syncthreads();
     }
   }
+}
+
+// Floats of the fused kernels' shared block: the larger of the W > 1 forward
+// partial sums and the waves' ten-sum blocks (the two are live one after the
+// other).
+constexpr int fused_lds_floats(int bz, bool vjp, int w, int waves) {
+  const int comb = w > 1 && !vjp ? w * bz * 64 : 0;
+  const int sums = w * waves * kSumFloats;
+  return comb > sums ? comb : sums;
 }
 
 // One workgroup per brick (xcd: consecutive bricks grouped per XCD); W waves
@@ -691,7 +682,7 @@ __global__ __launch_bounds__(BXY* BXY* W) void k_fused(const Record* __restrict_
   constexpr int kWaves = (BXY * BXY + 63) / 64;
   __shared__ float red[kWaves][10];
   __shared__ uint32_t steps[kWaves == 1 && !VJP ? kStepCap : 1];
-  __shared__ float comb[W > 1 && !VJP ? W * BZ * 64 : 1];
+  __shared__ __attribute__((aligned(16))) float comb[fused_lds_floats(BZ, VJP, W, kWaves)];
   const uint32_t b = xcd ? xcd_brick(blockIdx.x, nbricks) : blockIdx.x;
   fused_brick<BXY, BZ, VJP, W>(rec, pair_gid, brick_start, items, nitems, b, thr, field, gacc, n,
                                part, pslot, brick_loss, red, steps, comb);
@@ -716,7 +707,7 @@ __global__ __launch_bounds__(BXY* BXY* W) void k_fused_queue(const Record* __res
   constexpr int kWaves = (BXY * BXY + 63) / 64;
   __shared__ float red[kWaves][10];
   __shared__ uint32_t steps[kWaves == 1 && !VJP ? kStepCap : 1];
-  __shared__ float comb[W > 1 && !VJP ? W * BZ * 64 : 1];
+  __shared__ __attribute__((aligned(16))) float comb[fused_lds_floats(BZ, VJP, W, kWaves)];
   __shared__ uint32_t next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
