@@ -279,6 +279,34 @@ def test_loss_grad_both_backward_forms(kind):
     check_grad(grad, gr, slack=slack)
 
 
+@pytest.mark.parametrize("waves", [1, 2])
+@pytest.mark.parametrize("deterministic", [True, False])
+def test_loss_grad_crowded_bricks(deterministic, waves):
+    """1,500 primitives in a 16 x 16 x 32 grid: each of its four 8 x 8 x 32
+    bricks holds well over the 512 pairs whose active offsets the forward
+    pass records, so the backward pass also runs its unrecorded form (the
+    box z-range with a support test per offset) for the later pairs."""
+    g, torch = _lib()
+    grid = F.Grid(16, 16, 32, 0, 0, 0)
+    n = 1500
+    p = S.random_params(n, (16, 16, 32), seed=61, scale_range=(1.0, 3.0),
+                        weight_range=(-0.2, 0.2), unit_quat=False)
+    p = p.astype(np.float32).astype(np.float64)
+    field = np.random.default_rng(62).uniform(-0.5, 1.0, size=grid.shape).astype(np.float32)
+    ctx = g.Context(k=3.0, brick=8, brick_z=32, brick_waves=waves, deterministic=deterministic)
+    pp = g.Params(ctx, n).upload(p.astype(np.float32))
+    f = torch.from_numpy(field).cuda()
+    grad = torch.empty((11, n), device="cuda", dtype=torch.float32)
+    L = g.loss_grad(ctx, pp, f, g.Grid(16, 16, 32), grad)
+    pairs = ctx.stats()["n_overlaps"]
+    print(f"crowded bricks: {pairs} pairs over 4 bricks", flush=True)
+    assert pairs > 4 * 600  # > 512 per brick on average
+    Lr, gr = F.loss_grad(p, field.astype(np.float64), grid, 3.0)
+    assert abs(L - Lr) <= 1e-5 * Lr
+    slack, _ = F.boundary_slack(p, field, grid, 3.0, BAND)
+    check_grad(grad.cpu().numpy().astype(np.float64), gr, slack=slack)
+
+
 def test_deterministic_gradient_is_bitwise_reproducible():
     g, torch = _lib()
     grid = F.Grid(40, 36, 44)
