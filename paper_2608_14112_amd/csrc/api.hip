@@ -692,7 +692,7 @@ gve_status gve_params_create(gve_ctx* ctx, int64_t n, gve_params** out) {
   if (e == hipSuccess) e = hipMalloc(&p->m, f11);
   if (e == hipSuccess) e = hipMalloc(&p->v, f11);
   if (e == hipSuccess) e = hipMalloc(&p->acc, sizeof(float) * gve::kAccStride * (size_t)n);
-  if (e == hipSuccess) e = hipMalloc(&p->rec, sizeof(gve::Record) * (size_t)n);
+  if (e == hipSuccess) e = hipMalloc(&p->rec, gve::record_bytes(n));
   if (e == hipSuccess) e = hipMalloc(&p->count, sizeof(uint32_t) * (size_t)n);
   if (e == hipSuccess) e = hipMalloc(&p->offset, sizeof(uint32_t) * (size_t)(n + 1));
   if (e == hipSuccess) e = gve::fill_f32(p->theta, 11 * n, 0.0f, ctx->stream);

@@ -33,7 +33,8 @@ __device__ inline int item_of_prim(const ItemDesc* __restrict__ items, int nitem
 
 __device__ inline uint32_t prep_one(const float* __restrict__ theta, int64_t n, int64_t i,
                                     const ItemDesc& g, float k, BrickGeom bg,
-                                    Record* __restrict__ rec, bool& degenerate) {
+                                    Record* __restrict__ rec, BoxXY* __restrict__ box,
+                                    bool& degenerate) {
   const float mx = theta[0 * n + i], my = theta[1 * n + i], mz = theta[2 * n + i];
   float qw = theta[3 * n + i], qx = theta[4 * n + i], qy = theta[5 * n + i],
         qz = theta[6 * n + i];
@@ -79,6 +80,10 @@ __device__ inline uint32_t prep_one(const float* __restrict__ theta, int64_t n, 
   r.s[2] = -kHalfLog2e * sxx * idet;
   r.gx = -pxz / pzz;
   r.gy = -pyz / pzz;
+  r.sgx = r.sz * r.gx;
+  r.sgy = r.sz * r.gy;
+  r.cz = __builtin_amdgcn_exp2f(-2.0f * r.sz * r.sz);
+  r.spare = 0.0f;
 
   // conservative box: relative and absolute slack cover float32 rounding here
   const float mu3[3] = {mx, my, mz};
@@ -115,9 +120,13 @@ __device__ inline uint32_t prep_one(const float* __restrict__ theta, int64_t n, 
 #pragma unroll
     for (int j = 0; j < 3; ++j) { lo[j] = 1; hi[j] = 0; }
   }
-#pragma unroll
-  for (int j = 0; j < 3; ++j) { r.lo[j] = lo[j]; r.hi[j] = hi[j]; }
+  r.zlo = lo[2];
+  r.zhi = hi[2];
   rec[i] = r;
+  BoxXY b;
+  b.lo[0] = lo[0]; b.lo[1] = lo[1];
+  b.hi[0] = hi[0]; b.hi[1] = hi[1];
+  box[i] = b;
   return cnt;
 }
 
@@ -132,7 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_prep(const float* __restrict__ the
   bool degenerate = false;
   if (i < n)
     cnt = prep_one(theta, n, i, items[item_of_prim(items, nitems, (uint32_t)i)], k, bg, rec,
-                   degenerate);
+                   record_boxes(rec, n), degenerate);
   if (i < n) count[i] = cnt;
   // degenerate quaternions (rare): one atomic per wave that has any
   const uint64_t deg = __builtin_amdgcn_ballot_w64(degenerate);
@@ -174,14 +183,14 @@ __global__ __launch_bounds__(kThreads) void k_prep(const float* __restrict__ the
 // and (log2 e / 2) d^T P d = sz^2 t^2 - qxy.  The test is conservative: a brick
 // it keeps may still miss (the brick kernels test every column anyway).
 // (ox, oy, oz): the volume's origin minus the primitive's centre (float).
-__device__ inline bool brick_meets_support(const Record& r, float ox, float oy, float oz,
-                                           BrickGeom bg, uint32_t bx, uint32_t by, uint32_t bz,
-                                           float k) {
+__device__ inline bool brick_meets_support(const Record& r, const BoxXY& box, float ox, float oy,
+                                           float oz, BrickGeom bg, uint32_t bx, uint32_t by,
+                                           uint32_t bz, float k) {
   const int bxy = bg.Bxy, bzz = bg.Bz;
   const int sxy = __builtin_ctz(bxy), sz = __builtin_ctz(bzz);  // edges are powers of two
-  const int xa = max((int)(bx << sxy), r.lo[0]), xb = min((int)(bx << sxy) + bxy - 1, r.hi[0]);
-  const int ya = max((int)(by << sxy), r.lo[1]), yb = min((int)(by << sxy) + bxy - 1, r.hi[1]);
-  const int za = max((int)(bz << sz), r.lo[2]), zb = min((int)(bz << sz) + bzz - 1, r.hi[2]);
+  const int xa = max((int)(bx << sxy), box.lo[0]), xb = min((int)(bx << sxy) + bxy - 1, box.hi[0]);
+  const int ya = max((int)(by << sxy), box.lo[1]), yb = min((int)(by << sxy) + bxy - 1, box.hi[1]);
+  const int za = max((int)(bz << sz), r.zlo), zb = min((int)(bz << sz) + bzz - 1, r.zhi);
   const float dx = 0.5f * (float)(xa + xb) + ox;
   const float dy = 0.5f * (float)(ya + yb) + oy;
   const float dz = 0.5f * (float)(za + zb) + oz;
@@ -228,15 +237,15 @@ struct BoxBricks {
   }
 };
 
-__device__ inline BoxBricks box_bricks(const Record& r, BrickGeom bg) {
+__device__ inline BoxBricks box_bricks(const Record& r, const BoxXY& box, BrickGeom bg) {
   BoxBricks b;
   // brick edges are powers of two; box corners are >= 0
   const uint32_t sxy = (uint32_t)__builtin_ctz(bg.Bxy), sz = (uint32_t)__builtin_ctz(bg.Bz);
-  b.bx0 = (uint32_t)r.lo[0] >> sxy;
-  b.by0 = (uint32_t)r.lo[1] >> sxy;
-  b.bz0 = (uint32_t)r.lo[2] >> sz;
-  b.nbx = ((uint32_t)r.hi[0] >> sxy) - b.bx0 + 1;
-  b.nby = ((uint32_t)r.hi[1] >> sxy) - b.by0 + 1;
+  b.bx0 = (uint32_t)box.lo[0] >> sxy;
+  b.by0 = (uint32_t)box.lo[1] >> sxy;
+  b.bz0 = (uint32_t)r.zlo >> sz;
+  b.nbx = ((uint32_t)box.hi[0] >> sxy) - b.bx0 + 1;
+  b.nby = ((uint32_t)box.hi[1] >> sxy) - b.by0 + 1;
   b.inv_nbx = 1.0f / (float)b.nbx;
   b.inv_nby = 1.0f / (float)b.nby;
   return b;
@@ -265,18 +274,22 @@ __global__ __launch_bounds__(kThreads) void k_cull(const Record* __restrict__ re
   const bool room = fits == nullptr || *fits != 0u;
   uint32_t o = 0, total = 0;
   Record r{};
+  BoxXY box{};
   if (live && room) {
-    // the offsets and the record loaded together, one wait for all (pinning
-    // the record here keeps its loads from following the offsets' latency)
+    // the offsets, the record and the box loaded together, one wait for all
+    // (pinning them here keeps their loads from following the offsets'
+    // latency)
     o = box_off[i];
     total = box_off[i + 1] - o;
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const u32x4* src = reinterpret_cast<const u32x4*>(rec + i);
-    u32x4 q[4];
+    u32x4 q[5];
 #pragma unroll
     for (int h = 0; h < 4; ++h) q[h] = src[h];
-    asm volatile("" ::"v"(q[0]), "v"(q[1]), "v"(q[2]), "v"(q[3]));
+    q[4] = *reinterpret_cast<const u32x4*>(record_boxes(rec, n) + i);
+    asm volatile("" ::"v"(q[0]), "v"(q[1]), "v"(q[2]), "v"(q[3]), "v"(q[4]));
     __builtin_memcpy(&r, q, sizeof(Record));
+    __builtin_memcpy(&box, &q[4], sizeof(BoxXY));
   }
   if (live && !room && sub == 0) count[i] = 0;
   BoxBricks bb{};
@@ -285,7 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_cull(const Record* __restrict__ re
   float ox = 0.f, oy = 0.f, oz = 0.f;
   uint32_t kb0 = 0, knbx = 0, knby = 0;
   if (total > 0) {
-    bb = box_bricks(r, bg);
+    bb = box_bricks(r, box, bg);
     const ItemDesc& it = items[item_of_prim(items, nitems, (uint32_t)i)];
     ox = (float)it.x0 - r.mu[0];
     oy = (float)it.y0 - r.mu[1];
@@ -304,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void k_cull(const Record* __restrict__ re
     uint32_t bx = 0, by = 0, bz = 0;
     if (j < total) {
       bb.at(j, bx, by, bz);
-      keep = brick_meets_support(r, ox, oy, oz, bg, bx, by, bz, k);
+      keep = brick_meets_support(r, box, ox, oy, oz, bg, bx, by, bz, k);
     }
     const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
     // brick key: the global brick id (x fastest within the volume)

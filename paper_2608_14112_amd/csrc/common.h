@@ -22,17 +22,39 @@ namespace gve {
 // complement -(log2 e / 2) (Sigma_xy)^{-1}:
 //     d^T A d = qxy - (sz (dz - gx dx - gy dy))^2,  sz = sqrt(-A_zz).
 //   mu[3], c, sz, s[3] = (S_xx, 2 S_xy, S_yy), gx, gy,
-//   lo[3], hi[3] : inclusive voxel-index bounding box of the k-sigma support.
+//   zlo, zhi : inclusive voxel z-index range of the k-sigma support box,
+//   sgx = sz gx, sgy = sz gy : the slopes of w = sz t in x and y,
+//   cz = exp2(-2 sz^2) : the ratio of consecutive first differences' factors
+//        in the backward recurrence, the same in every brick.
+// The box's x and y ranges, which only the binning reads, are BoxXY entries
+// stored after the n records of a parameter set (record_boxes).
 struct alignas(64) Record {
   float mu[3];
   float c;
   float sz;
   float s[3];
   float gx, gy;
-  int lo[3];
-  int hi[3];
+  int zlo, zhi;
+  float sgx, sgy;
+  float cz;
+  float spare;
 };
 static_assert(sizeof(Record) == 64, "record must be 64 bytes");
+
+struct alignas(16) BoxXY {
+  int lo[2];
+  int hi[2];
+};
+static_assert(sizeof(BoxXY) == 16, "box must be 16 bytes");
+
+// Bytes of a record array for n primitives: n records, then n boxes.
+inline size_t record_bytes(int64_t n) { return (sizeof(Record) + sizeof(BoxXY)) * (size_t)n; }
+__host__ __device__ inline BoxXY* record_boxes(Record* rec, int64_t n) {
+  return reinterpret_cast<BoxXY*>(rec + n);
+}
+__host__ __device__ inline const BoxXY* record_boxes(const Record* rec, int64_t n) {
+  return reinterpret_cast<const BoxXY*>(rec + n);
+}
 
 constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
 

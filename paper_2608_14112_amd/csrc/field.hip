@@ -105,7 +105,7 @@ __device__ inline float lds_sum10(const float (&v)[10], float* __restrict__ buf,
 // expansion in powers of zz about the brick's first voxel would, when the
 // vertex is far from it).
 struct ColumnSetup {
-  float qxy, t0, wm;  // vertex height, t at the brick's first z, w at its middle
+  float qxy, wm;  // vertex height, w at the brick's middle
   int za, zb;
   uint32_t zmask;  // bit zz set when brick offset zz lies in the z-range of the box
 };
@@ -113,15 +113,17 @@ struct ColumnSetup {
 template <int BZ>
 __device__ inline ColumnSetup column_setup(const Record& r, float px, float py, float pz0, int iz0) {
   ColumnSetup s;
-  s.za = max(r.lo[2] - iz0, 0);
-  s.zb = min(r.hi[2] - iz0, BZ - 1);
+  s.za = max(r.zlo - iz0, 0);
+  s.zb = min(r.zhi - iz0, BZ - 1);
   // bits za..zb (BZ <= 32; 2u << 31 wraps to 0, giving all ones)
   s.zmask = (s.zb >= s.za) ? (((2u << s.zb) - 1u) & ~((1u << s.za) - 1u)) : 0u;
   const float dx = px - r.mu[0];
   const float dy = py - r.mu[1];
   s.qxy = fmaf(r.s[0], dx, r.s[1] * dy) * dx + r.s[2] * dy * dy;
-  s.t0 = (pz0 - r.mu[2]) - fmaf(r.gx, dx, r.gy * dy);
-  s.wm = r.sz * (s.t0 + (float)(BZ / 2));
+  // w = sz t at the brick's middle: the brick offset from the centre first
+  // (pz0 + BZ / 2 is exact and the same for every pair of the brick), then
+  // the record's scaled slopes
+  s.wm = fmaf(-r.sgy, dy, fmaf(-r.sgx, dx, r.sz * ((pz0 + (float)(BZ / 2)) - r.mu[2])));
   return s;
 }
 
@@ -391,7 +393,8 @@ __device__ inline void backward_steps(const ColumnSetup& s, float szv, uint32_t 
 
 // Backward steps of a recorded pair by recurrence.  Along a column Q is a
 // parabola in zz: with R(zz) = exp2(Q(zz + 1) - Q(zz)) = exp2(-(2 w + sz) sz)
-// and C = exp2(-2 sz^2), G(zz + 1) = G(zz) R(zz) and R(zz + 1) = R(zz) C, two
+// and C = exp2(-2 sz^2) (the record's cz), G(zz + 1) = G(zz) R(zz) and
+// R(zz + 1) = R(zz) C, two
 // products per step in place of w, Q and an exp2.  The chain starts exactly
 // one offset before the first recorded offset z0 (w, Q, and exp2 of Q and of
 // the first difference there) and advances once per offset up to the last,
@@ -406,14 +409,13 @@ __device__ inline void backward_steps(const ColumnSetup& s, float szv, uint32_t 
 // 1e-5, keeps the direct exponential.  The support test is G > T with
 // T = exp2(thr).
 template <int BZ>
-__device__ inline void backward_steps_chain(const ColumnSetup& s, float szv, float sz, int z0,
-                                            int z1, const float (&res)[BZ], float T, float& se,
-                                            float& sK, float& sKK) {
+__device__ inline void backward_steps_chain(const ColumnSetup& s, float szv, float sz, float C,
+                                            int z0, int z1, const float (&res)[BZ], float T,
+                                            float& se, float& sK, float& sKK) {
   const float w0 = fmaf((float)(z0 - 1 - BZ / 2), szv, s.wm);
   const float q0 = quad_w(s, w0);
   float G = q0 > -100.0f ? __builtin_amdgcn_exp2f(q0) : 0.0f;
   float R = __builtin_amdgcn_exp2f(fminf(-fmaf(2.0f, w0, sz) * sz, 100.0f));
-  const float C = __builtin_amdgcn_exp2f(-2.0f * sz * sz);
   // offsets z0 .. z1 (z1 <= 31; 2u << 31 wraps to 0, giving all ones)
   const uint32_t span = ((2u << z1) - 1u) & ~((1u << z0) - 1u);
 #pragma unroll
@@ -606,7 +608,7 @@ __device__ __attribute__((always_inline)) inline void fused_brick(const Record* 
         if (recorded) {
           const int z0 = (int)__builtin_ctz(run), z1 = 31 - (int)__builtin_clz(run);
           if ((float)(z1 - z0 + 1) * r.sz < reach)
-            backward_steps_chain<BZ>(s, szv, r.sz, z0, z1, res, T, se, sK, sKK);
+            backward_steps_chain<BZ>(s, szv, r.sz, r.cz, z0, z1, res, T, se, sK, sKK);
           else
             backward_steps<BZ, false>(s, szv, run, res, thr, se, sK, sKK);
         } else {
