@@ -94,25 +94,26 @@ __global__ __launch_bounds__(kThreads) void k_col_reduce(const uint32_t* __restr
   csum[(int64_t)blockIdx.x * kRadix + threadIdx.x] = s;
 }
 
-// One workgroup of 1024 threads: per digit, the exclusive scan of the chunk
-// sums over the `nchunks` (<= 256) chunks, plus the items of all smaller
-// digits; the result (the write offset of each chunk's first tile)
-// overwrites csum.  Thread (q, d) takes digit d over a quarter of the chunks.
+// One workgroup of 1024 threads: per digit, the exclusive scan over `nrows`
+// (<= 256) rows of 256 counts, plus the items of all smaller digits, written
+// to out (which may be in: the chunk sums are scanned in place, and a
+// histogram of at most 256 tiles is scanned straight into the offsets).
+// Thread (q, d) takes digit d over a quarter of the rows.
 constexpr int kScanParts = 4;
 constexpr int kScanThreads = kScanParts * kRadix;
-__global__ __launch_bounds__(kScanThreads) void k_col_scan(uint32_t* __restrict__ csum,
-                                                           int64_t nchunks) {
+__global__ __launch_bounds__(kScanThreads) void k_col_scan(const uint32_t* in, uint32_t* out,
+                                                           int64_t nrows) {
   __shared__ uint32_t part[kScanParts][kRadix];
   __shared__ uint32_t wsum[kWaves];
   __shared__ uint32_t dbase[kRadix];
   const int d = threadIdx.x & (kRadix - 1);
   const int q = threadIdx.x / kRadix;
-  const int64_t per = (nchunks + kScanParts - 1) / kScanParts;
-  const int64_t c0 = min(q * per, nchunks);
-  const int64_t c1 = min(c0 + per, nchunks);
+  const int64_t per = (nrows + kScanParts - 1) / kScanParts;
+  const int64_t c0 = min(q * per, nrows);
+  const int64_t c1 = min(c0 + per, nrows);
   uint32_t sum = 0;
 #pragma unroll 16
-  for (int64_t c = c0; c < c1; ++c) sum += csum[c * kRadix + d];
+  for (int64_t c = c0; c < c1; ++c) sum += in[c * kRadix + d];
   part[q][d] = sum;
   __syncthreads();
   uint32_t before = 0, total = 0;
@@ -145,8 +146,8 @@ __global__ __launch_bounds__(kScanThreads) void k_col_scan(uint32_t* __restrict_
   uint32_t run = dbase[d] + before;
 #pragma unroll 16
   for (int64_t c = c0; c < c1; ++c) {
-    const uint32_t v = csum[c * kRadix + d];
-    csum[c * kRadix + d] = run;
+    const uint32_t v = in[c * kRadix + d];
+    out[c * kRadix + d] = run;
     run += v;
   }
 }
@@ -282,11 +283,16 @@ hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int
                        mask, t, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_col_reduce, dim3((unsigned)nchunks), dim3(kThreads), 0, s, hist, t, crows,
-                       csum);
-    hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(kScanThreads), 0, s, csum, nchunks);
-    hipLaunchKernelGGL(k_col_apply, dim3((unsigned)nchunks), dim3(kThreads), 0, s, hist, t, crows,
-                       csum, offs);
+    if (t <= kRadix) {
+      // one tile per chunk: the chunk sums would be the histogram's rows
+      hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(kScanThreads), 0, s, hist, offs, t);
+    } else {
+      hipLaunchKernelGGL(k_col_reduce, dim3((unsigned)nchunks), dim3(kThreads), 0, s, hist, t,
+                         crows, csum);
+      hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(kScanThreads), 0, s, csum, csum, nchunks);
+      hipLaunchKernelGGL(k_col_apply, dim3((unsigned)nchunks), dim3(kThreads), 0, s, hist, t,
+                         crows, csum, offs);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)t), dim3(kThreads), 0, s, keys[cur], vals[cur], n,
