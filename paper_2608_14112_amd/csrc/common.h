@@ -172,7 +172,9 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void
 // Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits of
 // the key.  Ping-pongs between buffers 0 and 1; returns in *which the index of
 // the buffer that holds the result.  With dn, the item count is
-// min(n, *dn) read on the device (n is then the buffers' capacity).
+// min(n, *dn) read on the device (n is then the buffers' capacity).  hist
+// must hold sort_hist_bytes(m) bytes for some m >= n (one buffer serves every
+// sort of at most m items).
 size_t sort_hist_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits,
                             void* hist, int* which, hipStream_t s, const uint32_t* dn = nullptr);

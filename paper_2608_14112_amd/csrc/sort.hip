@@ -253,12 +253,14 @@ int64_t chunk_rows(int64_t ntiles) { return (ntiles + kRadix - 1) / kRadix; }
 
 }  // namespace
 
+// Room for a sort of any item count up to n: the histogram and the offsets
+// (256 per tile), and the chunk sums sized for the largest chunk count, 256
+// (the count for fewer items can be larger: 512 tiles make 256 chunks of 2,
+// 513 tiles 171 chunks of 3).
 size_t sort_hist_bytes(int64_t n) {
   int64_t t = ntiles_of(n > 0 ? n : 1);
   int64_t h = (int64_t)kRadix * t;
-  const int64_t crows = chunk_rows(t);
-  const int64_t nchunks = (t + crows - 1) / crows;
-  return (2 * (size_t)h + (size_t)kRadix * nchunks) * sizeof(uint32_t) + 256;
+  return (2 * (size_t)h + (size_t)kRadix * kRadix) * sizeof(uint32_t) + 256;
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int bits,
