@@ -305,30 +305,30 @@ struct AssembleArgs {
   double s_cap;
   uint64_t seed;
   float* theta;           // [11][n]
+  const double* J6;       // [n][6] structure tensors at the seeds (k_tensor)
 };
+
+// One wave per primitive: the structure tensor at its seed voxel (S1d).
+__global__ __launch_bounds__(256) void k_tensor(const float* __restrict__ f, Dims d,
+                                                const int64_t* __restrict__ det,
+                                                const int64_t* __restrict__ cov, int64_t n_det,
+                                                int64_t n, double* __restrict__ J6) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;  // wave-uniform
+  const int64_t vox = i < n_det ? det[i] : cov[i - n_det];
+  const int64_t ii = vox % d.nx, jj = (vox / d.nx) % d.ny, kk = vox / (d.nx * d.ny);
+  wave_structure_tensor(f, d, ii, jj, kk, J6 + 6 * i);
+}
 
 __global__ __launch_bounds__(128) void k_assemble(AssembleArgs a) {
   const int64_t i = (int64_t)blockIdx.x * 128 + threadIdx.x;
   if (i >= a.n) return;
   const int group = i < a.n_det ? 0 : 1;
   const int64_t vox = group == 0 ? a.det[i] : a.cov[i - a.n_det];
-  const int64_t ii = vox % a.d.nx, jj = (vox / a.d.nx) % a.d.ny, kk = vox / (a.d.nx * a.d.ny);
   const int64_t n = a.n;
-  // structure tensor over the clipped 7^3 box (S1d)
-  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  const int64_t ka = max((int64_t)0, kk - 3), kb = min(a.d.nz - 1, kk + 3);
-  const int64_t ja = max((int64_t)0, jj - 3), jb = min(a.d.ny - 1, jj + 3);
-  const int64_t ia = max((int64_t)0, ii - 3), ib = min(a.d.nx - 1, ii + 3);
-  for (int64_t z = ka; z <= kb; ++z)
-    for (int64_t y = ja; y <= jb; ++y)
-      for (int64_t x = ia; x <= ib; ++x) {
-        float gx, gy, gz;
-        grad_parts(a.f, a.d, x, y, z, &gx, &gy, &gz);
-        const double X = gx, Y = gy, Z = gz;
-        J[0][0] += X * X; J[0][1] += X * Y; J[0][2] += X * Z;
-        J[1][1] += Y * Y; J[1][2] += Y * Z; J[2][2] += Z * Z;
-      }
-  J[1][0] = J[0][1]; J[2][0] = J[0][2]; J[2][1] = J[1][2];
+  // structure tensor over the clipped 7^3 box (S1d), from k_tensor
+  const double* t = a.J6 + 6 * i;
+  double J[3][3] = {{t[0], t[1], t[2]}, {t[1], t[3], t[4]}, {t[2], t[4], t[5]}};
   double R[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
   if (J[0][0] + J[1][1] + J[2][2] >= 1e-12) {
     double A[3][3], V[3][3];
@@ -594,7 +594,7 @@ hipError_t alloc_set_state(unsigned long long* st, unsigned long long prefix,
 hipError_t alloc_assemble(const float* f, const float* g32, const gve_grid& g, const int64_t* det,
                           const int64_t* cov, int64_t n_det, int64_t n, const double* s_base,
                           const unsigned long long* g99_state, uint64_t seed, float* theta,
-                          hipStream_t s) {
+                          double* J6, hipStream_t s) {
   AssembleArgs a;
   a.f = f;
   a.g32 = g32;
@@ -611,6 +611,11 @@ hipError_t alloc_assemble(const float* f, const float* g32, const gve_grid& g, c
   a.s_cap = (double)mx / 16.0;
   a.seed = seed;
   a.theta = theta;
+  a.J6 = J6;
+  hipLaunchKernelGGL(k_tensor, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, f, a.d, det, cov,
+                     n_det, n, J6);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_assemble, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, a);
   return hipGetLastError();
 }

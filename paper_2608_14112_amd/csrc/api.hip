@@ -1470,7 +1470,7 @@ gve_status gve_allocate(gve_ctx* ctx, const float* d_field, gve_grid g, int64_t 
                o_best = take(4096 * 8), o_dot = take(sizeof(double) * gve::alloc_dot_tmp_doubles()),
                o_less = take(4 * (nb + 1)), o_tie = take(4 * (nb + 1)), o_toff = take(4 * (nb + 1)),
                o_take = take(4 * (nb + 1)), o_ooff = take(4 * (nb + 1)), o_det = take(8 * n_det),
-               o_cov = take(8 * n_cov);
+               o_cov = take(8 * n_cov), o_j6 = take(6 * sizeof(double) * (size_t)budget);
   TRY(ensure(ctx, ctx->ws.alloc, off));
   TRY(ensure(ctx, ctx->ws.voxf, sizeof(float) * (size_t)M));
   TRY(ensure(ctx, ctx->ws.scan_tmp, gve::scan_tmp_bytes(nb + 1)));
@@ -1539,7 +1539,7 @@ gve_status gve_allocate(gve_ctx* ctx, const float* d_field, gve_grid g, int64_t 
   TRY_A(gve::alloc_spacing(p->theta, budget, n_det, n_cov, F64(o_best), sb + 1, s));
   // S1d/S1e: frames, scales, values
   TRY_A(gve::alloc_assemble(d_field, g32, g, det, cov, n_det, budget, sb, st_g99, seed, p->theta,
-                            s));
+                            F64(o_j6), s));
   // weights: U = sum a_i G_i on the grid (g32's buffer is free now), kappa
   Binned bn;
   st = bin(ctx, p, g, &bn);
@@ -1884,12 +1884,14 @@ gve_status gve_features(gve_ctx* ctx, const gve_params* p, const float* d_field,
   TRY(validate_grid(ctx, g));
   TRY(set_device(ctx));
   const int64_t M = g.nx * g.ny * g.nz;
-  TRY(ensure(ctx, ctx->ws.sat, 2 * sizeof(double) * (size_t)M));
+  // summed-area tables of V and V^2, then the primitives' structure tensors
+  TRY(ensure(ctx, ctx->ws.sat, sizeof(double) * (2 * (size_t)M + 6 * (size_t)p->n)));
   double* s1 = static_cast<double*>(ctx->ws.sat.ptr);
   double* s2 = s1 + M;
+  double* J6 = s2 + M;
   TRY_HIP(ctx, gve::mlp_sat(d_field, g, s1, s2, ctx->stream));
-  TRY_HIP(ctx, gve::mlp_features(d_field, p->theta, p->n, n_detail, g, g99, ctx->opt.k, s1, s2, d_X,
-                                 ctx->stream));
+  TRY_HIP(ctx, gve::mlp_features(d_field, p->theta, p->n, n_detail, g, g99, ctx->opt.k, s1, s2, J6,
+                                 d_X, ctx->stream));
   return GVE_OK;
 }
 

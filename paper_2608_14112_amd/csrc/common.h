@@ -324,10 +324,11 @@ hipError_t alloc_jitter(const gve_grid& g, const int64_t* det, const int64_t* co
                         int64_t n, uint64_t seed, float* theta, hipStream_t s);
 hipError_t alloc_spacing(const float* theta, int64_t n, int64_t first, int64_t ng, double* best,
                          double* s_base, hipStream_t s);
+// J6: 6 n doubles of workspace (the seeds' structure tensors).
 hipError_t alloc_assemble(const float* f, const float* g32, const gve_grid& g, const int64_t* det,
                           const int64_t* cov, int64_t n_det, int64_t n, const double* s_base,
                           const unsigned long long* g99_state, uint64_t seed, float* theta,
-                          hipStream_t s);
+                          double* J6, hipStream_t s);
 size_t alloc_dot_tmp_doubles();
 hipError_t alloc_weights(const float* U, const float* f, int64_t M, float* c_row, int64_t n,
                          double* tmp, hipStream_t s);
@@ -383,9 +384,10 @@ hipError_t mlp_standardize(const float* X, const uint32_t* perm, int64_t rows, i
 hipError_t mlp_perm_keys(uint32_t* keys, uint32_t* vals, int64_t n, uint64_t seed, uint64_t epoch,
                          hipStream_t s);
 hipError_t mlp_sat(const float* f, const gve_grid& g, double* s1, double* s2, hipStream_t s);
+// J6: 6 n doubles of workspace (the structure tensors at the centres).
 hipError_t mlp_features(const float* f, const float* theta, int64_t n, int64_t n_detail,
                         const gve_grid& g, double g99, float k, const double* s1, const double* s2,
-                        float* X, hipStream_t s);
+                        double* J6, float* X, hipStream_t s);
 hipError_t mlp_targets(const float* ta, const float* tr, int64_t n, float* T, hipStream_t s);
 hipError_t mlp_apply_delta(float* theta, const float* base, const float* Y, int64_t n,
                            const float* tmean, const float* tstd, float alpha, hipStream_t s);

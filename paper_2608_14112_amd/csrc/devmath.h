@@ -124,6 +124,42 @@ static __device__ inline float grad_mag32(const float* __restrict__ f, Dims d, i
   return (float)sqrt((x * x + y * y) + z * z);
 }
 
+// Structure tensor at voxel (ci, cj, ck): the sum of g g^T over the 7^3 box
+// around it, clipped to the grid, with g the central-difference gradient
+// (grad_parts).  Called by all 64 lanes of a wave: the box's voxels are dealt
+// to the lanes (voxel t, x fastest, to lane t mod 64), so that a wave's loads
+// fall on neighbouring voxels; each lane sums its own in float64, the six
+// unique entries (xx, xy, xz, yy, yz, zz) are added across the wave, and
+// lanes 0 .. 5 store entry `lane` to J6.
+static __device__ inline void wave_structure_tensor(const float* __restrict__ f, Dims d,
+                                                    int64_t ci, int64_t cj, int64_t ck,
+                                                    double* __restrict__ J6) {
+  const int lane = threadIdx.x & 63;
+  const int64_t ia = ci - 3 < 0 ? 0 : ci - 3, ib = ci + 3 > d.nx - 1 ? d.nx - 1 : ci + 3;
+  const int64_t ja = cj - 3 < 0 ? 0 : cj - 3, jb = cj + 3 > d.ny - 1 ? d.ny - 1 : cj + 3;
+  const int64_t ka = ck - 3 < 0 ? 0 : ck - 3, kb = ck + 3 > d.nz - 1 ? d.nz - 1 : ck + 3;
+  const int wx = (int)(ib - ia + 1), wy = (int)(jb - ja + 1), wz = (int)(kb - ka + 1);
+  const int cnt = wx * wy * wz;
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = lane; t < cnt; t += 64) {
+    const int x = t % wx, r = t / wx;
+    float gx, gy, gz;
+    grad_parts(f, d, ia + x, ja + r % wy, ka + r / wy, &gx, &gy, &gz);
+    const double X = gx, Y = gy, Z = gz;
+    s[0] += X * X; s[1] += X * Y; s[2] += X * Z;
+    s[3] += Y * Y; s[4] += Y * Z; s[5] += Z * Z;
+  }
+  double out = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double v = s[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == k) out = v;
+  }
+  if (lane < 6) J6[lane] = out;
+}
+
 // Cyclic Jacobi on a symmetric 3x3 matrix (double); eigenvectors in V's columns.
 static __device__ inline void jacobi3(double A[3][3], double V[3][3]) {
   for (int a = 0; a < 3; ++a)

@@ -303,8 +303,32 @@ struct FeatArgs {
   float k;
   const double* s1;
   const double* s2;
+  const double* J6;  // [n][6] structure tensors at the centres (k_feat_tensor)
   float* X;  // [n][16]
 };
+
+// The voxel nearest primitive i's centre, clamped to the grid.
+__device__ inline void centre_voxel(const float* __restrict__ theta, int64_t n, int64_t i,
+                                    const gve_grid& g, int64_t c[3]) {
+  const double mu[3] = {theta[0 * n + i], theta[1 * n + i], theta[2 * n + i]};
+  const int64_t org[3] = {g.x0, g.y0, g.z0};
+  const int64_t dim[3] = {g.nx, g.ny, g.nz};
+  for (int ax = 0; ax < 3; ++ax) {
+    int64_t v = (int64_t)floor(mu[ax] - (double)org[ax] + 0.5);
+    c[ax] = v < 0 ? 0 : (v > dim[ax] - 1 ? dim[ax] - 1 : v);
+  }
+}
+
+// One wave per primitive: the structure tensor at its centre voxel.
+__global__ __launch_bounds__(256) void k_feat_tensor(const float* __restrict__ f,
+                                                     const float* __restrict__ theta, int64_t n,
+                                                     gve_grid g, double* __restrict__ J6) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;  // wave-uniform
+  int64_t c[3];
+  centre_voxel(theta, n, i, g, c);
+  wave_structure_tensor(f, Dims{g.nx, g.ny, g.nz}, c[0], c[1], c[2], J6 + 6 * i);
+}
 
 __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
   const int64_t i = (int64_t)blockIdx.x * 128 + threadIdx.x;
@@ -315,22 +339,10 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
   const int64_t org[3] = {a.g.x0, a.g.y0, a.g.z0};
   const int64_t dim[3] = {a.g.nx, a.g.ny, a.g.nz};
   int64_t c[3];
-  for (int ax = 0; ax < 3; ++ax) {
-    int64_t v = (int64_t)floor(mu[ax] - (double)org[ax] + 0.5);
-    c[ax] = v < 0 ? 0 : (v > dim[ax] - 1 ? dim[ax] - 1 : v);
-  }
-  // structure tensor at the seed voxel
-  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int64_t z = max((int64_t)0, c[2] - 3); z <= min(d.nz - 1, c[2] + 3); ++z)
-    for (int64_t y = max((int64_t)0, c[1] - 3); y <= min(d.ny - 1, c[1] + 3); ++y)
-      for (int64_t x = max((int64_t)0, c[0] - 3); x <= min(d.nx - 1, c[0] + 3); ++x) {
-        float gx, gy, gz;
-        grad_parts(a.f, d, x, y, z, &gx, &gy, &gz);
-        const double X = gx, Y = gy, Z = gz;
-        J[0][0] += X * X; J[0][1] += X * Y; J[0][2] += X * Z;
-        J[1][1] += Y * Y; J[1][2] += Y * Z; J[2][2] += Z * Z;
-      }
-  J[1][0] = J[0][1]; J[2][0] = J[0][2]; J[2][1] = J[1][2];
+  centre_voxel(a.theta, n, i, a.g, c);
+  // structure tensor at the seed voxel, from k_feat_tensor
+  const double* t = a.J6 + 6 * i;
+  double J[3][3] = {{t[0], t[1], t[2]}, {t[1], t[3], t[4]}, {t[2], t[4], t[5]}};
   double lam[3] = {0, 0, 0};
   double E[3][3] = {{0, 0, 1}, {0, 1, 0}, {1, 0, 0}};  // rows: e1, e2, e3
   if (J[0][0] + J[1][1] + J[2][2] >= 1e-12) {
@@ -553,8 +565,12 @@ hipError_t mlp_sat(const float* f, const gve_grid& g, double* s1, double* s2, hi
 
 hipError_t mlp_features(const float* f, const float* theta, int64_t n, int64_t n_detail,
                         const gve_grid& g, double g99, float k, const double* s1, const double* s2,
-                        float* X, hipStream_t s) {
-  FeatArgs a{f, theta, n, n_detail, g, g99, k, s1, s2, X};
+                        double* J6, float* X, hipStream_t s) {
+  FeatArgs a{f, theta, n, n_detail, g, g99, k, s1, s2, J6, X};
+  hipLaunchKernelGGL(k_feat_tensor, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, f, theta, n, g,
+                     J6);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, a);
   return hipGetLastError();
 }
