@@ -3,10 +3,15 @@ from the device allocation, k = 3, the benchmark's launch configuration
 (default options: 8x8x32 bricks, XCD chunk schedule, atomic sums).
 
 The oracle cannot evaluate a billion voxels, so it checks samples it can
-compute one by one: the field at 200 random voxels (from every primitive whose
-support box holds the voxel), and the loss gradient of 24 random primitives
-(on a sub-grid covering each one's support box, with every primitive whose
-box meets that sub-grid, which is exactly the data its gradient depends on).
+compute one by one: the field at sampled voxels (from every primitive whose
+support box holds the voxel), and the loss gradient of sampled primitives (on
+a sub-grid covering each one's support box, with every primitive whose box
+meets that sub-grid, which is exactly the data its gradient depends on).
+
+Besides uniform samples, both tests take the cases a brick kernel is most
+likely to get wrong: voxels on the grid's corners and faces and on brick
+edges (x, y at 0 or 7 modulo 8, z at 0 or 31 modulo 32), primitives whose
+support box the grid clips, and the largest and smallest support boxes.
 """
 import math
 
@@ -52,12 +57,48 @@ def _meets(lo, hi, a, b):
     return np.nonzero(np.all(lo <= b, axis=1) & np.all(hi >= a, axis=1))[0]
 
 
+def _sample_voxels(rng):
+    """Uniform voxels, the eight corners, voxels on each face and voxels on
+    brick edges (8 x 8 x 32 bricks)."""
+    e = N_SIDE - 1
+    uniform = rng.integers(0, N_SIDE, size=(400, 3))
+    corners = np.array([[x, y, z] for x in (0, e) for y in (0, e) for z in (0, e)])
+    faces = rng.integers(0, N_SIDE, size=(60, 3))
+    faces[np.arange(60), np.arange(60) % 3] = np.where(np.arange(60) % 2 == 0, 0, e)
+    edges = 8 * rng.integers(0, N_SIDE // 8, size=(60, 3))
+    edges[:, 0] += rng.choice([0, 7], size=60)
+    edges[:, 1] += rng.choice([0, 7], size=60)
+    edges[:, 2] = 32 * rng.integers(0, N_SIDE // 32, size=60) + rng.choice([0, 31], size=60)
+    return np.concatenate([uniform, corners, faces, edges])
+
+
+def _sample_primitives(rng, lo, hi):
+    """Uniform primitives, primitives whose support box the grid clips, and
+    the largest and smallest clipped boxes (largest among those of at most
+    250,000 voxels, which the oracle visits in seconds)."""
+    a = np.maximum(lo, 0)
+    b = np.minimum(hi, N_SIDE - 1)
+    vol = np.prod(np.maximum(b - a + 1, 0), axis=1)
+    clipped = np.nonzero((np.any(lo < 0, axis=1) | np.any(hi > N_SIDE - 1, axis=1))
+                         & (vol > 0))[0]
+    picks = list(rng.choice(BUDGET, size=24, replace=False))
+    if clipped.size:
+        picks += list(rng.choice(clipped, size=min(6, clipped.size), replace=False))
+    key = np.where(vol <= 250_000, vol, -1)
+    order = np.argsort(key, kind="stable")
+    picks += list(order[-3:]) + list(order[np.searchsorted(key[order], 1):][:3])
+    print(f"[fullsize] {clipped.size} clipped boxes; picked boxes of {vol[order[-1]]} "
+          f"and {vol[order[np.searchsorted(key[order], 1)]]} voxels", flush=True)
+    return np.unique(np.array(picks, dtype=np.int64))
+
+
 def test_field_at_sampled_voxels(workload):
     g, torch, ctx, field, grid, P, theta = workload
     out = g.evaluate(ctx, P, grid)
     lo, hi = _boxes(theta, 3.0)
     rng = np.random.default_rng(11)
-    vox = rng.integers(0, N_SIDE, size=(200, 3))
+    vox = _sample_voxels(rng)
+    print(f"[fullsize] field at {len(vox)} voxels", flush=True)
     flat = out.reshape(-1)
     for x, y, z in vox:
         cand = _meets(lo, hi, np.array([x, y, z]), np.array([x, y, z]))
@@ -75,7 +116,7 @@ def test_gradient_of_sampled_primitives(workload):
     grad = grad.cpu().numpy().astype(np.float64)
     lo, hi = _boxes(theta, 3.0)
     rng = np.random.default_rng(12)
-    picks = rng.choice(BUDGET, size=24, replace=False)
+    picks = _sample_primitives(rng, lo, hi)
     fld = field  # torch, on the device
     for i in picks:
         a = np.maximum(lo[i], 0)
