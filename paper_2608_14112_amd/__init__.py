@@ -32,6 +32,13 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python paper_2608_14112_amd/build.py` "
         "(there is no fallback implementation)")
 
+# torch first: its libraries load the HIP runtime it ships (soname
+# libamdhip64.so.7), which libgve.so's dependency then resolves to.  Loaded the
+# other way round, the system runtime comes first and torch still loads its own
+# copy by path, leaving two HIP runtimes in the process (context creation then
+# fails).
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 NPARAM = 11

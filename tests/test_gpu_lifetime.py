@@ -46,3 +46,33 @@ def test_destroy_frees_the_workspace():
     assert ws > 4 * n_side ** 3       # the dense residual alone is M floats
     # a leak of the workspace would lose 5 x ws
     assert free0 - free1 < ws
+
+
+def test_package_imported_before_torch_shares_its_hip_runtime():
+    """A program that imports the package before torch gets one HIP runtime
+    (torch's), and a context works on torch's tensors: run in a fresh process,
+    since this one has imported torch already."""
+    import os
+    import subprocess
+    import sys
+
+    code = """
+import paper_2608_14112_amd as g
+import numpy as np
+import torch
+from synth import fields as S
+hip = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}
+assert len(hip) == 1, hip
+ctx = g.Context()
+grid = g.Grid(32, 32, 32)
+P = g.Params(ctx, 200).upload(S.random_params(200, 32, seed=5).astype(np.float32))
+out = g.evaluate(ctx, P, grid)
+torch.cuda.synchronize()
+assert torch.isfinite(out).all() and float(out.abs().sum()) > 0
+print('one runtime:', hip.pop(), flush=True)
+"""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=300)
+    print(r.stdout, r.stderr[-2000:], flush=True)
+    assert r.returncode == 0
