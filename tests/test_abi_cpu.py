@@ -128,3 +128,17 @@ def test_binding_structs_match_the_header(tmp_path):
         assert int(out[f"{cname} size"]) == ctypes.sizeof(cls), cname
         for field, _ in cls._fields_:
             assert int(out[f"{cname}.{field}"]) == getattr(cls, field).offset, (cname, field)
+
+
+def test_binding_maps_one_hip_runtime():
+    """Importing the binding (in a fresh process, before anything else) leaves
+    one HIP runtime mapped, torch's: the library's dependency resolves to it."""
+    import subprocess
+    import sys
+
+    code = ("import paper_2608_14112_amd\n"
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "1"
