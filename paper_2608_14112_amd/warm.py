@@ -60,14 +60,35 @@ def plain_run(ctx: Context, field, grid: Grid, budget: int, seed: int, iters: in
             "info": info}
 
 
+def next_call_size(losses, target_loss: float, rate, most: int):
+    """Iterations for the next refinement call, and the updated rate.
+
+    `losses` are the previous call's losses (before each of its updates) and
+    `rate` the last known decrease of log(loss) per iteration.  The remaining
+    iterations are predicted from the most recent rate (the loss's decrease
+    slows as refinement converges, so the prediction falls short rather than
+    overshoots) and rounded down; at least one."""
+    if len(losses) >= 2 and losses[0] > losses[-1] > 0:
+        rate = (math.log(losses[0]) - math.log(losses[-1])) / (len(losses) - 1)
+    if not rate or not losses[-1] > 0 or not target_loss > 0:
+        return most, rate
+    # updates still needed from the state of losses[-1]; the call's last
+    # update is already done, and a call of n records the state after n - 1
+    left = (math.log(losses[-1]) - math.log(target_loss)) / rate
+    return int(max(1, min(most, math.floor(left)))), rate
+
+
 def warm_run(ctx: Context, mlp: MLP, field, grid: Grid, budget: int, seed: int, target_loss: float,
-             max_iters: int, chunk: int = 16):
+             max_iters: int, chunk: int = 0, first: int = 64):
     """Warm-started refinement until the loss reaches target_loss (or max_iters).
 
-    Refines in calls of `chunk` iterations; each call returns the loss before
-    each of its updates, so the first loss at or below the target gives the
-    iteration count (the rest of that call's iterations are extra work that
-    the wall time includes)."""
+    Refines in calls that each return the loss before each of their updates,
+    so the first loss at or below the target gives the iteration count; the
+    rest of that call's iterations are extra work that the wall time
+    includes.  chunk > 0: calls of `chunk` iterations.  chunk = 0: the first
+    call runs `first` iterations and each later one as many as the loss's
+    recent rate of decrease predicts are still needed (`next_call_size`), so
+    that few calls are made and the last one ends near the target."""
     import torch
 
     M = grid.nx * grid.ny * grid.nz
@@ -80,8 +101,9 @@ def warm_run(ctx: Context, mlp: MLP, field, grid: Grid, budget: int, seed: int, 
     cur = L[applied] if applied else L[0]
     start_loss = cur
     if cur > target_loss:
+        size, rate = (chunk if chunk > 0 else first), None
         while it < max_iters:
-            step = min(chunk, max_iters - it)
+            step = min(size, max_iters - it)
             losses = refine(ctx, P, field, grid, step)
             # losses[j] is the loss before update j: stop at the first that meets the target
             hit = np.nonzero(losses <= target_loss)[0]
@@ -90,6 +112,8 @@ def warm_run(ctx: Context, mlp: MLP, field, grid: Grid, budget: int, seed: int, 
                 cur = float(losses[hit[0]])
                 break
             it += step
+            if chunk <= 0:
+                size, rate = next_call_size(losses, target_loss, rate, first)
         else:
             cur = loss_grad(ctx, P, field, grid)
     torch.cuda.synchronize()
