@@ -70,7 +70,7 @@ def next_call_size(losses, target_loss: float, rate, most: int):
     overshoots) and rounded down; at least one."""
     if len(losses) >= 2 and losses[0] > losses[-1] > 0:
         rate = (math.log(losses[0]) - math.log(losses[-1])) / (len(losses) - 1)
-    if not rate or not losses[-1] > 0 or not target_loss > 0:
+    if not rate or not 0 < losses[-1] < math.inf or not target_loss > 0:
         return most, rate
     # updates still needed from the state of losses[-1]; the call's last
     # update is already done, and a call of n records the state after n - 1

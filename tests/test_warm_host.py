@@ -31,3 +31,11 @@ def test_next_call_size_keeps_the_last_rate_and_falls_back():
     # no decrease seen and no earlier rate: the largest call
     assert next_call_size(np.array([2.0, 2.0, 2.0]), 1.0, None, 32) == (32, None)
     assert next_call_size(np.array([1.0, 2.0]), 0.5, None, 16) == (16, None)
+
+
+def test_next_call_size_with_non_finite_losses():
+    from paper_2608_14112_amd.warm import next_call_size
+
+    assert next_call_size(np.array([2.0, np.inf]), 1.0, 0.01, 16) == (16, 0.01)
+    assert next_call_size(np.array([2.0, np.nan]), 1.0, 0.01, 16) == (16, 0.01)
+    assert next_call_size(np.array([np.nan, 1.5]), 1.0, None, 16) == (16, None)
